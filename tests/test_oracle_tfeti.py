@@ -1,0 +1,166 @@
+"""Pins of the oracle's TFETI solver (Section 4.2, Algorithm 3) against the
+saddle-point system it must solve (dense brute force), the monolithic
+Dirichlet-eliminated system, and the algebraic identities of the method:
+orthonormal kernel basis, generalized inverse, projector, symmetry and
+definiteness of F on Ker G, feasibility and equilibrium of the result, and
+invariance to the choice of generalized inverse."""
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from oracle import assembly
+from oracle.mesh import Mesh
+from oracle.tfeti import TFETI, regularize
+import workloads as W
+
+
+def elastic_problem(w):
+    mesh = Mesh(w)
+    ed = assembly.element_dofs_torn(mesh)
+    ne = mesh.n_elems
+    a = assembly.assemble(mesh, ed, mesh.n_torn, np.zeros(mesh.n_torn),
+                          np.zeros((ne, 8, 6)), np.zeros((ne, 8)))
+    tf = TFETI(mesh)
+    tf.set_matrix(a["K"])
+    return mesh, tf, a["K"], mesh.torn_load(1.0)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return elastic_problem(W.small_cube(S=(2, 2, 2), n=(2, 3, 2), amp=400.0, shear=100.0))
+
+
+def test_rigid_modes_orthonormal_and_in_kernel(small):
+    mesh, tf, K, f = small
+    for s, R in zip(mesh.subs, tf.R):
+        assert np.allclose(R.T @ R, np.eye(6), atol=1e-14)
+        Kp = K[s.off:s.off + s.n_dofs, s.off:s.off + s.n_dofs]
+        assert np.abs(Kp @ R).max() <= 1e-10 * abs(Kp).max()
+
+
+def test_generalized_inverse_identity(small):
+    mesh, tf, K, f = small
+    s = mesh.subs[3]
+    Kp = K[s.off:s.off + s.n_dofs, s.off:s.off + s.n_dofs].toarray()
+    Kr = tf.Kreg[3].toarray()
+    X = np.linalg.solve(Kr, Kp)
+    assert np.abs(Kp @ X - Kp).max() <= 1e-9 * np.abs(Kp).max()
+    # regularization adds only inside the existing band
+    diff = (tf.Kreg[3] - sp.csr_matrix(Kp)).tocoo()
+    bw = max(abs(i - j) for i, j in zip(*sp.csr_matrix(Kp).nonzero()))
+    assert np.abs(diff.row - diff.col).max() <= bw
+
+
+def test_projector_properties(small):
+    mesh, tf, K, f = small
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(mesh.m)
+    y = rng.standard_normal(mesh.m)
+    Px = tf.project(x)
+    assert np.allclose(tf.project(Px), Px, atol=1e-12)
+    assert abs(Px @ y - x @ tf.project(y)) < 1e-10
+    assert np.abs(tf.G @ Px).max() < 1e-12
+
+
+def test_F_symmetric_positive_on_kerG(small):
+    mesh, tf, K, f = small
+    rng = np.random.default_rng(2)
+    xs = [tf.project(rng.standard_normal(mesh.m)) for _ in range(4)]
+    Fx = [tf.F(x) for x in xs]
+    for i in range(4):
+        assert xs[i] @ Fx[i] > 0
+        for j in range(4):
+            a, b = xs[i] @ Fx[j], xs[j] @ Fx[i]
+            assert abs(a - b) <= 1e-10 * abs(a)
+
+
+def test_tfeti_equals_dense_kkt(small):
+    """The pair (u, lambda) must solve the saddle-point system of Section 4.2."""
+    mesh, tf, K, f = small
+    res = tf.solve(f, eps=1e-13)
+    n, m = mesh.n_torn, mesh.m
+    A = np.zeros((n + m, n + m))
+    A[:n, :n] = K.toarray()
+    A[:n, n:] = mesh.B.T.toarray()
+    A[n:, :n] = mesh.B.toarray()
+    rhs = np.concatenate([f, np.zeros(m)])
+    x = np.linalg.solve(A, rhs)
+    u, lam = x[:n], x[n:]
+    assert np.linalg.norm(res["u"] - u) <= 1e-9 * np.linalg.norm(u)
+    assert np.linalg.norm(res["lam"] - lam) <= 1e-8 * np.linalg.norm(lam)
+
+
+def test_tfeti_invariants(small):
+    mesh, tf, K, f = small
+    res = tf.solve(f, eps=1e-12)
+    u, lam = res["u"], res["lam"]
+    assert np.linalg.norm(mesh.B @ u) <= 1e-10 * np.linalg.norm(u)
+    g = tf.Rmat.T @ (f - mesh.B.T @ lam)
+    assert np.abs(g).max() <= 1e-11 * np.abs(f).max()
+    resid = K @ u - (f - mesh.B.T @ lam)
+    assert np.linalg.norm(resid) <= 1e-8 * np.linalg.norm(f)
+    assert res["converged"] and res["iters"] > 3
+
+
+def test_tfeti_equals_monolithic():
+    w = W.config(0)
+    mesh, tf, K, f = elastic_problem(w)
+    res = tf.solve(f, eps=1e-12)
+    # monolithic: assemble the global stiffness, drop Dirichlet rows/columns
+    eg = assembly.element_dofs_global(mesh)
+    ne = mesh.n_elems
+    ng = 3 * mesh.n_gnodes
+    a = assembly.assemble(mesh, eg, ng, np.zeros(ng), np.zeros((ne, 8, 6)), np.zeros((ne, 8)))
+    fg = np.zeros(ng)
+    for s in mesh.subs:
+        np.add.at(fg.reshape(-1, 3), s.l2g, f[s.off:s.off + s.n_dofs].reshape(-1, 3))
+    free = ~mesh.dir_mask.ravel()
+    Kf = a["K"][free][:, free].toarray()
+    ug = np.zeros(ng)
+    ug[free] = sla.solve(Kf, fg[free], assume_a="pos")
+    ut = res["u"][mesh.untorn_index()]
+    assert np.linalg.norm(ut - ug) <= 1e-9 * np.linalg.norm(ug)
+
+
+def test_generalized_inverse_choice_invariance(small):
+    """Fixing-node K_reg^{-1}, (K + rho R R^T)^{-1} and the Moore-Penrose
+    pseudoinverse give the same lambda, u and PCGP iteration count."""
+    mesh, tf, K, f = small
+    ref = tf.solve(f, eps=1e-10)
+
+    class Alt(TFETI):
+        def __init__(self, base, mode):
+            self.__dict__.update(base.__dict__)
+            self.mode = mode
+            self.inv = []
+            for s, R in zip(mesh.subs, base.R):
+                Kp = K[s.off:s.off + s.n_dofs, s.off:s.off + s.n_dofs].toarray()
+                if mode == "pinv":
+                    self.inv.append(np.linalg.pinv(Kp, rcond=1e-12))
+                else:
+                    rho = Kp.diagonal().max()
+                    self.inv.append(np.linalg.inv(Kp + rho * R @ R.T))
+
+        def kplus(self, x):
+            y = np.empty_like(x)
+            for s, Ai in zip(mesh.subs, self.inv):
+                y[s.off:s.off + s.n_dofs] = Ai @ x[s.off:s.off + s.n_dofs]
+            return y
+
+    for mode in ("pinv", "rrT"):
+        alt = Alt(tf, mode).solve(f, eps=1e-10)
+        assert abs(alt["iters"] - ref["iters"]) <= 1
+        assert np.linalg.norm(alt["lam"] - ref["lam"]) <= 1e-8 * np.linalg.norm(ref["lam"])
+        assert np.linalg.norm(alt["u"] - ref["u"]) <= 1e-8 * np.linalg.norm(ref["u"])
+
+
+def test_warm_start_reaches_same_solution(small):
+    mesh, tf, K, f = small
+    ref = tf.solve(f, eps=1e-10)
+    rng = np.random.default_rng(3)
+    guess = ref["lam"] + 1e-3 * np.linalg.norm(ref["lam"]) / np.sqrt(mesh.m) * rng.standard_normal(mesh.m)
+    ws = tf.solve(f, eps=1e-10, lam_guess=guess)
+    assert ws["iters"] < ref["iters"]
+    assert np.linalg.norm(ws["u"] - ref["u"]) <= 1e-8 * np.linalg.norm(ref["u"])
