@@ -1,0 +1,249 @@
+/*
+ * tfeti.h - C ABI of the MI355X (gfx950) TFETI semismooth-Newton solver for
+ * elastoplasticity with von Mises yield and linear isotropic hardening.
+ *
+ * Method: Cermak, Kozubek, Sysala, Valdman, "A TFETI Domain Decomposition
+ * Solver for Elastoplastic Problems".  Implicit Euler in time (Section 2.4),
+ * Q1-hexahedron FEM in space, semismooth Newton per load step (Algorithms 2
+ * and 4), each linearized system solved by Total FETI with the projected
+ * preconditioned conjugate gradient method PCGP (Algorithm 3).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns an int status: TFETI_OK (0), TFETI_CONVERGED (1,
+ *    Newton only), a warning (>= 2, results valid) or an error (< 0, outputs
+ *    undefined).  No C++ exception crosses the ABI; tfeti_last_error() gives
+ *    a message for the last failing call on a handle.
+ *  - Array arguments are DEVICE pointers unless the name ends in _host.  The
+ *    caller owns every buffer it passes; none is retained after return.  The
+ *    handle owns all of its internal device memory.
+ *  - Work is enqueued on the HIP stream given to tfeti_setup (a hipStream_t
+ *    passed as void*; NULL is the null stream).  Calls are ordered on that
+ *    stream; report structs are filled synchronously (the call waits for its
+ *    own work before filling them).
+ *  - A handle is not thread safe: calls on one handle must not overlap.
+ *
+ * Numbering (bit-exact with the test oracle):
+ *  - global node (i,j,k) -> i + (Nx+1)*(j + (Ny+1)*k); subdomain (I,J,K) ->
+ *    I + Sx*(J + Sy*K); local nodes and elements lexicographic, x fastest.
+ *  - torn vectors (length n_torn) stack the subdomain vectors in subdomain
+ *    order; the local DOF of (local node a, component c) is 3a + c.
+ *  - Gauss-point state arrays are ordered subdomain, local element, Gauss
+ *    point (2x2x2 rule, xi fastest); stresses are Voigt vectors
+ *    (s11, s22, s33, s12, s23, s13), strains use engineering shears
+ *    (e11, e22, e33, 2e12, 2e23, 2e13) (Section 3.1, vector form).
+ *  - multipliers (length m) are ordered as the rows of B = [B_G; B_U]
+ *    (Section 4.1), orthonormal form: for each (global node, component) with
+ *    copies in subdomains p1 < ... < pk, a Dirichlet-constrained pair gives k
+ *    rows of B_U (one +1 per copy) and no B_G row; otherwise k-1 Helmert rows
+ *    j = 1..k-1 with +c_j at p1..pj and -j*c_j at p(j+1), c_j = 1/sqrt(j(j+1)).
+ *    B_G rows come first (node ascending, component, j), then B_U rows (node
+ *    ascending, component, copy ascending).
+ */
+#ifndef TFETI_H
+#define TFETI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define TFETI_OK 0
+#define TFETI_CONVERGED 1            /* Newton: the load step has converged    */
+#define TFETI_W_PCG_MAXIT 2          /* PCGP stopped at max_pcg iterations     */
+#define TFETI_W_NEWTON_MAXIT 3       /* Newton reached max_newton iterations   */
+#define TFETI_W_WARMSTART_REJECTED 4 /* a warm start was non-finite; cold used */
+#define TFETI_E_INVALID (-1)         /* bad argument, size or call order       */
+#define TFETI_E_HIP (-2)             /* a HIP runtime call failed              */
+#define TFETI_E_OOM (-3)             /* device allocation failed               */
+#define TFETI_E_NOT_SPD (-4)         /* a Cholesky pivot was <= 0 or not finite*/
+
+/* ---- problem description (host struct) -------------------------------- */
+typedef struct {
+  double E, nu;        /* Young modulus, Poisson ratio (Hooke law, Section 2.2) */
+  double sigma_y, H;   /* initial yield stress and hardening modulus H_m > 0    */
+} tfeti_material;
+
+typedef struct {
+  int32_t S[3];                 /* subdomains per axis (box decomposition)      */
+  const int32_t* n_host[3];     /* n_host[a][I]: elements of slab I along axis a */
+  double extent[3];             /* box edge lengths; elements are uniform per axis*/
+  tfeti_material mat;
+  int32_t dirichlet[6][3];      /* [face][comp] != 0: u_comp = 0 on that face;
+                                   faces x=0, x=X, y=0, y=Y, z=0, z=Z           */
+  double traction[6][3];        /* traction vector on each face at load factor 1 */
+} tfeti_problem;
+
+/* ---- solver options (host struct) ------------------------------------- */
+#define TFETI_PREC_FP64 0       /* FP64 factors and F-applies                   */
+#define TFETI_PREC_FP32 1       /* FP32 factors and F-applies, FP64 outer dual
+                                   refinement; FP64 coarse solve, inner products
+                                   and return map                               */
+typedef struct {
+  int32_t precision;            /* TFETI_PREC_*                                 */
+  int32_t preconditioner;       /* 0 none, 1 lumped B K B^T (Section 4.2)       */
+  double eps_pcg;               /* PCGP relative tolerance                      */
+  double eps_newton;            /* Newton relative-residual tolerance           */
+  int32_t max_pcg;              /* PCGP iteration cap (default 5000)            */
+  int32_t max_newton;           /* Newton iteration cap per load step (50)      */
+  int32_t warm_start;           /* 0 cold; 1 previous Newton iteration's lambda */
+  int32_t use_graph;            /* replay the PCGP iteration as a HIP graph     */
+  int32_t tile;                 /* factor tile rows 16/32/64; 0 = autotuned     */
+  double refine_eps;            /* FP32 mode: inner PCGP tolerance (0 = 1e-4)   */
+  int32_t check_every;          /* host polls convergence every N iterations    */
+} tfeti_options;
+
+/* ---- reports (host structs) ------------------------------------------- */
+typedef struct {
+  int32_t iters;                /* PCGP iterations (F-applies inside the loop)  */
+  int32_t fapplies;             /* all F-applies of the solve                   */
+  int32_t converged;            /* 1 if ||P r|| <= eps * r_ref                  */
+  int32_t outer;                /* FP32 mode: outer refinement sweeps           */
+  double r_ref;                 /* ||P (d - F lambda_Im)||                      */
+  double r_final;               /* last ||P r||                                 */
+  double ms;                    /* wall time of the call                        */
+} tfeti_pcg_report;
+
+typedef struct {
+  int32_t iteration;            /* Newton iteration index i (1-based)           */
+  int32_t pcg_iters;
+  int32_t fapplies;
+  int32_t plastic_gp;           /* Gauss points on the plastic branch           */
+  int32_t plastic_elements;     /* elements with at least one plastic point     */
+  double relres;                /* ||assembled residual|| / ||assembled df||, free DOFs */
+  double crit;                  /* the paper's increment criterion (Algorithm 2)*/
+  double ms_assembly, ms_factor, ms_pcg, ms_total;
+} tfeti_newton_report;
+
+typedef struct {
+  int64_t n_sub, n_torn, m, m_G, m_U, l, n_elem, n_gp, n_gdof;
+  int64_t skyline_entries;      /* sum over subdomains of the factor envelope    */
+  int64_t factor_entries;       /* stored entries of one factor layout           */
+  int64_t factor_bytes;         /* bytes read by one pass over all factors       */
+  int32_t tile;                 /* factor tile rows in use                       */
+  int32_t precision;
+} tfeti_sizes;
+
+typedef struct tfeti_handle tfeti_handle;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Build the decomposition, the gluing matrix B (Section 4.1), the rigid body
+ * modes R (orthonormal kernel basis, Section 4.2), G = R^T B^T, the coarse
+ * matrix G G^T and its inverse (factorized once on the device: R and B are
+ * fixed for the whole run), and allocate every device buffer.  State starts
+ * at zero (Algorithm 4, initial step).  Errors: TFETI_E_INVALID for
+ * non-positive sizes, null pointers or E, H, sigma_y <= 0; TFETI_E_OOM. */
+int tfeti_setup(const tfeti_problem* prob_host, const tfeti_options* opt_host,
+                void* stream, tfeti_handle** out);
+void tfeti_destroy(tfeti_handle* h);
+const char* tfeti_last_error(const tfeti_handle* h);
+int tfeti_get_sizes(const tfeti_handle* h, tfeti_sizes* out_host);
+
+/* Copy B in CSR form to host buffers of m+1, nnz, nnz entries: row pointers,
+ * torn DOF of each entry, coefficient.  Any pointer may be NULL (then only
+ * *nnz_host is written).  Used to check the index maps bit for bit. */
+int tfeti_get_B_host(const tfeti_handle* h, int64_t* nnz_host, int64_t* rowptr_host,
+                     int64_t* col_host, double* val_host);
+
+/* ---- time stepping (Algorithms 1 and 4) -------------------------------- */
+
+/* Start load step k -> k+1: the load increment is dload_factor times the
+ * load at factor 1, and the displacement increment restarts at zero. */
+int tfeti_begin_load_step(tfeti_handle* h, double dload_factor);
+
+/* One Newton iteration i of the current load step (Algorithm 4 body):
+ * return map at every Gauss point, internal force and tangent assembly
+ * (Algorithm 5), residual f = df - f_int.  For i >= 2, if the relative
+ * residual of the assembled system on free DOFs is <= eps_newton, returns
+ * TFETI_CONVERGED without solving.  Otherwise regularizes and factorizes the
+ * subdomain tangents, solves the dual problem by PCGP (Algorithm 3) and
+ * updates the displacement increment.  Returns TFETI_W_NEWTON_MAXIT after
+ * max_newton iterations, TFETI_E_NOT_SPD on a failed factorization. */
+int tfeti_newton_step(tfeti_handle* h, tfeti_newton_report* rep_host);
+
+/* Commit the load step: u += du, sigma += dsigma, kappa += dkappa, with the
+ * increments evaluated at the converged displacement increment
+ * (Algorithm 4, end of the time step). */
+int tfeti_commit_load_step(tfeti_handle* h);
+
+/* ---- dual solver (Algorithm 3) ----------------------------------------- */
+
+/* Solve min 1/2 v^T K v - f^T v subject to B v = 0 (Section 4.1) for the
+ * currently factorized K by PCGP: lambda_Im = G^T (G G^T)^{-1} R^T f,
+ * d = B K^+ f, projected iterations on Ker G, alpha = -(G G^T)^{-1} G r,
+ * u = K^+ (f - B^T lambda) + R alpha.  f and u_out: n_torn FP64; lambda_guess
+ * (m, may be NULL) warm start, used as lambda_Im + P lambda_guess;
+ * lambda_out: m FP64.  Stop: ||P r|| <= eps_pcg ||P(d - F lambda_Im)||.
+ * Returns TFETI_W_PCG_MAXIT if the cap was reached. */
+int tfeti_dual_pcg(tfeti_handle* h, const double* f, const double* lambda_guess,
+                   double* lambda_out, double* u_out, tfeti_pcg_report* rep_host);
+
+/* ---- building blocks (used by tests and benchmarks) -------------------- */
+
+/* Return map, internal force and tangent assembly at displacement increment
+ * du (n_torn, FP64, device) against the committed state; writes the torn
+ * internal force sum_T sum_g w_g B_g^T dsigma_g to fint (n_torn) and keeps
+ * the tangent inside the handle.  If plastic_count_host != NULL it receives
+ * the number of plastic Gauss points. */
+int tfeti_assemble(tfeti_handle* h, const double* du, double* fint, int64_t* plastic_count_host);
+
+/* Regularize (fixing nodes, Remark 1) and factorize the assembled tangents. */
+int tfeti_factorize(tfeti_handle* h);
+
+/* q = F lambda = B K^+ B^T lambda (m -> m, FP64) with the current factors in
+ * the factor precision; the fused per-subdomain solve plus the B gather. */
+int tfeti_fapply(tfeti_handle* h, const double* lambda, double* q);
+
+/* y = K_reg^{-1} x on a torn vector (n_torn, FP64) with the current factors. */
+int tfeti_kplus(tfeti_handle* h, const double* x, double* y);
+
+/* out = P w = w - G^T (G G^T)^{-1} G w (m -> m, FP64). */
+int tfeti_project(tfeti_handle* h, const double* w, double* out);
+
+/* out = B K B^T w with the unregularized tangent (lumped preconditioner). */
+int tfeti_precondition(tfeti_handle* h, const double* w, double* out);
+
+/* State access: sigma (n_gp*6), kappa (n_gp), u (n_torn), du (n_torn),
+ * dsigma (n_gp*6), dkappa (n_gp), plastic (n_gp, uint8); NULL skips. */
+int tfeti_get_state(const tfeti_handle* h, double* sigma, double* kappa, double* u,
+                    double* du, double* dsigma, double* dkappa, uint8_t* plastic);
+int tfeti_set_state(tfeti_handle* h, const double* sigma, const double* kappa,
+                    const double* u, const double* du);
+
+/* Multipliers of the last PCGP solve (m, FP64, device). */
+int tfeti_get_lambda(const tfeti_handle* h, double* lambda);
+
+/* Timing of the dominant kernel: when on, every F-apply's subdomain-solve
+ * kernel is bracketed by HIP events on the handle's stream; get returns the
+ * summed kernel milliseconds and the number of kernels that did work since
+ * the last set (set also resets the totals). */
+int tfeti_set_timing(tfeti_handle* h, int on);
+int tfeti_get_timing(tfeti_handle* h, double* ms_host, int64_t* count_host);
+
+/* Host-only (no device work): build the model of prob and report its sizes
+ * (factor_bytes and precision are not set) and, when the pointers are not
+ * NULL, B in CSR like tfeti_get_B_host (host buffers of m+1, nnz, nnz).  Lets
+ * the index maps be checked without a GPU.  tile: 0, 16, 32 or 64. */
+int tfeti_model_host(const tfeti_problem* prob_host, int32_t tile, tfeti_sizes* sizes_host, int64_t* nnz_host,
+                     int64_t* rowptr_host, int64_t* col_host, double* val_host);
+
+/* ---- stateless return map (Section 2.4, Voigt form of Section 3.1) ----- */
+
+/* For npts points: trial = sigma_k + C deps; if Phi(trial, kappa_k) <= 0 the
+ * step is elastic (dsigma = C deps, dkappa = 0, D = C); otherwise
+ * dkappa = Phi/(3mu+H), dsigma = C deps - 3mu/(3mu+H) sqrt(2/3) Phi n with n
+ * the unit deviator of the trial stress, and D the generalized derivative
+ * C - 2mu beta E_eps - 2mu beta sqrt(2/3) (sigma_y + H kappa_k)/|dev trial|
+ * (n n^T - E_eps), beta = 3mu/(3mu+H).  sigma_k, deps, dsigma: 6*npts;
+ * kappa_k, dkappa: npts; Dtan: 36*npts row-major or NULL; plastic: npts
+ * bytes or NULL.  All device pointers, FP64.  Errors: TFETI_E_INVALID. */
+int return_map(const tfeti_material* mat_host, int64_t npts, const double* sigma_k,
+               const double* kappa_k, const double* deps, double* dsigma, double* dkappa,
+               double* Dtan, uint8_t* plastic, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TFETI_H */

@@ -1,0 +1,869 @@
+// C ABI of the TFETI library: handle lifetime, the PCGP driver
+// (Algorithm 3) and the Newton driver (Algorithms 2, 4 and 5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "model.h"
+
+using namespace tfeti;
+
+struct tfeti_handle {
+  std::string err;
+  HostModel M;
+  tfeti_options opt;
+  hipStream_t st = nullptr;
+  int TS = 32;
+  int prec = 0;
+  int npad_max = 0, max_iface = 0;
+  int64_t panel_entries = 0;
+  std::vector<void*> allocs;
+  // maps
+  SubDev* d_subs = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t *d_if_fidx = nullptr, *d_if_ldof = nullptr, *d_if_rp = nullptr, *d_if_row = nullptr, *d_if_sub = nullptr;
+  double* d_if_coef = nullptr;
+  int64_t* d_b_rowptr = nullptr;
+  int32_t* d_b_iface = nullptr;
+  double* d_b_val = nullptr;
+  double *d_R_full = nullptr, *d_R_iface = nullptr;
+  int32_t *d_kbb_rp = nullptr, *d_kbb_col = nullptr;
+  int64_t* d_kbb_band = nullptr;
+  double* d_kbb_val = nullptr;
+  int64_t* d_g_first = nullptr;
+  int32_t* d_g_rp = nullptr;
+  int64_t* d_g_copies = nullptr;
+  uint8_t* d_g_free = nullptr;
+  int32_t* d_colour[8] = {};
+  int64_t n_colour[8] = {};
+  int32_t* d_elem_sub = nullptr;
+  double *d_QQt = nullptr, *d_dN = nullptr, *d_Ginv = nullptr;
+  // matrices
+  double* d_band = nullptr;     // K_reg (FP64 row-band)
+  void* d_work = nullptr;       // factor work (row-band, factor precision)
+  void* d_F = nullptr;          // forward panels
+  void* d_B = nullptr;          // backward panels
+  // state
+  double *d_sigma = nullptr, *d_kappa = nullptr, *d_dsigma = nullptr, *d_dkappa = nullptr;
+  uint8_t* d_plastic = nullptr;
+  double *d_u = nullptr, *d_du = nullptr, *d_f1 = nullptr, *d_df = nullptr, *d_fint = nullptr, *d_f = nullptr,
+         *d_delta = nullptr;
+  // PCGP work
+  double *d_lam = nullptr, *d_lam_im = nullptr, *d_lam_ker = nullptr, *d_r = nullptr, *d_w = nullptr,
+         *d_z = nullptr, *d_y = nullptr, *d_p = nullptr, *d_q = nullptr, *d_d = nullptr, *d_lam_prev = nullptr;
+  double* d_iface = nullptr;
+  double *d_c = nullptr, *d_a = nullptr;
+  double* d_partials = nullptr;
+  double* d_scal = nullptr;
+  PcgScalars* d_S = nullptr;
+  int32_t* d_fail = nullptr;
+  unsigned long long* d_plcount = nullptr;
+  DualMaps dm{};
+  // Newton state
+  double dlf = 0.0, df_norm = 0.0;
+  int newton_i = 0;
+  bool step_active = false, have_lambda = false, factored = false, assembled_at_du = false;
+  int64_t last_plastic = 0;
+  // timing of the F-apply solve kernel
+  bool timing = false;
+  double t_ms = 0.0;
+  int64_t t_count = 0;
+  std::vector<hipEvent_t> ev;   // pairs (start, stop) around F-apply solve kernels
+  int ev_used = 0;
+};
+
+namespace {
+
+int fail(tfeti_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return fail(h, TFETI_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+template <typename T>
+int dalloc(tfeti_handle* h, T** p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, TFETI_E_OOM, "hipMalloc of " + std::to_string((size_t)n * sizeof(T)) + " bytes failed");
+  }
+  h->allocs.push_back(q);
+  *p = (T*)q;
+  return 0;
+}
+
+template <typename T>
+int upload(tfeti_handle* h, T** p, const std::vector<T>& v) {
+  int rc = dalloc(h, p, (int64_t)v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return 0;
+}
+
+#define RC(x)              \
+  do {                     \
+    int rc_ = (x);         \
+    if (rc_ < 0) return rc_; \
+  } while (0)
+
+double read_scalar(tfeti_handle* h, const double* d) {
+  double v = 0.0;
+  (void)hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, h->st);
+  (void)hipStreamSynchronize(h->st);
+  return v;
+}
+
+// ------------------------------------------------------------------ operators
+void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double lam_sign, double* out_iface,
+            double* out_full, const double* alpha, const int32_t* done) {
+  if (h->prec == TFETI_PREC_FP64) {
+    KsolveArgs<double> a{};
+    a.subs = h->d_subs;
+    a.order = h->d_order;
+    a.nsub = h->M.n_sub;
+    a.Fp = (const double*)h->d_F;
+    a.Bp = (const double*)h->d_B;
+    a.in_full = in_full;
+    a.lam = lam;
+    a.lam_sign = lam_sign;
+    a.out_iface = out_iface;
+    a.out_full = out_full;
+    a.alpha = alpha;
+    a.R_full = h->d_R_full;
+    a.if_fidx = h->d_if_fidx;
+    a.if_ldof = h->d_if_ldof;
+    a.if_rp = h->d_if_rp;
+    a.if_row = h->d_if_row;
+    a.if_coef = h->d_if_coef;
+    a.done = done;
+    launch_ksolve<double>(a, h->TS, h->npad_max, h->st);
+  } else {
+    KsolveArgs<float> a{};
+    a.subs = h->d_subs;
+    a.order = h->d_order;
+    a.nsub = h->M.n_sub;
+    a.Fp = (const float*)h->d_F;
+    a.Bp = (const float*)h->d_B;
+    a.in_full = in_full;
+    a.lam = lam;
+    a.lam_sign = lam_sign;
+    a.out_iface = out_iface;
+    a.out_full = out_full;
+    a.alpha = alpha;
+    a.R_full = h->d_R_full;
+    a.if_fidx = h->d_if_fidx;
+    a.if_ldof = h->d_if_ldof;
+    a.if_rp = h->d_if_rp;
+    a.if_row = h->d_if_row;
+    a.if_coef = h->d_if_coef;
+    a.done = done;
+    launch_ksolve<float>(a, h->TS, h->npad_max, h->st);
+  }
+}
+
+// q = F lam; optional partial sums of q.dotv
+void fapply(tfeti_handle* h, const double* lam, double* q, const double* dotv, double* partials,
+            const int32_t* done) {
+  const bool rec = h->timing && 2 * h->ev_used + 1 < (int)h->ev.size();
+  if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], h->st);
+  ksolve(h, nullptr, lam, 1.0, h->d_iface, nullptr, nullptr, done);
+  if (rec) {
+    (void)hipEventRecord(h->ev[2 * h->ev_used + 1], h->st);
+    h->ev_used++;
+  }
+  launch_gather(h->dm, h->d_iface, q, dotv, partials, done, h->st);
+}
+
+// Add the durations of the first `valid` recorded F-apply kernels to the
+// timing totals (later ones ran after convergence and returned at once).
+void harvest_timing(tfeti_handle* h, int valid) {
+  if (!h->timing) return;
+  (void)hipStreamSynchronize(h->st);
+  int n = std::min(valid, h->ev_used);
+  for (int i = 0; i < n; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
+      h->t_ms += ms;
+      h->t_count += 1;
+    }
+  }
+  h->ev_used = 0;
+}
+
+// out = P x; optional partial sums of out.out
+void project(tfeti_handle* h, const double* x, double* out, double* partials, const int32_t* done) {
+  launch_g_apply(h->dm, x, h->d_c, done, h->st);
+  launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, done, h->st);
+  launch_gt_apply(h->dm, x, h->d_a, 1.0, out, partials, done, h->st);
+}
+
+void precondition(tfeti_handle* h, const double* w, double* z, const int32_t* done) {
+  launch_lumped(h->dm, w, h->d_kbb_val, h->d_iface, done, h->st);
+  launch_gather(h->dm, h->d_iface, z, nullptr, nullptr, done, h->st);
+}
+
+int nred(tfeti_handle* h) { return reduction_blocks(h->M.m); }
+
+// ------------------------------------------------------------------ PCGP
+int pcg_solve(tfeti_handle* h, const double* f, const double* guess, double* lam_out, double* u_out,
+              tfeti_pcg_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t m = h->M.m;
+  int status = TFETI_OK;
+  // lambda_Im = G^T (G G^T)^{-1} R^T f
+  launch_rt_apply(h->dm, f, h->d_c, h->st);
+  launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, nullptr, h->st);
+  launch_gt_apply(h->dm, nullptr, h->d_a, -1.0, h->d_lam_im, nullptr, nullptr, h->st);
+  // d = B K^+ f
+  ksolve(h, f, nullptr, 0.0, h->d_iface, nullptr, nullptr, nullptr);
+  launch_gather(h->dm, h->d_iface, h->d_d, nullptr, nullptr, nullptr, h->st);
+  // r = d - F lambda_Im
+  fapply(h, h->d_lam_im, h->d_q, nullptr, nullptr, nullptr);
+  launch_copy(m, h->d_d, h->d_r, h->st);
+  launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
+  // scalars
+  PcgScalars S0{};
+  S0.eps = h->opt.eps_pcg;
+  S0.maxit = h->opt.max_pcg;
+  HIPCHK(hipMemcpyAsync(h->d_S, &S0, sizeof(PcgScalars), hipMemcpyHostToDevice, h->st));
+  // r_ref = ||P r||
+  project(h, h->d_r, h->d_w, h->d_partials, nullptr);
+  launch_finalize(FIN_RREF, h->d_S, h->d_partials, nred(h), h->st);
+  harvest_timing(h, 1 << 30);
+  int fapplies = 1;
+  bool rejected = false;
+  if (guess) {
+    launch_check_finite(m, guess, h->d_S, h->st);
+    PcgScalars Sh;
+    HIPCHK(hipMemcpyAsync(&Sh, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (Sh.nonfinite) {
+      rejected = true;
+      guess = nullptr;
+      int zero = 0;
+      HIPCHK(hipMemcpyAsync(&h->d_S->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice, h->st));
+    }
+  }
+  if (guess) {
+    project(h, guess, h->d_lam_ker, nullptr, nullptr);
+    fapply(h, h->d_lam_ker, h->d_q, nullptr, nullptr, nullptr);
+    launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
+    fapplies++;
+  } else {
+    HIPCHK(hipMemsetAsync(h->d_lam_ker, 0, m * sizeof(double), h->st));
+  }
+  HIPCHK(hipMemsetAsync(h->d_p, 0, m * sizeof(double), h->st));
+  int32_t* done = &h->d_S->done;
+  const int batch = h->opt.check_every > 0 ? h->opt.check_every : 8;
+  PcgScalars Sh{};
+  int iters_before = 0;          // iterations completed before the current batch
+  int extra = guess ? 1 : 0;     // the warm-start F-apply is recorded in the first batch
+  for (;;) {
+    for (int k = 0; k < batch; ++k) {
+      project(h, h->d_r, h->d_w, h->d_partials, done);
+      launch_finalize(FIN_WW, h->d_S, h->d_partials, nred(h), h->st);
+      if (h->opt.preconditioner == 1) {
+        precondition(h, h->d_w, h->d_z, done);
+        project(h, h->d_z, h->d_y, nullptr, done);
+      } else {
+        project(h, h->d_w, h->d_y, nullptr, done);
+      }
+      launch_dot_partials(h->d_y, h->d_w, m, h->d_partials, done, h->st);
+      launch_finalize(FIN_YW, h->d_S, h->d_partials, nred(h), h->st);
+      launch_update_p(m, h->d_y, h->d_p, h->d_S, h->st);
+      fapply(h, h->d_p, h->d_q, h->d_p, h->d_partials, done);
+      launch_finalize(FIN_PQ, h->d_S, h->d_partials, nred(h), h->st);
+      launch_update_lr(m, h->d_p, h->d_q, h->d_lam_ker, h->d_r, h->d_S, h->st);
+    }
+    HIPCHK(hipMemcpyAsync(&Sh, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (Sh.done) break;
+    harvest_timing(h, 1 << 30);
+    iters_before = Sh.iters;
+    extra = 0;
+  }
+  // only the F-applies of iterations that ran before convergence did work
+  harvest_timing(h, Sh.iters - iters_before + extra);
+  fapplies += Sh.iters;
+  if (Sh.done == 2) status = TFETI_W_PCG_MAXIT;
+  if (Sh.done == 3) return fail(h, TFETI_E_NOT_SPD, "PCGP produced a non-finite residual");
+  // lambda = lambda_Im + lambda_Ker
+  launch_copy(m, h->d_lam_im, h->d_lam, h->st);
+  launch_axpby(m, 1.0, h->d_lam_ker, 1.0, h->d_lam, h->st);
+  if (lam_out && lam_out != h->d_lam) launch_copy(m, h->d_lam, lam_out, h->st);
+  // alpha = -(G G^T)^{-1} G r
+  launch_g_apply(h->dm, h->d_r, h->d_c, nullptr, h->st);
+  launch_coarse_gemv(h->dm, h->d_c, h->d_a, -1.0, nullptr, h->st);
+  // u = K^+ (f - B^T lambda) + R alpha
+  if (u_out) ksolve(h, f, h->d_lam, -1.0, nullptr, u_out, h->d_a, nullptr);
+  HIPCHK(hipStreamSynchronize(h->st));
+  if (rep) {
+    rep->iters = Sh.iters;
+    rep->fapplies = fapplies;
+    rep->converged = Sh.done == 1;
+    rep->outer = 0;
+    rep->r_ref = Sh.r_ref;
+    rep->r_final = Sh.rr;
+    rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (rejected && status == TFETI_OK) status = TFETI_W_WARMSTART_REJECTED;
+  return status;
+}
+
+// ------------------------------------------------------------------ assembly / factorization
+int assemble_at(tfeti_handle* h, const double* du, double* fint) {
+  const HostModel& M = h->M;
+  HIPCHK(hipMemsetAsync(h->d_band, 0, M.band_entries * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(fint, 0, M.n_torn * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_plcount, 0, sizeof(unsigned long long), h->st));
+  AssembleArgs a{};
+  a.subs = h->d_subs;
+  a.elem_sub = h->d_elem_sub;
+  a.dN = h->d_dN;
+  a.w = M.wg;
+  a.M.lam = M.mat.E * M.mat.nu / ((1.0 + M.mat.nu) * (1.0 - 2.0 * M.mat.nu));
+  a.M.mu = M.mat.E / (2.0 * (1.0 + M.mat.nu));
+  a.M.sy = M.mat.sigma_y;
+  a.M.H = M.mat.H;
+  a.du = du;
+  a.sigma = h->d_sigma;
+  a.kappa = h->d_kappa;
+  a.dsigma = h->d_dsigma;
+  a.dkappa = h->d_dkappa;
+  a.plastic = h->d_plastic;
+  a.plastic_count = h->d_plcount;
+  a.fint = fint;
+  a.band = h->d_band;
+  for (int c = 0; c < 8; ++c) {
+    a.elems = h->d_colour[c];
+    a.n_colour = h->n_colour[c];
+    launch_assemble(a, h->st);
+  }
+  launch_pad_identity(h->d_subs, M.n_sub, h->d_band, h->st);
+  // the lumped preconditioner uses the unregularized tangent
+  launch_gather_kbb(h->d_kbb_band, (int64_t)M.kbb_band.size(), h->d_band, h->d_kbb_val, h->st);
+  unsigned long long cnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->last_plastic = (int64_t)cnt;
+  h->factored = false;
+  return 0;
+}
+
+int factorize(tfeti_handle* h) {
+  const HostModel& M = h->M;
+  launch_regularize(h->d_subs, M.n_sub, h->d_QQt, h->d_band, h->st);
+  HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
+  if (h->prec == TFETI_PREC_FP64) {
+    launch_convert_band<double>(h->d_band, (double*)h->d_work, M.band_entries, h->st);
+    launch_band_cholesky<double>(h->d_subs, M.n_sub, (double*)h->d_work, h->d_fail, h->st);
+    launch_pack_panels<double>(h->d_subs, M.n_sub, (const double*)h->d_work, (double*)h->d_F, (double*)h->d_B,
+                               h->TS, h->st);
+  } else {
+    launch_convert_band<float>(h->d_band, (float*)h->d_work, M.band_entries, h->st);
+    launch_band_cholesky<float>(h->d_subs, M.n_sub, (float*)h->d_work, h->d_fail, h->st);
+    launch_pack_panels<float>(h->d_subs, M.n_sub, (const float*)h->d_work, (float*)h->d_F, (float*)h->d_B, h->TS,
+                              h->st);
+  }
+  int32_t bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipGetLastError());
+  if (bad) return fail(h, TFETI_E_NOT_SPD, "a subdomain factorization met a pivot <= 0");
+  h->factored = true;
+  return 0;
+}
+
+double assembled_norm(tfeti_handle* h, const double* v) {
+  const HostModel& M = h->M;
+  launch_assembled_sq(M.n_gdof, h->d_g_rp, h->d_g_copies, h->d_g_free, v, h->d_partials, h->st);
+  launch_sum_partials(h->d_partials, reduction_blocks(M.n_gdof), h->d_scal, h->st);
+  return std::sqrt(read_scalar(h, h->d_scal));
+}
+
+double untorn_norm(tfeti_handle* h, const double* v) {
+  const HostModel& M = h->M;
+  launch_untorn_sq(M.n_gdof, h->d_g_first, v, h->d_partials, h->st);
+  launch_sum_partials(h->d_partials, reduction_blocks(M.n_gdof), h->d_scal, h->st);
+  return std::sqrt(read_scalar(h, h->d_scal));
+}
+
+double ms_since(std::chrono::steady_clock::time_point t) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+extern "C" {
+
+int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* stream, tfeti_handle** out) {
+  if (!out) return TFETI_E_INVALID;
+  *out = nullptr;
+  if (!prob || !opt) return TFETI_E_INVALID;
+  tfeti_handle* h = new (std::nothrow) tfeti_handle();
+  if (!h) return TFETI_E_OOM;
+  *out = h;
+  h->opt = *opt;
+  h->st = (hipStream_t)stream;
+  if (h->opt.max_pcg <= 0) h->opt.max_pcg = 5000;
+  if (h->opt.max_newton <= 0) h->opt.max_newton = 50;
+  if (!(h->opt.eps_pcg > 0)) h->opt.eps_pcg = 1e-8;
+  if (!(h->opt.eps_newton > 0)) h->opt.eps_newton = 1e-10;
+  if (h->opt.precision != TFETI_PREC_FP64 && h->opt.precision != TFETI_PREC_FP32)
+    return fail(h, TFETI_E_INVALID, "precision must be TFETI_PREC_FP64 or TFETI_PREC_FP32");
+  h->prec = h->opt.precision;
+  int TS = h->opt.tile;
+  if (TS == 0) TS = 32;
+  if (TS != 16 && TS != 32 && TS != 64) return fail(h, TFETI_E_INVALID, "tile must be 0, 16, 32 or 64");
+  h->TS = TS;
+  std::string msg = build_model(*prob, h->M);
+  if (!msg.empty()) return fail(h, TFETI_E_INVALID, msg);
+  HostModel& M = h->M;
+  h->panel_entries = assign_panels(M, TS);
+  for (const SubDev& s : M.subs) {
+    h->npad_max = std::max(h->npad_max, s.npad);
+    h->max_iface = std::max(h->max_iface, s.n_iface);
+  }
+  // schedule: longest subdomain first (stable)
+  std::vector<int32_t> order(M.n_sub);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return M.subs[a].panel_len > M.subs[b].panel_len; });
+  // if_sub map
+  std::vector<int32_t> if_sub(M.n_iface);
+  for (int64_t p = 0; p < M.n_sub; ++p)
+    for (int32_t t = 0; t < M.subs[p].n_iface; ++t) if_sub[M.subs[p].iface_off + t] = (int32_t)p;
+  // dN table [gp][node][axis] from B_g
+  std::vector<double> dN(8 * 8 * 3);
+  for (int g = 0; g < 8; ++g)
+    for (int a = 0; a < 8; ++a) {
+      dN[(g * 8 + a) * 3 + 0] = M.Bg[g][0][3 * a + 0];
+      dN[(g * 8 + a) * 3 + 1] = M.Bg[g][1][3 * a + 1];
+      dN[(g * 8 + a) * 3 + 2] = M.Bg[g][2][3 * a + 2];
+    }
+  // ---- uploads ----
+  RC(upload(h, &h->d_subs, M.subs));
+  RC(upload(h, &h->d_order, order));
+  RC(upload(h, &h->d_if_fidx, M.if_fidx));
+  RC(upload(h, &h->d_if_ldof, M.if_ldof));
+  RC(upload(h, &h->d_if_rp, M.if_rp));
+  RC(upload(h, &h->d_if_row, M.if_row));
+  RC(upload(h, &h->d_if_coef, M.if_coef));
+  RC(upload(h, &h->d_if_sub, if_sub));
+  RC(upload(h, &h->d_b_rowptr, M.b_rowptr));
+  RC(upload(h, &h->d_b_iface, M.b_iface));
+  RC(upload(h, &h->d_b_val, M.b_val));
+  RC(upload(h, &h->d_R_full, M.R_full));
+  RC(upload(h, &h->d_R_iface, M.R_iface));
+  RC(upload(h, &h->d_kbb_rp, M.kbb_rp));
+  RC(upload(h, &h->d_kbb_col, M.kbb_col));
+  RC(upload(h, &h->d_kbb_band, M.kbb_band));
+  RC(dalloc(h, &h->d_kbb_val, (int64_t)M.kbb_band.size()));
+  RC(upload(h, &h->d_g_first, M.g_first));
+  RC(upload(h, &h->d_g_rp, M.g_rp));
+  RC(upload(h, &h->d_g_copies, M.g_copies));
+  RC(upload(h, &h->d_g_free, M.g_free));
+  for (int c = 0; c < 8; ++c) {
+    RC(upload(h, &h->d_colour[c], M.colour_elems[c]));
+    h->n_colour[c] = (int64_t)M.colour_elems[c].size();
+  }
+  RC(upload(h, &h->d_elem_sub, M.elem_sub));
+  RC(upload(h, &h->d_QQt, M.QQt));
+  RC(upload(h, &h->d_dN, dN));
+  RC(upload(h, &h->d_f1, M.f1));
+  // matrices
+  const size_t fsz = h->prec == TFETI_PREC_FP64 ? sizeof(double) : sizeof(float);
+  RC(dalloc(h, &h->d_band, M.band_entries));
+  {
+    void* q = nullptr;
+    if (hipMalloc(&q, (size_t)M.band_entries * fsz) != hipSuccess) return fail(h, TFETI_E_OOM, "factor work");
+    h->allocs.push_back(q);
+    h->d_work = q;
+    if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_entries, 1) * fsz) != hipSuccess)
+      return fail(h, TFETI_E_OOM, "forward panels");
+    h->allocs.push_back(q);
+    h->d_F = q;
+    if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_entries, 1) * fsz) != hipSuccess)
+      return fail(h, TFETI_E_OOM, "backward panels");
+    h->allocs.push_back(q);
+    h->d_B = q;
+  }
+  // state
+  RC(dalloc(h, &h->d_sigma, 6 * M.n_gp));
+  RC(dalloc(h, &h->d_kappa, M.n_gp));
+  RC(dalloc(h, &h->d_dsigma, 6 * M.n_gp));
+  RC(dalloc(h, &h->d_dkappa, M.n_gp));
+  RC(dalloc(h, &h->d_plastic, M.n_gp));
+  RC(dalloc(h, &h->d_u, M.n_torn));
+  RC(dalloc(h, &h->d_du, M.n_torn));
+  RC(dalloc(h, &h->d_df, M.n_torn));
+  RC(dalloc(h, &h->d_fint, M.n_torn));
+  RC(dalloc(h, &h->d_f, M.n_torn));
+  RC(dalloc(h, &h->d_delta, M.n_torn));
+  double** mv[] = {&h->d_lam, &h->d_lam_im, &h->d_lam_ker, &h->d_r, &h->d_w, &h->d_z,
+                   &h->d_y,   &h->d_p,      &h->d_q,       &h->d_d, &h->d_lam_prev};
+  for (double** v : mv) RC(dalloc(h, v, M.m));
+  RC(dalloc(h, &h->d_iface, M.n_iface));
+  RC(dalloc(h, &h->d_c, M.lc_pad));
+  RC(dalloc(h, &h->d_a, M.lc_pad));
+  RC(dalloc(h, &h->d_partials, 1024));
+  RC(dalloc(h, &h->d_scal, 16));
+  RC(dalloc(h, &h->d_S, 1));
+  RC(dalloc(h, &h->d_fail, 1));
+  RC(dalloc(h, &h->d_plcount, 1));
+  RC(dalloc(h, &h->d_Ginv, (int64_t)M.lc * M.lc));
+  HIPCHK(hipMemsetAsync(h->d_sigma, 0, 6 * M.n_gp * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_kappa, 0, M.n_gp * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_dsigma, 0, 6 * M.n_gp * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_dkappa, 0, M.n_gp * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_plastic, 0, M.n_gp, h->st));
+  HIPCHK(hipMemsetAsync(h->d_u, 0, M.n_torn * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_du, 0, M.n_torn * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_df, 0, M.n_torn * sizeof(double), h->st));
+  HIPCHK(hipMemsetAsync(h->d_lam_prev, 0, M.m * sizeof(double), h->st));
+  // dual maps
+  DualMaps& dm = h->dm;
+  dm.m = M.m;
+  dm.n_iface = M.n_iface;
+  dm.nsub = M.n_sub;
+  dm.l = M.lc;
+  dm.subs = h->d_subs;
+  dm.b_rowptr = h->d_b_rowptr;
+  dm.b_iface = h->d_b_iface;
+  dm.b_val = h->d_b_val;
+  dm.if_rp = h->d_if_rp;
+  dm.if_row = h->d_if_row;
+  dm.if_coef = h->d_if_coef;
+  dm.if_sub = h->d_if_sub;
+  dm.R_iface = h->d_R_iface;
+  dm.R_full = h->d_R_full;
+  dm.kbb_rp = h->d_kbb_rp;
+  dm.kbb_col = h->d_kbb_col;
+  dm.Ginv = h->d_Ginv;
+  dm.max_iface = h->max_iface;
+  // ---- coarse problem: banded Cholesky of G G^T, then the dense inverse ----
+  {
+    double* d_cb = nullptr;
+    RC(upload(h, &d_cb, M.GGt_band));
+    SubDev cs;
+    std::memset(&cs, 0, sizeof(cs));
+    cs.npad = M.lc_pad;
+    cs.ndof = M.lc;
+    cs.b = M.bc;
+    cs.Wb = M.bc + 1;
+    std::vector<SubDev> csv{cs};
+    SubDev* d_cs = nullptr;
+    RC(upload(h, &d_cs, csv));
+    HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
+    launch_band_cholesky<double>(d_cs, 1, d_cb, h->d_fail, h->st);
+    launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st);
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    if (bad) return fail(h, TFETI_E_NOT_SPD, "coarse matrix G G^T is not positive definite");
+  }
+  h->ev.assign(2 * 512, nullptr);
+  for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
+  return TFETI_OK;
+}
+
+void tfeti_destroy(tfeti_handle* h) {
+  if (!h) return;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  else (void)hipDeviceSynchronize();
+  for (void* p : h->allocs) (void)hipFree(p);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+}
+
+const char* tfeti_last_error(const tfeti_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+int tfeti_get_sizes(const tfeti_handle* h, tfeti_sizes* o) {
+  if (!h || !o) return TFETI_E_INVALID;
+  const HostModel& M = h->M;
+  o->n_sub = M.n_sub;
+  o->n_torn = M.n_torn;
+  o->m = M.m;
+  o->m_G = M.mG;
+  o->m_U = M.mU;
+  o->l = M.lc;
+  o->n_elem = M.n_elem;
+  o->n_gp = M.n_gp;
+  o->n_gdof = M.n_gdof;
+  o->skyline_entries = M.skyline_entries;
+  o->factor_entries = h->panel_entries;
+  o->factor_bytes = h->panel_entries * (h->prec == TFETI_PREC_FP64 ? 8 : 4);
+  o->tile = h->TS;
+  o->precision = h->prec;
+  return TFETI_OK;
+}
+
+int tfeti_get_B_host(const tfeti_handle* h, int64_t* nnz, int64_t* rowptr, int64_t* col, double* val) {
+  if (!h || !nnz) return TFETI_E_INVALID;
+  const HostModel& M = h->M;
+  *nnz = (int64_t)M.b_col.size();
+  if (rowptr) std::memcpy(rowptr, M.b_rowptr.data(), M.b_rowptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, M.b_col.data(), M.b_col.size() * sizeof(int64_t));
+  if (val) std::memcpy(val, M.b_val.data(), M.b_val.size() * sizeof(double));
+  return TFETI_OK;
+}
+
+int tfeti_begin_load_step(tfeti_handle* h, double dlf) {
+  if (!h) return TFETI_E_INVALID;
+  if (!std::isfinite(dlf)) return fail(h, TFETI_E_INVALID, "load factor increment must be finite");
+  const HostModel& M = h->M;
+  h->dlf = dlf;
+  launch_copy(M.n_torn, h->d_f1, h->d_df, h->st);
+  launch_axpby(M.n_torn, 0.0, nullptr, dlf, h->d_df, h->st);
+  HIPCHK(hipMemsetAsync(h->d_du, 0, M.n_torn * sizeof(double), h->st));
+  h->df_norm = assembled_norm(h, h->d_df);
+  h->newton_i = 0;
+  h->step_active = true;
+  h->have_lambda = false;
+  h->assembled_at_du = false;
+  return TFETI_OK;
+}
+
+int tfeti_newton_step(tfeti_handle* h, tfeti_newton_report* rep) {
+  if (!h) return TFETI_E_INVALID;
+  if (!h->step_active) return fail(h, TFETI_E_INVALID, "tfeti_begin_load_step must come first");
+  const HostModel& M = h->M;
+  auto t0 = std::chrono::steady_clock::now();
+  tfeti_newton_report r{};
+  r.iteration = ++h->newton_i;
+  // return map, internal force, tangent at du
+  RC(assemble_at(h, h->d_du, h->d_fint));
+  h->assembled_at_du = true;
+  launch_copy(M.n_torn, h->d_df, h->d_f, h->st);
+  launch_axpby(M.n_torn, -1.0, h->d_fint, 1.0, h->d_f, h->st);
+  double fn = assembled_norm(h, h->d_f);
+  r.relres = h->df_norm > 0 ? fn / h->df_norm : 0.0;
+  r.plastic_gp = (int32_t)h->last_plastic;
+  r.ms_assembly = ms_since(t0);
+  if (r.iteration >= 2 && r.relres <= h->opt.eps_newton) {
+    r.crit = 0.0;
+    r.ms_total = ms_since(t0);
+    if (rep) *rep = r;
+    return TFETI_CONVERGED;
+  }
+  if (r.iteration > h->opt.max_newton) {
+    r.ms_total = ms_since(t0);
+    if (rep) *rep = r;
+    return fail(h, TFETI_W_NEWTON_MAXIT, "Newton iteration cap reached");
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  RC(factorize(h));
+  r.ms_factor = ms_since(t1);
+  auto t2 = std::chrono::steady_clock::now();
+  tfeti_pcg_report pr{};
+  const double* guess = (h->opt.warm_start && h->have_lambda) ? h->d_lam_prev : nullptr;
+  int st = pcg_solve(h, h->d_f, guess, h->d_lam_prev, h->d_delta, &pr);
+  if (st < 0) return st;
+  h->have_lambda = true;
+  r.ms_pcg = ms_since(t2);
+  r.pcg_iters = pr.iters;
+  r.fapplies = pr.fapplies;
+  // the paper's increment criterion, untorn norms
+  double nd = untorn_norm(h, h->d_delta);
+  double nold = untorn_norm(h, h->d_du);
+  launch_axpby(M.n_torn, 1.0, h->d_delta, 1.0, h->d_du, h->st);
+  h->assembled_at_du = false;
+  double nnew = untorn_norm(h, h->d_du);
+  r.crit = (nnew + nold) > 0 ? nd / (nnew + nold) : 0.0;
+  // plastic elements
+  {
+    std::vector<uint8_t> pl(M.n_gp);
+    HIPCHK(hipMemcpyAsync(pl.data(), h->d_plastic, M.n_gp, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    int64_t ne = 0;
+    for (int64_t e = 0; e < M.n_elem; ++e) {
+      bool any = false;
+      for (int g = 0; g < 8; ++g) any |= pl[8 * e + g] != 0;
+      ne += any;
+    }
+    r.plastic_elements = (int32_t)ne;
+  }
+  r.ms_total = ms_since(t0);
+  if (rep) *rep = r;
+  return st == TFETI_W_PCG_MAXIT ? TFETI_W_PCG_MAXIT : TFETI_OK;
+}
+
+int tfeti_commit_load_step(tfeti_handle* h) {
+  if (!h) return TFETI_E_INVALID;
+  if (!h->step_active) return fail(h, TFETI_E_INVALID, "no active load step");
+  const HostModel& M = h->M;
+  if (!h->assembled_at_du) RC(assemble_at(h, h->d_du, h->d_fint));
+  launch_axpby(6 * M.n_gp, 1.0, h->d_dsigma, 1.0, h->d_sigma, h->st);
+  launch_axpby(M.n_gp, 1.0, h->d_dkappa, 1.0, h->d_kappa, h->st);
+  launch_axpby(M.n_torn, 1.0, h->d_du, 1.0, h->d_u, h->st);
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->step_active = false;
+  return TFETI_OK;
+}
+
+int tfeti_dual_pcg(tfeti_handle* h, const double* f, const double* guess, double* lam_out, double* u_out,
+                   tfeti_pcg_report* rep) {
+  if (!h || !f) return TFETI_E_INVALID;
+  if (!h->factored) return fail(h, TFETI_E_INVALID, "no factorized operator: call tfeti_assemble and tfeti_factorize");
+  return pcg_solve(h, f, guess, lam_out, u_out, rep);
+}
+
+int tfeti_assemble(tfeti_handle* h, const double* du, double* fint, int64_t* plastic_count) {
+  if (!h || !du || !fint) return TFETI_E_INVALID;
+  RC(assemble_at(h, du, fint));
+  h->assembled_at_du = false;
+  if (plastic_count) *plastic_count = h->last_plastic;
+  return TFETI_OK;
+}
+
+int tfeti_factorize(tfeti_handle* h) {
+  if (!h) return TFETI_E_INVALID;
+  return factorize(h);
+}
+
+int tfeti_fapply(tfeti_handle* h, const double* lam, double* q) {
+  if (!h || !lam || !q) return TFETI_E_INVALID;
+  if (!h->factored) return fail(h, TFETI_E_INVALID, "no factorized operator");
+  fapply(h, lam, q, nullptr, nullptr, nullptr);
+  if (h->timing && h->ev_used * 2 + 2 >= (int)h->ev.size()) harvest_timing(h, 1 << 30);
+  HIPCHK(hipGetLastError());
+  return TFETI_OK;
+}
+
+int tfeti_kplus(tfeti_handle* h, const double* x, double* y) {
+  if (!h || !x || !y) return TFETI_E_INVALID;
+  if (!h->factored) return fail(h, TFETI_E_INVALID, "no factorized operator");
+  ksolve(h, x, nullptr, 0.0, nullptr, y, nullptr, nullptr);
+  HIPCHK(hipGetLastError());
+  return TFETI_OK;
+}
+
+int tfeti_project(tfeti_handle* h, const double* w, double* out) {
+  if (!h || !w || !out) return TFETI_E_INVALID;
+  project(h, w, out, nullptr, nullptr);
+  HIPCHK(hipGetLastError());
+  return TFETI_OK;
+}
+
+int tfeti_precondition(tfeti_handle* h, const double* w, double* out) {
+  if (!h || !w || !out) return TFETI_E_INVALID;
+  precondition(h, w, out, nullptr);
+  HIPCHK(hipGetLastError());
+  return TFETI_OK;
+}
+
+int tfeti_get_state(const tfeti_handle* hc, double* sigma, double* kappa, double* u, double* du, double* dsigma,
+                    double* dkappa, uint8_t* plastic) {
+  tfeti_handle* h = const_cast<tfeti_handle*>(hc);
+  if (!h) return TFETI_E_INVALID;
+  const HostModel& M = h->M;
+  if (sigma) HIPCHK(hipMemcpyAsync(sigma, h->d_sigma, 6 * M.n_gp * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (kappa) HIPCHK(hipMemcpyAsync(kappa, h->d_kappa, M.n_gp * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (u) HIPCHK(hipMemcpyAsync(u, h->d_u, M.n_torn * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (du) HIPCHK(hipMemcpyAsync(du, h->d_du, M.n_torn * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (dsigma)
+    HIPCHK(hipMemcpyAsync(dsigma, h->d_dsigma, 6 * M.n_gp * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (dkappa) HIPCHK(hipMemcpyAsync(dkappa, h->d_dkappa, M.n_gp * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (plastic) HIPCHK(hipMemcpyAsync(plastic, h->d_plastic, M.n_gp, hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return TFETI_OK;
+}
+
+int tfeti_set_state(tfeti_handle* h, const double* sigma, const double* kappa, const double* u, const double* du) {
+  if (!h) return TFETI_E_INVALID;
+  const HostModel& M = h->M;
+  if (sigma) HIPCHK(hipMemcpyAsync(h->d_sigma, sigma, 6 * M.n_gp * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (kappa) HIPCHK(hipMemcpyAsync(h->d_kappa, kappa, M.n_gp * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (u) HIPCHK(hipMemcpyAsync(h->d_u, u, M.n_torn * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  if (du) HIPCHK(hipMemcpyAsync(h->d_du, du, M.n_torn * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->assembled_at_du = false;
+  return TFETI_OK;
+}
+
+int tfeti_get_lambda(const tfeti_handle* hc, double* lam) {
+  tfeti_handle* h = const_cast<tfeti_handle*>(hc);
+  if (!h || !lam) return TFETI_E_INVALID;
+  HIPCHK(hipMemcpyAsync(lam, h->d_lam, h->M.m * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return TFETI_OK;
+}
+
+int tfeti_set_timing(tfeti_handle* h, int on) {
+  if (!h) return TFETI_E_INVALID;
+  h->timing = on != 0;
+  h->t_ms = 0.0;
+  h->t_count = 0;
+  return TFETI_OK;
+}
+
+int tfeti_get_timing(tfeti_handle* h, double* ms_host, int64_t* count_host) {
+  if (!h || !ms_host || !count_host) return TFETI_E_INVALID;
+  harvest_timing(h, 1 << 30);
+  *ms_host = h->t_ms;
+  *count_host = h->t_count;
+  return TFETI_OK;
+}
+
+int return_map(const tfeti_material* mat, int64_t npts, const double* sigma_k, const double* kappa_k,
+               const double* deps, double* dsigma, double* dkappa, double* Dtan, uint8_t* plastic, void* stream) {
+  if (!mat || npts < 0) return TFETI_E_INVALID;
+  if (npts > 0 && (!sigma_k || !kappa_k || !deps || !dsigma || !dkappa)) return TFETI_E_INVALID;
+  if (!(mat->E > 0 && mat->nu > -1.0 && mat->nu < 0.5 && mat->sigma_y > 0 && mat->H > 0)) return TFETI_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  launch_return_map(*mat, npts, sigma_k, kappa_k, deps, dsigma, dkappa, Dtan, plastic, st);
+  if (hipGetLastError() != hipSuccess) return TFETI_E_HIP;
+  return TFETI_OK;
+}
+
+}  // extern "C"
+
+extern "C" int tfeti_model_host(const tfeti_problem* prob, int32_t tile, tfeti_sizes* sizes, int64_t* nnz,
+                                int64_t* rowptr, int64_t* col, double* val) {
+  if (!prob || !sizes) return TFETI_E_INVALID;
+  if (tile == 0) tile = 32;
+  if (tile != 16 && tile != 32 && tile != 64) return TFETI_E_INVALID;
+  HostModel M;
+  std::string msg = build_model(*prob, M);
+  if (!msg.empty()) return TFETI_E_INVALID;
+  int64_t pe = assign_panels(M, tile);
+  sizes->n_sub = M.n_sub;
+  sizes->n_torn = M.n_torn;
+  sizes->m = M.m;
+  sizes->m_G = M.mG;
+  sizes->m_U = M.mU;
+  sizes->l = M.lc;
+  sizes->n_elem = M.n_elem;
+  sizes->n_gp = M.n_gp;
+  sizes->n_gdof = M.n_gdof;
+  sizes->skyline_entries = M.skyline_entries;
+  sizes->factor_entries = pe;
+  sizes->factor_bytes = 0;
+  sizes->tile = tile;
+  sizes->precision = -1;
+  if (nnz) *nnz = (int64_t)M.b_col.size();
+  if (rowptr) std::memcpy(rowptr, M.b_rowptr.data(), M.b_rowptr.size() * sizeof(int64_t));
+  if (col) std::memcpy(col, M.b_col.data(), M.b_col.size() * sizeof(int64_t));
+  if (val) std::memcpy(val, M.b_val.data(), M.b_val.size() * sizeof(double));
+  return TFETI_OK;
+}

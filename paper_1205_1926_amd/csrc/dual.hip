@@ -1,0 +1,359 @@
+// Dual-space kernels of the PCGP (Algorithm 3), all FP64: the B gather,
+// G w = R^T B^T w, G^T a = B R a, the dense coarse solve with (G G^T)^{-1},
+// the lumped preconditioner B K B^T (Section 4.2), deterministic two-stage
+// reductions and the scalar updates of the iteration.  Every kernel of the
+// iteration returns at once when the device "done" flag is set, so a fixed
+// number of iterations can be enqueued (or replayed from a graph) and the
+// ones after convergence cost only their launch.
+#include "kernels.h"
+
+namespace tfeti {
+
+namespace {
+constexpr int RB = 256;            // threads of reduction blocks
+constexpr int kMaxRedBlocks = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = RB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+}  // namespace
+
+int reduction_blocks(int64_t n) {
+  int64_t b = (n + RB - 1) / RB;
+  if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------- gather
+__global__ __launch_bounds__(RB) void gather_kernel(int64_t m, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ ent, const double* __restrict__ val,
+                                                    const double* __restrict__ iface, double* __restrict__ out,
+                                                    const double* __restrict__ dotv, double* __restrict__ partials,
+                                                    const int32_t* __restrict__ done) {
+  __shared__ double sh[RB];
+  if (done && *done) return;
+  double acc = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < m; r += (int64_t)gridDim.x * RB) {
+    double q = 0.0;
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) q += val[e] * iface[ent[e]];
+    out[r] = q;
+    if (dotv) acc += q * dotv[r];
+  }
+  if (partials) {
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+void launch_gather(const DualMaps& M, const double* iface, double* out, const double* dotv, double* partials,
+                   const int32_t* done, hipStream_t st) {
+  gather_kernel<<<dim3(reduction_blocks(M.m)), dim3(RB), 0, st>>>(M.m, M.b_rowptr, M.b_iface, M.b_val, iface, out,
+                                                                    dotv, partials, done);
+}
+
+// ---------------------------------------------------------------- G w
+__global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* __restrict__ w,
+                                                     double* __restrict__ c, const int32_t* __restrict__ done) {
+  __shared__ double sh[RB];
+  if (done && *done) return;
+  const int64_t p = blockIdx.x;
+  const SubDev s = M.subs[p];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < s.n_iface; t += RB) {
+    const int64_t it = s.iface_off + t;
+    double v = 0.0;
+    for (int e = M.if_rp[it]; e < M.if_rp[it + 1]; ++e) v += M.if_coef[e] * w[M.if_row[e]];
+    const double* R = M.R_iface + 6 * it;
+    for (int j = 0; j < 6; ++j) acc[j] += R[j] * v;
+  }
+  for (int j = 0; j < 6; ++j) {
+    double s6 = block_sum(acc[j], sh);
+    if (threadIdx.x == 0) c[6 * p + j] = s6;
+  }
+}
+
+void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st) {
+  g_apply_kernel<<<dim3((unsigned)M.nsub), dim3(RB), 0, st>>>(M, w, c, done);
+}
+
+// ---------------------------------------------------------------- R^T f
+__global__ __launch_bounds__(RB) void rt_apply_kernel(DualMaps M, const double* __restrict__ f,
+                                                      double* __restrict__ c) {
+  __shared__ double sh[RB];
+  const int64_t p = blockIdx.x;
+  const SubDev s = M.subs[p];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int ld = threadIdx.x; ld < s.ndof; ld += RB) {
+    double v = f[s.dof_off + ld];
+    const double* R = M.R_full + 6 * (s.dof_off + ld);
+    for (int j = 0; j < 6; ++j) acc[j] += R[j] * v;
+  }
+  for (int j = 0; j < 6; ++j) {
+    double s6 = block_sum(acc[j], sh);
+    if (threadIdx.x == 0) c[6 * p + j] = s6;
+  }
+}
+
+void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t st) {
+  rt_apply_kernel<<<dim3((unsigned)M.nsub), dim3(RB), 0, st>>>(M, f, c);
+}
+
+// ---------------------------------------------------------------- coarse solve
+// a = scale * Ginv c: one wave per row, lanes stride the columns, wave
+// reduction by shuffles (fixed order).
+__global__ __launch_bounds__(256) void coarse_gemv_kernel(int64_t l, const double* __restrict__ G,
+                                                          const double* __restrict__ c, double* __restrict__ a,
+                                                          double scale, const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= l) return;
+  const double* g = G + row * l;
+  double acc = 0.0;
+  for (int64_t j = lane; j < l; j += 64) acc += g[j] * c[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) a[row] = scale * acc;
+}
+
+void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double scale, const int32_t* done,
+                        hipStream_t st) {
+  coarse_gemv_kernel<<<dim3((unsigned)((M.l + 3) / 4)), dim3(256), 0, st>>>(M.l, M.Ginv, c, a, scale, done);
+}
+
+// ---------------------------------------------------------------- x - G^T a
+__global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* __restrict__ x,
+                                                      const double* __restrict__ a, double sign,
+                                                      double* __restrict__ out, double* __restrict__ partials,
+                                                      const int32_t* __restrict__ done) {
+  __shared__ double sh[RB];
+  if (done && *done) return;
+  double acc = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < M.m; r += (int64_t)gridDim.x * RB) {
+    double g = 0.0;
+    for (int64_t e = M.b_rowptr[r]; e < M.b_rowptr[r + 1]; ++e) {
+      const int32_t t = M.b_iface[e];
+      const double* R = M.R_iface + 6 * (int64_t)t;
+      const double* ap = a + 6 * (int64_t)M.if_sub[t];
+      double v = 0.0;
+      for (int j = 0; j < 6; ++j) v += R[j] * ap[j];
+      g += M.b_val[e] * v;
+    }
+    double o = (x ? x[r] : 0.0) - sign * g;
+    out[r] = o;
+    acc += o * o;
+  }
+  if (partials) {
+    double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
+                     double* partials, const int32_t* done, hipStream_t st) {
+  gt_apply_kernel<<<dim3(reduction_blocks(M.m)), dim3(RB), 0, st>>>(M, x, a, sign, out, partials, done);
+}
+
+// ---------------------------------------------------------------- lumped preconditioner
+__global__ __launch_bounds__(RB) void lumped_kernel(DualMaps M, const double* __restrict__ w,
+                                                    const double* __restrict__ kv, double* __restrict__ out,
+                                                    const int32_t* __restrict__ done) {
+  extern __shared__ double vloc[];
+  if (done && *done) return;
+  const int64_t p = blockIdx.x;
+  const SubDev s = M.subs[p];
+  for (int t = threadIdx.x; t < s.n_iface; t += RB) {
+    const int64_t it = s.iface_off + t;
+    double v = 0.0;
+    for (int e = M.if_rp[it]; e < M.if_rp[it + 1]; ++e) v += M.if_coef[e] * w[M.if_row[e]];
+    vloc[t] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < s.n_iface; t += RB) {
+    const int64_t it = s.iface_off + t;
+    double y = 0.0;
+    for (int q = M.kbb_rp[it]; q < M.kbb_rp[it + 1]; ++q) y += kv[q] * vloc[M.kbb_col[q] - s.iface_off];
+    out[it] = y;
+  }
+}
+
+void launch_lumped(const DualMaps& M, const double* w, const double* kbb_val, double* iface_out,
+                   const int32_t* done, hipStream_t st) {
+  size_t shm = (size_t)(M.max_iface > 0 ? M.max_iface : 1) * sizeof(double);
+  lumped_kernel<<<dim3((unsigned)M.nsub), dim3(RB), shm, st>>>(M, w, kbb_val, iface_out, done);
+}
+
+// ---------------------------------------------------------------- reductions
+__global__ __launch_bounds__(RB) void dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                 int64_t n, double* __restrict__ partials,
+                                                 const int32_t* __restrict__ done) {
+  __shared__ double sh[RB];
+  if (done && *done) return;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) acc += x[i] * y[i];
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void launch_dot_partials(const double* x, const double* y, int64_t n, double* partials, const int32_t* done,
+                         hipStream_t st) {
+  dot_kernel<<<dim3(reduction_blocks(n)), dim3(RB), 0, st>>>(x, y, n, partials, done);
+}
+
+__global__ __launch_bounds__(RB) void finalize_kernel(int kind, PcgScalars* S, const double* __restrict__ partials,
+                                                      int nparts) {
+  __shared__ double sh[RB];
+  if (kind != FIN_RREF && kind != FIN_SUM_TMP0 && S->done) return;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += RB) acc += partials[i];
+  double sum = block_sum(acc, sh);
+  if (threadIdx.x != 0) return;
+  switch (kind) {
+    case FIN_WW: {
+      S->ww = sum;
+      double nw = sqrt(sum);
+      S->rr = nw;
+      if (!(nw == nw)) {
+        S->nonfinite = 1;
+        S->done = 3;
+      } else if (nw <= S->eps * S->r_ref || S->r_ref == 0.0) {
+        S->done = 1;
+      } else if (S->iters >= S->maxit) {
+        S->done = 2;
+      }
+      break;
+    }
+    case FIN_YW:
+      S->yw = sum;
+      S->beta = (S->iters == 0) ? 0.0 : sum / S->yw_prev;
+      break;
+    case FIN_PQ:
+      S->pq = sum;
+      S->gamma = S->yw / sum;
+      S->yw_prev = S->yw;
+      S->iters += 1;
+      break;
+    case FIN_RREF:
+      S->r_ref = sqrt(sum);
+      break;
+    case FIN_SUM_TMP0:
+      S->tmp0 = sum;
+      break;
+  }
+}
+
+void launch_finalize(int kind, PcgScalars* S, const double* partials, int nparts, hipStream_t st) {
+  finalize_kernel<<<dim3(1), dim3(RB), 0, st>>>(kind, S, partials, nparts);
+}
+
+__global__ void sum_partials_kernel(const double* __restrict__ partials, int n, double* __restrict__ out) {
+  __shared__ double sh[RB];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += RB) acc += partials[i];
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st) {
+  sum_partials_kernel<<<dim3(1), dim3(RB), 0, st>>>(partials, n, out);
+}
+
+// ---------------------------------------------------------------- vector updates
+__global__ void axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * (x ? x[i] : 0.0) + b * y[i];
+}
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
+  if (n > 0) axpby_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, a, x, b, y);
+}
+
+__global__ void copy_kernel(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+void launch_copy(int64_t n, const double* x, double* y, hipStream_t st) {
+  if (n > 0) copy_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, x, y);
+}
+
+__global__ void update_p_kernel(int64_t n, const double* __restrict__ y, double* __restrict__ p,
+                                const PcgScalars* __restrict__ S) {
+  if (S->done) return;
+  const double beta = S->beta;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = y[i] + beta * p[i];
+}
+void launch_update_p(int64_t n, const double* y, double* p, const PcgScalars* S, hipStream_t st) {
+  update_p_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, y, p, S);
+}
+
+__global__ void update_lr_kernel(int64_t n, const double* __restrict__ p, const double* __restrict__ q,
+                                 double* __restrict__ lam, double* __restrict__ r, const PcgScalars* __restrict__ S) {
+  if (S->done) return;
+  const double g = S->gamma;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    lam[i] += g * p[i];
+    r[i] -= g * q[i];
+  }
+}
+void launch_update_lr(int64_t n, const double* p, const double* q, double* lam, double* r, const PcgScalars* S,
+                      hipStream_t st) {
+  update_lr_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, p, q, lam, r, S);
+}
+
+__global__ void check_finite_kernel(int64_t n, const double* __restrict__ x, PcgScalars* S) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(x[i])) S->nonfinite = 1;
+}
+void launch_check_finite(int64_t n, const double* x, PcgScalars* S, hipStream_t st) {
+  if (n > 0) check_finite_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, x, S);
+}
+
+// ---------------------------------------------------------------- Newton-level norms
+__global__ __launch_bounds__(RB) void assembled_sq_kernel(int64_t n, const int32_t* __restrict__ rp,
+                                                          const int64_t* __restrict__ cp,
+                                                          const uint8_t* __restrict__ free_,
+                                                          const double* __restrict__ v, double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+    if (!free_[i]) continue;
+    double s = 0.0;
+    for (int32_t e = rp[i]; e < rp[i + 1]; ++e) s += v[cp[e]];
+    acc += s * s;
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void launch_assembled_sq(int64_t n_gdof, const int32_t* g_rp, const int64_t* g_copies, const uint8_t* g_free,
+                         const double* v, double* partials, hipStream_t st) {
+  assembled_sq_kernel<<<dim3(reduction_blocks(n_gdof)), dim3(RB), 0, st>>>(n_gdof, g_rp, g_copies, g_free, v,
+                                                                            partials);
+}
+
+__global__ __launch_bounds__(RB) void untorn_sq_kernel(int64_t n, const int64_t* __restrict__ first,
+                                                       const double* __restrict__ v, double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+    double x = v[first[i]];
+    acc += x * x;
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void launch_untorn_sq(int64_t n_gdof, const int64_t* g_first, const double* v, double* partials, hipStream_t st) {
+  untorn_sq_kernel<<<dim3(reduction_blocks(n_gdof)), dim3(RB), 0, st>>>(n_gdof, g_first, v, partials);
+}
+
+}  // namespace tfeti

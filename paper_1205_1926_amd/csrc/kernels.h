@@ -1,0 +1,140 @@
+// Kernel argument structs and launchers (host side) of the TFETI library.
+#pragma once
+
+#include "tfeti_internal.h"
+
+namespace tfeti {
+
+struct MatC {
+  double lam, mu, sy, H;
+};
+
+struct AssembleArgs {
+  const SubDev* subs;
+  const int32_t* elems;       // elements of one parity class
+  int64_t n_colour;
+  const int32_t* elem_sub;
+  const double* dN;           // [8 gp][8 node][3 axis]
+  double w;                   // Gauss weight times det J
+  MatC M;
+  const double* du;           // torn displacement increment
+  const double* sigma;        // committed stress (n_gp * 6)
+  const double* kappa;        // committed hardening (n_gp)
+  double* dsigma;
+  double* dkappa;
+  uint8_t* plastic;
+  unsigned long long* plastic_count;
+  double* fint;               // torn internal force (accumulated)
+  double* band;               // row-band tangent (accumulated)
+};
+
+void launch_return_map(const tfeti_material& mat, int64_t npts, const double* sig, const double* kap,
+                       const double* de, double* ds, double* dk, double* Dt, uint8_t* pl, hipStream_t st);
+void launch_assemble(const AssembleArgs& args, hipStream_t st);
+void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStream_t st);
+void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, double* out, hipStream_t st);
+void launch_regularize(const SubDev* subs, int64_t nsub, const double* QQt, double* band, hipStream_t st);
+
+// ---- factorization -------------------------------------------------------
+// In-place band Cholesky of every subdomain's row-band matrix (type T).
+template <typename T>
+void launch_band_cholesky(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, hipStream_t st);
+// Convert the FP64 row-band K_reg into the factor work buffer of type T.
+template <typename T>
+void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st);
+// Pack the factors into forward (F) and backward (B) panels with inverted
+// diagonal tiles.
+template <typename T>
+void launch_pack_panels(const SubDev* subs, int64_t nsub, const T* band, T* Fp, T* Bp, int TS, hipStream_t st);
+// Dense inverse of the coarse matrix from its banded Cholesky factor.
+void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st);
+
+// ---- subdomain solves -----------------------------------------------------
+template <typename T>
+struct KsolveArgs {
+  const SubDev* subs;
+  const int32_t* order;       // schedule: workgroup -> subdomain
+  int64_t nsub;
+  const T* Fp;
+  const T* Bp;
+  const double* in_full;      // torn input or nullptr
+  const double* lam;          // multipliers for B^T lam or nullptr
+  double lam_sign;            // x += lam_sign * B^T lam
+  double* out_iface;          // z at touched DOFs or nullptr
+  double* out_full;           // torn output or nullptr
+  const double* alpha;        // adds R alpha to out_full if not nullptr
+  const double* R_full;
+  const int32_t* if_fidx;
+  const int32_t* if_ldof;
+  const int32_t* if_rp;
+  const int32_t* if_row;
+  const double* if_coef;
+  const int32_t* done;        // skip when *done != 0 (nullptr: never)
+  int32_t part_off;           // LDS offset (entries of T) of the partial sums; set by the launcher
+};
+template <typename T>
+void launch_ksolve(const KsolveArgs<T>& a, int TS, int npad_max, hipStream_t st);
+
+// ---- dual-space kernels (FP64) ---------------------------------------------
+struct DualMaps {
+  int64_t m, n_iface, nsub, l;
+  const SubDev* subs;
+  const int64_t* b_rowptr;
+  const int32_t* b_iface;
+  const double* b_val;
+  const int32_t* if_rp;
+  const int32_t* if_row;
+  const double* if_coef;
+  const int32_t* if_sub;
+  const double* R_iface;
+  const double* R_full;
+  const int32_t* kbb_rp;
+  const int32_t* kbb_col;
+  const double* Ginv;
+  int32_t max_iface;          // largest per-subdomain touched-DOF count (LDS of the preconditioner)
+};
+
+// out[r] = sum_e b_val[e] * iface[b_iface[e]]; if dotv: partial sums of out.dotv
+void launch_gather(const DualMaps& M, const double* iface, double* out, const double* dotv, double* partials,
+                   const int32_t* done, hipStream_t st);
+// c[6p+j] = sum_t R_iface[t][j] (B^T w)_t   (G w)
+void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st);
+// c[6p+j] = sum_ld R_full[ld][j] f[ld]       (R^T f)
+void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t st);
+// a = scale * Ginv c
+void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double scale, const int32_t* done,
+                        hipStream_t st);
+// out = (x ? x : 0) - sign * G^T a; optional partial sums of out.out
+void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
+                     double* partials, const int32_t* done, hipStream_t st);
+// iface_out = K_bb (B^T w) per subdomain
+void launch_lumped(const DualMaps& M, const double* w, const double* kbb_val, double* iface_out,
+                   const int32_t* done, hipStream_t st);
+
+int reduction_blocks(int64_t n);
+void launch_dot_partials(const double* x, const double* y, int64_t n, double* partials, const int32_t* done,
+                         hipStream_t st);
+// scalar finalizers (single thread); see dual.hip
+void launch_finalize(int kind, PcgScalars* S, const double* partials, int nparts, hipStream_t st);
+enum FinalizeKind { FIN_WW = 0, FIN_YW = 1, FIN_PQ = 2, FIN_RREF = 3, FIN_SUM_TMP0 = 4 };
+
+// y = a x + b y style helpers (guarded by done when given)
+void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
+void launch_copy(int64_t n, const double* x, double* y, hipStream_t st);
+// p = y + beta p  (beta from S)
+void launch_update_p(int64_t n, const double* y, double* p, const PcgScalars* S, hipStream_t st);
+// lam += gamma p; r -= gamma q  (gamma from S)
+void launch_update_lr(int64_t n, const double* p, const double* q, double* lam, double* r, const PcgScalars* S,
+                      hipStream_t st);
+// nonfinite check: S->nonfinite |= any(!isfinite(x))
+void launch_check_finite(int64_t n, const double* x, PcgScalars* S, hipStream_t st);
+
+// ---- Newton-level kernels ---------------------------------------------------
+// partial sums of (sum over copies of v)^2 over free global DOFs
+void launch_assembled_sq(int64_t n_gdof, const int32_t* g_rp, const int64_t* g_copies, const uint8_t* g_free,
+                         const double* v, double* partials, hipStream_t st);
+// partial sums of v[g_first[i]]^2 and (v + w)[g_first]^2 etc. (kind selects)
+void launch_untorn_sq(int64_t n_gdof, const int64_t* g_first, const double* v, double* partials, hipStream_t st);
+void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
+
+}  // namespace tfeti

@@ -1,0 +1,214 @@
+// Subdomain solves with the regularized factors: the action of the
+// generalized inverse K^+ (Remark 1: forward and backward substitution per
+// subdomain) fused with the B^T scatter and the interface write of the dual
+// operator F = B K^+ B^T (Section 4.2).
+//
+// One workgroup per subdomain, in a schedule order chosen by the host
+// (longest subdomain first); the whole subdomain vector lives in LDS.  Each
+// triangular solve walks the block rows (TS rows each): all four waves
+// stream the off-diagonal panel chunks (16-byte loads, one output row per
+// lane, coalesced) and accumulate partial dot products; wave 0 reduces them
+// and applies the inverted diagonal tile with lane broadcasts.
+#include "kernels.h"
+
+namespace tfeti {
+
+namespace {
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+  static constexpr int V = 2;
+};
+template <>
+struct Vec<float> {
+  typedef float __attribute__((ext_vector_type(4))) type;
+  static constexpr int V = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ T bcast(T v, int l);
+template <>
+__device__ __forceinline__ float bcast<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ double bcast<double>(double v, int l) {
+  long long x = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), l);
+  int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename VT, int V>
+__device__ __forceinline__ auto vdot(const VT& a, const VT& b) -> decltype(a[0] * b[0]) {
+  auto s = a[0] * b[0];
+#pragma unroll
+  for (int v = 1; v < V; ++v) s += a[v] * b[v];
+  return s;
+}
+
+}  // namespace
+
+template <typename T, int TS>
+__global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
+  using VT = typename Vec<T>::type;
+  constexpr int V = Vec<T>::V;
+  constexpr int NT = 256;
+  constexpr int RPT = NT / TS;           // threads per tile row
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xs = reinterpret_cast<T*>(smem);
+  T* part = xs + A.part_off;             // after the largest subdomain vector
+
+  if (A.done && *A.done) return;
+  const int tid = threadIdx.x;
+  const int32_t p = A.order[blockIdx.x];
+  const SubDev s = A.subs[p];
+  const int n = s.npad, nb = n / TS;
+
+  // ---- input: x = in_full (factor order) + lam_sign B^T lam ----
+  for (int i = tid; i < n; i += NT) xs[i] = T(0);
+  __syncthreads();
+  if (A.in_full) {
+    for (int ld = tid; ld < s.ndof; ld += NT) xs[factor_index(s, ld)] = (T)A.in_full[s.dof_off + ld];
+    __syncthreads();
+  }
+  if (A.lam) {
+    for (int t = tid; t < s.n_iface; t += NT) {
+      const int64_t it = s.iface_off + t;
+      double v = A.in_full ? A.in_full[s.dof_off + A.if_ldof[it]] : 0.0;
+      double bt = 0.0;
+      for (int e = A.if_rp[it]; e < A.if_rp[it + 1]; ++e) bt += A.if_coef[e] * A.lam[A.if_row[e]];
+      xs[A.if_fidx[it]] = (T)(v + A.lam_sign * bt);
+    }
+  }
+  __syncthreads();
+
+  // ---- forward substitution L y = x (in place) ----
+  {
+    const T* P = A.Fp + s.panel_off;
+    int64_t off = 0;
+    const int r = tid % TS;
+    for (int I = 0; I < nb; ++I) {
+      const int w = I * TS < s.bo ? I * TS : s.bo;
+      const int nco = w / V;
+      const int c0 = I * TS - w;
+      T acc = T(0);
+      for (int cc = tid / TS; cc < nco; cc += RPT) {
+        VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)cc * TS + r) * V);
+        VT y = *reinterpret_cast<const VT*>(xs + c0 + cc * V);
+        acc += vdot<VT, V>(L, y);
+      }
+      part[tid] = acc;
+      __syncthreads();
+      if (tid < 64) {
+        T a = T(0);
+        if (tid < TS) {
+          T sum = T(0);
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) sum += part[k * TS + tid];
+          a = xs[I * TS + tid] - sum;
+        }
+        T y = T(0);
+#pragma unroll
+        for (int cc = 0; cc < TS / V; ++cc) {
+          VT L;
+          if (tid < TS)
+            L = *reinterpret_cast<const VT*>(P + off + ((int64_t)(nco + cc) * TS + tid) * V);
+          else
+            L = VT(T(0));
+#pragma unroll
+          for (int v = 0; v < V; ++v) y += L[v] * bcast<T>(a, cc * V + v);
+        }
+        if (tid < TS) xs[I * TS + tid] = y;
+      }
+      __syncthreads();
+      off += (int64_t)TS * (w + TS);
+    }
+  }
+
+  // ---- backward substitution L^T z = y (in place) ----
+  {
+    const T* P = A.Bp + s.panel_off;
+    int64_t off = s.panel_len;
+    const int c = tid % TS;
+    for (int I = nb - 1; I >= 0; --I) {
+      const int rem = n - (I + 1) * TS;
+      const int w = rem < s.bo ? rem : s.bo;
+      off -= (int64_t)TS * (TS + w);
+      const int nco = w / V;
+      const int rbase = (I + 1) * TS;
+      T acc = T(0);
+      for (int rr = tid / TS; rr < nco; rr += RPT) {
+        VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr) * TS + c) * V);
+        VT z = *reinterpret_cast<const VT*>(xs + rbase + rr * V);
+        acc += vdot<VT, V>(L, z);
+      }
+      part[tid] = acc;
+      __syncthreads();
+      if (tid < 64) {
+        T a = T(0);
+        if (tid < TS) {
+          T sum = T(0);
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) sum += part[k * TS + tid];
+          a = xs[I * TS + tid] - sum;
+        }
+        T z = T(0);
+#pragma unroll
+        for (int rc = 0; rc < TS / V; ++rc) {
+          VT L;
+          if (tid < TS)
+            L = *reinterpret_cast<const VT*>(P + off + ((int64_t)rc * TS + tid) * V);
+          else
+            L = VT(T(0));
+#pragma unroll
+          for (int v = 0; v < V; ++v) z += L[v] * bcast<T>(a, rc * V + v);
+        }
+        if (tid < TS) xs[I * TS + tid] = z;
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- outputs ----
+  if (A.out_iface) {
+    for (int t = tid; t < s.n_iface; t += NT) {
+      const int64_t it = s.iface_off + t;
+      A.out_iface[it] = (double)xs[A.if_fidx[it]];
+    }
+  }
+  if (A.out_full) {
+    for (int ld = tid; ld < s.ndof; ld += NT) {
+      double v = (double)xs[factor_index(s, ld)];
+      if (A.alpha) {
+        const double* R = A.R_full + 6 * (s.dof_off + ld);
+        const double* al = A.alpha + 6 * (int64_t)p;
+        for (int j = 0; j < 6; ++j) v += R[j] * al[j];
+      }
+      A.out_full[s.dof_off + ld] = v;
+    }
+  }
+}
+
+template <typename T>
+void launch_ksolve(const KsolveArgs<T>& a, int TS, int npad_max, hipStream_t st) {
+  // shared memory: the vector (npad_max entries, rounded to 16 bytes) + 256 partials
+  size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
+  size_t shm = vec + 256 * sizeof(T);
+  KsolveArgs<T> b = a;
+  b.part_off = (int32_t)(vec / sizeof(T));
+  dim3 grid((unsigned)a.nsub), block(256);
+  if (TS == 16)
+    ksolve_kernel<T, 16><<<grid, block, shm, st>>>(b);
+  else if (TS == 32)
+    ksolve_kernel<T, 32><<<grid, block, shm, st>>>(b);
+  else
+    ksolve_kernel<T, 64><<<grid, block, shm, st>>>(b);
+}
+template void launch_ksolve<double>(const KsolveArgs<double>&, int, int, hipStream_t);
+template void launch_ksolve<float>(const KsolveArgs<float>&, int, int, hipStream_t);
+
+}  // namespace tfeti

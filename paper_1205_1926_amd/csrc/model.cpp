@@ -1,0 +1,510 @@
+// Host-side construction of the TFETI model: structured Q1 mesh split into
+// box subdomains, factor ordering, the orthonormal gluing matrix B
+// (Section 4.1), rigid body modes (Section 4.2), index maps for the kernels,
+// and the coarse matrix G G^T (Algorithm 3, first step).
+#include "model.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace tfeti {
+
+namespace {
+
+inline int64_t gnode(const HostModel& M, int64_t i, int64_t j, int64_t k) {
+  return i + (int64_t)(M.N[0] + 1) * (j + (int64_t)(M.N[1] + 1) * k);
+}
+
+// Shape-function gradients of the trilinear hexahedron on [-1,1]^3, nodes
+// ordered (0,0,0),(1,0,0),(1,1,0),(0,1,0),(0,0,1),(1,0,1),(1,1,1),(0,1,1).
+const int kNodeOff[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
+                            {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
+
+void element_matrices(HostModel& M) {
+  const double g = 1.0 / std::sqrt(3.0);
+  for (int gp = 0; gp < 8; ++gp) {
+    double xi[3] = {(gp & 1) ? g : -g, (gp & 2) ? g : -g, (gp & 4) ? g : -g};
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 24; ++c) M.Bg[gp][r][c] = 0.0;
+    for (int a = 0; a < 8; ++a) {
+      double s[3], f[3];
+      for (int d = 0; d < 3; ++d) {
+        s[d] = kNodeOff[a][d] ? 1.0 : -1.0;
+        f[d] = 1.0 + xi[d] * s[d];
+      }
+      double dN[3];
+      dN[0] = 0.125 * s[0] * f[1] * f[2] * (2.0 / M.h[0]);
+      dN[1] = 0.125 * s[1] * f[0] * f[2] * (2.0 / M.h[1]);
+      dN[2] = 0.125 * s[2] * f[0] * f[1] * (2.0 / M.h[2]);
+      M.Bg[gp][0][3 * a + 0] = dN[0];
+      M.Bg[gp][1][3 * a + 1] = dN[1];
+      M.Bg[gp][2][3 * a + 2] = dN[2];
+      M.Bg[gp][3][3 * a + 0] = dN[1];
+      M.Bg[gp][3][3 * a + 1] = dN[0];
+      M.Bg[gp][4][3 * a + 1] = dN[2];
+      M.Bg[gp][4][3 * a + 2] = dN[1];
+      M.Bg[gp][5][3 * a + 0] = dN[2];
+      M.Bg[gp][5][3 * a + 2] = dN[0];
+    }
+  }
+  M.wg = M.h[0] * M.h[1] * M.h[2] / 8.0;
+}
+
+// Orthonormalize the columns of an (n x k) row-major matrix in place by two
+// passes of modified Gram-Schmidt.
+void mgs(double* A, int n, int k) {
+  for (int pass = 0; pass < 2; ++pass)
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i < j; ++i) {
+        double d = 0.0;
+        for (int r = 0; r < n; ++r) d += A[r * k + i] * A[r * k + j];
+        for (int r = 0; r < n; ++r) A[r * k + j] -= d * A[r * k + i];
+      }
+      double nn = 0.0;
+      for (int r = 0; r < n; ++r) nn += A[r * k + j] * A[r * k + j];
+      nn = std::sqrt(nn);
+      for (int r = 0; r < n; ++r) A[r * k + j] /= nn;
+    }
+}
+
+}  // namespace
+
+std::string build_model(const tfeti_problem& P, HostModel& M) {
+  for (int a = 0; a < 3; ++a) {
+    if (P.S[a] <= 0) return "S must be positive";
+    if (!P.n_host[a]) return "n_host must not be NULL";
+    if (!(P.extent[a] > 0.0)) return "extent must be positive";
+    M.S[a] = P.S[a];
+    M.slab[a].assign(P.n_host[a], P.n_host[a] + P.S[a]);
+    M.N[a] = 0;
+    for (int v : M.slab[a]) {
+      if (v <= 0 || v > 64) return "slab element counts must be in 1..64";
+      M.N[a] += v;
+    }
+    M.ext[a] = P.extent[a];
+    M.h[a] = P.extent[a] / M.N[a];
+  }
+  if (!(P.mat.E > 0 && P.mat.nu > -1.0 && P.mat.nu < 0.5 && P.mat.sigma_y > 0 && P.mat.H > 0))
+    return "material must satisfy E > 0, -1 < nu < 0.5, sigma_y > 0, H > 0";
+  M.mat = P.mat;
+  std::memcpy(M.dir, P.dirichlet, sizeof(M.dir));
+  std::memcpy(M.trac, P.traction, sizeof(M.trac));
+  element_matrices(M);
+
+  const int64_t Nx1 = M.N[0] + 1, Ny1 = M.N[1] + 1, Nz1 = M.N[2] + 1;
+  M.n_gnodes = Nx1 * Ny1 * Nz1;
+  M.n_gdof = 3 * M.n_gnodes;
+  M.n_sub = (int64_t)M.S[0] * M.S[1] * M.S[2];
+  if (M.n_sub > (1 << 20)) return "too many subdomains";
+
+  // ---- subdomains ----
+  std::vector<int32_t> start[3];
+  for (int a = 0; a < 3; ++a) {
+    start[a].resize(M.S[a]);
+    int acc = 0;
+    for (int I = 0; I < M.S[a]; ++I) {
+      start[a][I] = acc;
+      acc += M.slab[a][I];
+    }
+  }
+  M.subs.resize(M.n_sub);
+  M.sub_e0.resize(3 * M.n_sub);
+  int64_t dof_off = 0, elem_off = 0, band_off = 0;
+  for (int K = 0; K < M.S[2]; ++K)
+    for (int J = 0; J < M.S[1]; ++J)
+      for (int I = 0; I < M.S[0]; ++I) {
+        int64_t p = I + (int64_t)M.S[0] * (J + (int64_t)M.S[1] * K);
+        SubDev& s = M.subs[p];
+        std::memset(&s, 0, sizeof(SubDev));
+        s.n[0] = M.slab[0][I];
+        s.n[1] = M.slab[1][J];
+        s.n[2] = M.slab[2][K];
+        for (int a = 0; a < 3; ++a) s.N[a] = s.n[a] + 1;
+        M.sub_e0[3 * p + 0] = start[0][I];
+        M.sub_e0[3 * p + 1] = start[1][J];
+        M.sub_e0[3 * p + 2] = start[2][K];
+        // factor ordering: axes by increasing node count (stable), so that
+        // the half bandwidth 3 (N0 N1 + N0 + 1) + 2 is the smallest
+        int ord[3] = {0, 1, 2};
+        std::stable_sort(ord, ord + 3, [&](int x, int y) { return s.N[x] < s.N[y]; });
+        for (int a = 0; a < 3; ++a) s.perm[a] = ord[a];
+        int64_t nn = (int64_t)s.N[0] * s.N[1] * s.N[2];
+        s.ndof = (int32_t)(3 * nn);
+        s.npad = (s.ndof + kPadRows - 1) / kPadRows * kPadRows;
+        int32_t N0 = s.N[s.perm[0]], N1 = s.N[s.perm[1]], N2 = s.N[s.perm[2]];
+        s.b = 3 * (N0 * N1 + N0 + 1) + 2;
+        s.Wb = s.b + 1;
+        s.bo = (s.b + 3) / 4 * 4;
+        s.n_elem = s.n[0] * s.n[1] * s.n[2];
+        s.dof_off = dof_off;
+        s.elem_off = elem_off;
+        s.band_off = band_off;
+        dof_off += s.ndof;
+        elem_off += s.n_elem;
+        band_off += (int64_t)s.npad * s.Wb;
+        // fixing nodes: three non-collinear corners of the last node layer
+        int32_t last = N2 - 1;
+        int32_t fn[3] = {0 + N0 * (0 + N1 * last), (N0 - 1) + N0 * (0 + N1 * last),
+                         0 + N0 * ((N1 - 1) + N1 * last)};
+        for (int q = 0; q < 3; ++q)
+          for (int c = 0; c < 3; ++c) s.fix[3 * q + c] = 3 * fn[q] + c;
+      }
+  M.n_torn = dof_off;
+  M.n_elem = elem_off;
+  M.n_gp = 8 * elem_off;
+  M.band_entries = band_off;
+  if (M.n_torn >= (int64_t)1 << 31) return "torn vector too long for 32-bit indices";
+
+  // skyline (envelope) size of the factors: per row, distance to the first
+  // coupled column in the factor ordering
+  M.skyline_entries = 0;
+  for (const SubDev& s : M.subs) {
+    int32_t N0 = s.N[s.perm[0]], N1 = s.N[s.perm[1]], N2 = s.N[s.perm[2]];
+    for (int32_t c2 = 0; c2 < N2; ++c2)
+      for (int32_t c1 = 0; c1 < N1; ++c1)
+        for (int32_t c0 = 0; c0 < N0; ++c0) {
+          int32_t f = c0 + N0 * (c1 + N1 * c2);
+          int32_t g0 = std::max(c0 - 1, 0), g1 = std::max(c1 - 1, 0), g2 = std::max(c2 - 1, 0);
+          // smallest neighbour node index: lowest in every axis, but the
+          // neighbour must lie in an element shared with the node
+          int32_t fmin = g0 + N0 * (g1 + N1 * g2);
+          for (int c = 0; c < 3; ++c) M.skyline_entries += 3 * (f - fmin) + c + 1;
+        }
+  }
+
+  // ---- global node -> copies (p ascending) ----
+  std::vector<int32_t> cnt(M.n_gnodes + 1, 0);
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    for (int32_t k = 0; k < s.N[2]; ++k)
+      for (int32_t j = 0; j < s.N[1]; ++j)
+        for (int32_t i = 0; i < s.N[0]; ++i)
+          cnt[gnode(M, M.sub_e0[3 * p] + i, M.sub_e0[3 * p + 1] + j, M.sub_e0[3 * p + 2] + k) + 1]++;
+  }
+  for (int64_t g = 0; g < M.n_gnodes; ++g) cnt[g + 1] += cnt[g];
+  std::vector<int32_t> cp_sub(cnt[M.n_gnodes]), cp_loc(cnt[M.n_gnodes]);
+  {
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t p = 0; p < M.n_sub; ++p) {
+      const SubDev& s = M.subs[p];
+      for (int32_t k = 0; k < s.N[2]; ++k)
+        for (int32_t j = 0; j < s.N[1]; ++j)
+          for (int32_t i = 0; i < s.N[0]; ++i) {
+            int64_t g = gnode(M, M.sub_e0[3 * p] + i, M.sub_e0[3 * p + 1] + j, M.sub_e0[3 * p + 2] + k);
+            int32_t a = i + s.N[0] * (j + s.N[1] * k);
+            cp_sub[fill[g]] = (int32_t)p;
+            cp_loc[fill[g]] = a;
+            fill[g]++;
+          }
+    }
+  }
+
+  // ---- Dirichlet mask per (global node, component) ----
+  auto dirichlet = [&](int64_t g, int c) -> bool {
+    int64_t i = g % Nx1, j = (g / Nx1) % Ny1, k = g / (Nx1 * Ny1);
+    bool on[6] = {i == 0, i == M.N[0], j == 0, j == M.N[1], k == 0, k == M.N[2]};
+    for (int f = 0; f < 6; ++f)
+      if (on[f] && M.dir[f][c]) return true;
+    return false;
+  };
+
+  // ---- B: Helmert gluing rows, then Dirichlet rows ----
+  struct Ent {
+    int32_t p, a, c;
+    double v;
+  };
+  std::vector<int64_t> rpG{0}, rpU{0};
+  std::vector<Ent> eG, eU;
+  M.g_free.assign(M.n_gdof, 1);
+  for (int64_t g = 0; g < M.n_gnodes; ++g) {
+    int32_t k = cnt[g + 1] - cnt[g];
+    for (int c = 0; c < 3; ++c) {
+      if (dirichlet(g, c)) {
+        M.g_free[3 * g + c] = 0;
+        for (int32_t t = 0; t < k; ++t) {
+          eU.push_back({cp_sub[cnt[g] + t], cp_loc[cnt[g] + t], c, 1.0});
+          rpU.push_back((int64_t)eU.size());
+        }
+      } else if (k > 1) {
+        for (int32_t j = 1; j < k; ++j) {
+          double cj = 1.0 / std::sqrt((double)(j * (j + 1)));
+          for (int32_t t = 0; t < j; ++t) eG.push_back({cp_sub[cnt[g] + t], cp_loc[cnt[g] + t], c, cj});
+          eG.push_back({cp_sub[cnt[g] + j], cp_loc[cnt[g] + j], c, -(double)j * cj});
+          rpG.push_back((int64_t)eG.size());
+        }
+      }
+    }
+  }
+  M.mG = (int64_t)rpG.size() - 1;
+  M.mU = (int64_t)rpU.size() - 1;
+  M.m = M.mG + M.mU;
+  if (M.m >= (int64_t)1 << 31) return "too many multipliers";
+  int64_t nnz = (int64_t)eG.size() + (int64_t)eU.size();
+  M.b_rowptr.resize(M.m + 1);
+  M.b_col.resize(nnz);
+  M.b_val.resize(nnz);
+  std::vector<int32_t> e_sub(nnz), e_ldof(nnz);
+  for (int64_t r = 0; r <= M.mG; ++r) M.b_rowptr[r] = rpG[r];
+  for (int64_t r = 1; r <= M.mU; ++r) M.b_rowptr[M.mG + r] = (int64_t)eG.size() + rpU[r];
+  for (int64_t e = 0; e < nnz; ++e) {
+    const Ent& x = e < (int64_t)eG.size() ? eG[e] : eU[e - eG.size()];
+    e_sub[e] = x.p;
+    e_ldof[e] = 3 * x.a + x.c;
+    M.b_col[e] = M.subs[x.p].dof_off + 3 * x.a + x.c;
+    M.b_val[e] = x.v;
+  }
+
+  // ---- touched DOFs per subdomain ----
+  std::vector<int32_t> tidx(M.n_torn, -1);
+  for (int64_t e = 0; e < nnz; ++e) tidx[M.b_col[e]] = 0;
+  M.n_iface = 0;
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    SubDev& s = M.subs[p];
+    s.iface_off = M.n_iface;
+    int32_t cntp = 0;
+    for (int32_t ld = 0; ld < s.ndof; ++ld)
+      if (tidx[s.dof_off + ld] >= 0) {
+        tidx[s.dof_off + ld] = (int32_t)(M.n_iface + cntp);
+        M.if_ldof.push_back(ld);
+        M.if_fidx.push_back(factor_index(s, ld));
+        ++cntp;
+      }
+    s.n_iface = cntp;
+    M.n_iface += cntp;
+  }
+  M.b_iface.resize(nnz);
+  for (int64_t e = 0; e < nnz; ++e) M.b_iface[e] = tidx[M.b_col[e]];
+  // B^T per touched DOF: entries (row, coef) in row order
+  M.if_rp.assign(M.n_iface + 1, 0);
+  for (int64_t e = 0; e < nnz; ++e) M.if_rp[M.b_iface[e] + 1]++;
+  for (int64_t t = 0; t < M.n_iface; ++t) M.if_rp[t + 1] += M.if_rp[t];
+  M.if_row.resize(nnz);
+  M.if_coef.resize(nnz);
+  {
+    std::vector<int32_t> fill(M.if_rp.begin(), M.if_rp.end() - 1);
+    for (int64_t r = 0; r < M.m; ++r)
+      for (int64_t e = M.b_rowptr[r]; e < M.b_rowptr[r + 1]; ++e) {
+        int32_t t = M.b_iface[e];
+        M.if_row[fill[t]] = (int32_t)r;
+        M.if_coef[fill[t]] = M.b_val[e];
+        fill[t]++;
+      }
+  }
+
+  // ---- rigid body modes (translations, rotations about the centroid) ----
+  M.R_full.assign(6 * M.n_torn, 0.0);
+  M.QQt.assign(81 * M.n_sub, 0.0);
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    int64_t nn = s.ndof / 3;
+    double cx = 0, cy = 0, cz = 0;
+    std::vector<double> X(3 * nn);
+    for (int32_t k = 0; k < s.N[2]; ++k)
+      for (int32_t j = 0; j < s.N[1]; ++j)
+        for (int32_t i = 0; i < s.N[0]; ++i) {
+          int32_t a = i + s.N[0] * (j + s.N[1] * k);
+          X[3 * a + 0] = (M.sub_e0[3 * p] + i) * M.h[0];
+          X[3 * a + 1] = (M.sub_e0[3 * p + 1] + j) * M.h[1];
+          X[3 * a + 2] = (M.sub_e0[3 * p + 2] + k) * M.h[2];
+          cx += X[3 * a];
+          cy += X[3 * a + 1];
+          cz += X[3 * a + 2];
+        }
+    cx /= nn;
+    cy /= nn;
+    cz /= nn;
+    double* R = &M.R_full[6 * s.dof_off];
+    for (int64_t a = 0; a < nn; ++a) {
+      double x = X[3 * a] - cx, y = X[3 * a + 1] - cy, z = X[3 * a + 2] - cz;
+      double* r0 = R + 6 * (3 * a + 0);
+      double* r1 = R + 6 * (3 * a + 1);
+      double* r2 = R + 6 * (3 * a + 2);
+      r0[0] = 1.0; r1[1] = 1.0; r2[2] = 1.0;
+      r0[3] = -y; r1[3] = x;
+      r1[4] = -z; r2[4] = y;
+      r0[5] = z;  r2[5] = -x;
+    }
+    mgs(R, s.ndof, 6);
+    // Q: orthonormal basis of the rows of R at the fixing DOFs
+    double Rs[9 * 6];
+    for (int q = 0; q < 9; ++q) {
+      // find the local natural DOF of factor index s.fix[q]
+      int32_t f = s.fix[q], fnode = f / 3, c = f % 3;
+      int32_t N0 = s.N[s.perm[0]], N1 = s.N[s.perm[1]];
+      int32_t co[3];
+      co[s.perm[0]] = fnode % N0;
+      co[s.perm[1]] = (fnode / N0) % N1;
+      co[s.perm[2]] = fnode / (N0 * N1);
+      int32_t a = co[0] + s.N[0] * (co[1] + s.N[1] * co[2]);
+      for (int j = 0; j < 6; ++j) Rs[6 * q + j] = R[6 * (3 * a + c) + j];
+    }
+    mgs(Rs, 9, 6);
+    double* Q = &M.QQt[81 * p];
+    for (int i = 0; i < 9; ++i)
+      for (int j = 0; j < 9; ++j) {
+        double v = 0.0;
+        for (int c = 0; c < 6; ++c) v += Rs[6 * i + c] * Rs[6 * j + c];
+        Q[9 * i + j] = v;
+      }
+  }
+  M.R_iface.resize(6 * M.n_iface);
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    for (int32_t t = 0; t < s.n_iface; ++t) {
+      int32_t ld = M.if_ldof[s.iface_off + t];
+      for (int j = 0; j < 6; ++j) M.R_iface[6 * (s.iface_off + t) + j] = M.R_full[6 * (s.dof_off + ld) + j];
+    }
+  }
+
+  // ---- K_bb pattern: touched DOF pairs whose nodes share an element ----
+  M.kbb_rp.assign(M.n_iface + 1, 0);
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    for (int32_t t = 0; t < s.n_iface; ++t) {
+      int32_t ld = M.if_ldof[s.iface_off + t];
+      int32_t a = ld / 3;
+      int32_t i = a % s.N[0], j = (a / s.N[0]) % s.N[1], k = a / (s.N[0] * s.N[1]);
+      int32_t f = M.if_fidx[s.iface_off + t];
+      for (int dk = -1; dk <= 1; ++dk)
+        for (int dj = -1; dj <= 1; ++dj)
+          for (int di = -1; di <= 1; ++di) {
+            int32_t ii = i + di, jj = j + dj, kk = k + dk;
+            if (ii < 0 || jj < 0 || kk < 0 || ii >= s.N[0] || jj >= s.N[1] || kk >= s.N[2]) continue;
+            int32_t a2 = ii + s.N[0] * (jj + s.N[1] * kk);
+            for (int c2 = 0; c2 < 3; ++c2) {
+              int32_t t2 = tidx[s.dof_off + 3 * a2 + c2];
+              if (t2 < 0) continue;
+              int32_t f2 = M.if_fidx[t2];
+              int32_t r = std::max(f, f2), cc = std::min(f, f2);
+              M.kbb_col.push_back(t2);
+              M.kbb_band.push_back(s.band_off + (int64_t)r * s.Wb + (cc - r + s.b));
+            }
+          }
+      M.kbb_rp[s.iface_off + t + 1] = (int32_t)M.kbb_col.size();
+    }
+  }
+
+  // ---- untorn maps ----
+  M.g_first.resize(M.n_gdof);
+  M.g_rp.assign(M.n_gdof + 1, 0);
+  M.g_copies.clear();
+  M.g_copies.reserve(3 * cp_sub.size());
+  for (int64_t g = 0; g < M.n_gnodes; ++g)
+    for (int c = 0; c < 3; ++c) {
+      int64_t gd = 3 * g + c;
+      for (int32_t t = cnt[g]; t < cnt[g + 1]; ++t)
+        M.g_copies.push_back(M.subs[cp_sub[t]].dof_off + 3 * cp_loc[t] + c);
+      M.g_first[gd] = M.subs[cp_sub[cnt[g]]].dof_off + 3 * cp_loc[cnt[g]] + c;
+      M.g_rp[gd + 1] = (int32_t)M.g_copies.size();
+    }
+
+  // ---- colouring of elements ----
+  M.elem_sub.resize(M.n_elem);
+  for (int c = 0; c < 8; ++c) M.colour_elems[c].clear();
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    for (int32_t k = 0; k < s.n[2]; ++k)
+      for (int32_t j = 0; j < s.n[1]; ++j)
+        for (int32_t i = 0; i < s.n[0]; ++i) {
+          int64_t e = s.elem_off + i + s.n[0] * (j + s.n[1] * k);
+          M.elem_sub[e] = (int32_t)p;
+          M.colour_elems[(i & 1) | ((j & 1) << 1) | ((k & 1) << 2)].push_back((int32_t)e);
+        }
+  }
+
+  // ---- load at factor 1: each subdomain integrates its own loaded faces ----
+  M.f1.assign(M.n_torn, 0.0);
+  const double gq = 1.0 / std::sqrt(3.0);
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    for (int face = 0; face < 6; ++face) {
+      const double* t = M.trac[face];
+      if (t[0] == 0.0 && t[1] == 0.0 && t[2] == 0.0) continue;
+      int ax = face / 2, side = face % 2;
+      int loc = side ? s.n[ax] : 0;
+      if (M.sub_e0[3 * p + ax] + loc != (side ? M.N[ax] : 0)) continue;
+      int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+      double jac = M.h[a1] * M.h[a2] / 4.0;
+      const double ref[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+      double fl[4] = {0, 0, 0, 0};
+      for (int gj = 0; gj < 2; ++gj)
+        for (int gi = 0; gi < 2; ++gi) {
+          double u = gi ? gq : -gq, v = gj ? gq : -gq;
+          for (int q = 0; q < 4; ++q) fl[q] += 0.25 * (1 + u * ref[q][0]) * (1 + v * ref[q][1]) * jac;
+        }
+      const int dd[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+      for (int ib = 0; ib < s.n[a2]; ++ib)
+        for (int ia = 0; ia < s.n[a1]; ++ia)
+          for (int q = 0; q < 4; ++q) {
+            int co[3];
+            co[ax] = loc;
+            co[a1] = ia + dd[q][0];
+            co[a2] = ib + dd[q][1];
+            int32_t a = co[0] + s.N[0] * (co[1] + s.N[1] * co[2]);
+            for (int c = 0; c < 3; ++c) M.f1[s.dof_off + 3 * a + c] += fl[q] * t[c];
+          }
+    }
+  }
+
+  // ---- coarse matrix G G^T (G = R^T B^T), lower row-band ----
+  M.lc = (int32_t)(6 * M.n_sub);
+  int64_t maxdp = 0;
+  for (int64_t r = 0; r < M.m; ++r)
+    for (int64_t e = M.b_rowptr[r]; e < M.b_rowptr[r + 1]; ++e)
+      for (int64_t e2 = M.b_rowptr[r]; e2 < M.b_rowptr[r + 1]; ++e2)
+        maxdp = std::max<int64_t>(maxdp, std::abs((int64_t)e_sub[e] - e_sub[e2]));
+  M.bc = (int32_t)(6 * maxdp + 5);
+  M.lc_pad = (M.lc + kPadRows - 1) / kPadRows * kPadRows;
+  const int64_t Wc = M.bc + 1;
+  M.GGt_band.assign((int64_t)M.lc_pad * Wc, 0.0);
+  for (int64_t r = 0; r < M.m; ++r) {
+    // column r of G: for entry (p, ldof, v): v * R_p[ldof, :] at rows 6p..6p+5
+    int64_t e0 = M.b_rowptr[r], e1 = M.b_rowptr[r + 1];
+    for (int64_t e = e0; e < e1; ++e)
+      for (int64_t e2 = e0; e2 < e1; ++e2) {
+        int64_t pa = e_sub[e], pb = e_sub[e2];
+        if (pa < pb) continue;
+        const double* Ra = &M.R_full[6 * M.b_col[e]];
+        const double* Rb = &M.R_full[6 * M.b_col[e2]];
+        double va = M.b_val[e], vb = M.b_val[e2];
+        for (int i = 0; i < 6; ++i)
+          for (int j = 0; j < 6; ++j) {
+            int64_t gi = 6 * pa + i, gj = 6 * pb + j;
+            if (gj > gi) continue;
+            M.GGt_band[gi * Wc + (gj - gi + M.bc)] += (va * Ra[i]) * (vb * Rb[j]);
+          }
+      }
+  }
+  for (int64_t i = M.lc; i < M.lc_pad; ++i) M.GGt_band[i * Wc + M.bc] = 1.0;
+
+  // ---- sanity checks of every index map against its target ----
+  for (int64_t e = 0; e < nnz; ++e)
+    if (M.b_col[e] < 0 || M.b_col[e] >= M.n_torn || M.b_iface[e] < 0 || M.b_iface[e] >= M.n_iface)
+      return "internal: B map out of range";
+  for (int64_t t = 0; t < M.n_iface; ++t)
+    if (M.if_fidx[t] < 0) return "internal: touched DOF map";
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    for (int32_t t = 0; t < s.n_iface; ++t)
+      if (M.if_fidx[s.iface_off + t] >= s.ndof) return "internal: factor index out of range";
+    for (int q = 0; q < 9; ++q)
+      if (s.fix[q] < 0 || s.fix[q] >= s.ndof) return "internal: fixing DOF out of range";
+  }
+  for (size_t q = 0; q < M.kbb_band.size(); ++q)
+    if (M.kbb_band[q] < 0 || M.kbb_band[q] >= M.band_entries) return "internal: K_bb map out of range";
+  return "";
+}
+
+int64_t assign_panels(HostModel& M, int TS) {
+  int64_t off = 0;
+  for (SubDev& s : M.subs) {
+    s.panel_off = off;
+    s.panel_len = panel_entries(s.npad, s.bo, TS);
+    off += s.panel_len;
+  }
+  return off;
+}
+
+}  // namespace tfeti

@@ -1,0 +1,78 @@
+// Host-side model: mesh, box decomposition, factor ordering, gluing matrix
+// B, rigid modes, index maps and the coarse matrix G G^T.  Built once by
+// tfeti_setup; only integer maps and FP64 constants, no device state.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tfeti_internal.h"
+
+namespace tfeti {
+
+struct HostModel {
+  // problem
+  int32_t S[3];
+  std::vector<int32_t> slab[3];
+  double ext[3];
+  tfeti_material mat;
+  int32_t dir[6][3];
+  double trac[6][3];
+  // mesh
+  int32_t N[3];          // global elements per axis
+  double h[3];           // element edge lengths
+  int64_t n_gnodes = 0, n_gdof = 0;
+  int64_t n_torn = 0, n_elem = 0, n_gp = 0, n_sub = 0;
+  std::vector<SubDev> subs;
+  std::vector<int32_t> sub_e0;           // 3 per subdomain: first global element index per axis
+  // B in CSR (rows of B_G then B_U)
+  int64_t m = 0, mG = 0, mU = 0;
+  std::vector<int64_t> b_rowptr;        // m + 1
+  std::vector<int64_t> b_col;           // torn DOF per entry
+  std::vector<double> b_val;
+  std::vector<int32_t> b_iface;         // global touched index per entry
+  // touched DOFs ("interface"): per subdomain ascending local DOF
+  int64_t n_iface = 0;
+  std::vector<int32_t> if_fidx;         // factor index
+  std::vector<int32_t> if_ldof;         // local natural DOF
+  std::vector<int32_t> if_rp;           // n_iface + 1: entries of B^T per touched DOF
+  std::vector<int32_t> if_row;          // row of each entry
+  std::vector<double> if_coef;
+  // rigid modes
+  std::vector<double> R_full;           // n_torn * 6 (torn order)
+  std::vector<double> R_iface;          // n_iface * 6
+  // K_bb pattern (lumped preconditioner): CSR over touched DOFs
+  std::vector<int32_t> kbb_rp;          // n_iface + 1
+  std::vector<int32_t> kbb_col;         // global touched index
+  std::vector<int64_t> kbb_band;        // entry offset in the row-band storage
+  // untorn maps
+  std::vector<int64_t> g_first;         // n_gdof: torn index of the lowest-p copy
+  std::vector<int32_t> g_rp;            // n_gdof + 1
+  std::vector<int64_t> g_copies;        // torn indices of all copies
+  std::vector<uint8_t> g_free;          // 1 if not Dirichlet
+  // element colouring (2x2x2 parity classes share no node)
+  std::vector<int32_t> colour_elems[8];
+  std::vector<int32_t> elem_sub;
+  // fixing nodes: rho-free regularization block Q Q^T (9x9) per subdomain
+  std::vector<double> QQt;
+  // strain-displacement matrices of the (uniform) element, weights
+  double Bg[8][6][24];
+  double wg;
+  // load at factor 1, torn
+  std::vector<double> f1;
+  // coarse matrix G G^T in lower row-band form
+  int32_t lc = 0, bc = 0, lc_pad = 0;
+  std::vector<double> GGt_band;         // lc_pad rows of (bc + 1)
+  // sizes
+  int64_t band_entries = 0;             // sum npad * Wb
+  int64_t skyline_entries = 0;          // sum of envelope widths of the factors
+};
+
+// Build the host model; returns an empty string on success, else a message.
+std::string build_model(const tfeti_problem& prob, HostModel& M);
+
+// Assign panel offsets for tile TS; returns entries of one layout.
+int64_t assign_panels(HostModel& M, int TS);
+
+}  // namespace tfeti

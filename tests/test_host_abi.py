@@ -1,0 +1,105 @@
+"""CPU tests of the HIP library's host side: the shared library loads and
+exports every function declared in include/tfeti.h, and the host-built model
+(decomposition, gluing matrix B, sizes) matches the oracle bit for bit.
+No kernel is launched."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.mesh import Mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tfeti.h")
+LIB = os.path.join(ROOT, "paper_1205_1926_amd", "libtfeti.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libtfeti.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for fn in ("tfeti_setup", "tfeti_newton_step", "tfeti_dual_pcg", "return_map", "tfeti_fapply"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    from paper_1205_1926_amd import _capi
+    assert set(_capi.SIGNATURES) == set(declared_functions())
+
+
+@pytest.mark.parametrize("w", [W.config(0), W.config(1), W.small_cube(S=(3, 2, 2), n=(2, 3, 2)),
+                               W.patch_test(S=(2, 2, 3), n=(2, 1, 2)),
+                               W.Workload("uneven", (2, 3, 2), [3, 5], [2, 4, 3], [6, 2],
+                                          dirichlet=[[1, 0, 0], [0, 0, 0], [0, 1, 0], [0, 0, 0], [1, 1, 1], [0, 0, 0]])])
+def test_B_maps_bit_exact_with_oracle(w):
+    from paper_1205_1926_amd import model_host
+    sizes, rp, col, val = model_host(w)
+    m = Mesh(w)
+    assert (sizes["m"], sizes["m_G"], sizes["m_U"], sizes["n_torn"]) == (m.m, m.m_G, m.m_U, m.n_torn)
+    assert np.array_equal(rp, m.B_indptr)
+    assert np.array_equal(col, m.B_idx)
+    assert np.array_equal(val.view(np.uint64), m.B_val.view(np.uint64))
+
+
+def test_sizes_of_the_benchmark_mesh():
+    """10x10x10 subdomains of 8^3 elements: multiplier counts and the skyline
+    (envelope) of the factors, 535086 entries per subdomain."""
+    from paper_1205_1926_amd import model_host
+    sizes, *_ = model_host(W.config(4))
+    assert sizes["n_sub"] == 1000 and sizes["n_torn"] == 2187000
+    assert (sizes["m"], sizes["m_G"], sizes["m_U"]) == (612360, 588060, 24300)
+    assert sizes["l"] == 6000
+    assert sizes["skyline_entries"] == 535086 * 1000
+
+
+def test_skyline_count_by_brute_force():
+    """The library's envelope count equals the envelope of the oracle's
+    assembled subdomain matrix (first nonzero column per row)."""
+    from paper_1205_1926_amd import model_host
+    from oracle import assembly
+    w = W.small_cube(S=(1, 1, 1), n=(3, 2, 4))
+    sizes, *_ = model_host(w)
+    mesh = Mesh(w)
+    ed = assembly.element_dofs_torn(mesh)
+    a = assembly.assemble(mesh, ed, mesh.n_torn, np.zeros(mesh.n_torn), np.zeros((mesh.n_elems, 8, 6)),
+                          np.zeros((mesh.n_elems, 8)))
+    K = a["K"].tocsr()
+    # factor ordering of the library: axes by increasing node count (here y, x, z)
+    s = mesh.subs[0]
+    N = [s.n[0] + 1, s.n[1] + 1, s.n[2] + 1]
+    order = sorted(range(3), key=lambda ax: N[ax])
+    perm = np.zeros(mesh.n_torn, dtype=np.int64)
+    for a_ in range(s.n_nodes):
+        ijk = [a_ % N[0], (a_ // N[0]) % N[1], a_ // (N[0] * N[1])]
+        f = ijk[order[0]] + N[order[0]] * (ijk[order[1]] + N[order[1]] * ijk[order[2]])
+        for c in range(3):
+            perm[3 * a_ + c] = 3 * f + c
+    Kp = K[np.argsort(perm)][:, np.argsort(perm)].tocsr()
+    env = 0
+    for r in range(Kp.shape[0]):
+        cols = Kp.indices[Kp.indptr[r]:Kp.indptr[r + 1]]
+        cols = cols[np.abs(Kp.data[Kp.indptr[r]:Kp.indptr[r + 1]]) > 0]
+        env += r - cols.min() + 1
+    assert sizes["skyline_entries"] == env
+
+
+def test_invalid_problem_rejected():
+    from paper_1205_1926_amd import model_host, TfetiError
+    w = W.small_cube()
+    w.material.H = 0.0
+    with pytest.raises(TfetiError):
+        model_host(w)
