@@ -252,10 +252,11 @@ __global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restric
   __shared__ double red[256];
   int64_t p = blockIdx.x;
   if (p >= nsub) return;
-  const SubDev s = subs[p];
+  const int32_t ndof = subs[p].ndof, Wb = subs[p].Wb, b = subs[p].b;
+  const int64_t boff = subs[p].band_off;
   double mx = 0.0;
-  for (int32_t r = threadIdx.x; r < s.ndof; r += blockDim.x) {
-    double v = band[s.band_off + (int64_t)r * s.Wb + s.b];
+  for (int32_t r = threadIdx.x; r < ndof; r += blockDim.x) {
+    double v = band[boff + (int64_t)r * Wb + b];
     mx = v > mx ? v : mx;
   }
   red[threadIdx.x] = mx;
@@ -267,8 +268,9 @@ __global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restric
   double rho = red[0];
   if (threadIdx.x < 81) {
     int i = threadIdx.x / 9, j = threadIdx.x % 9;
-    int32_t fi = s.fix[i], fj = s.fix[j];
-    if (fi >= fj) band[s.band_off + (int64_t)fi * s.Wb + (fj - fi + s.b)] += rho * QQt[81 * p + 9 * i + j];
+    const int32_t* fix = subs[p].fix;
+    int32_t fi = fix[i], fj = fix[j];
+    if (fi >= fj) band[boff + (int64_t)fi * Wb + (fj - fi + b)] += rho * QQt[81 * p + 9 * i + j];
   }
 }
 

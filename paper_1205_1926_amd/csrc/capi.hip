@@ -23,7 +23,7 @@ struct tfeti_handle {
   hipStream_t st = nullptr;
   int TS = 32;
   int prec = 0;
-  int npad_max = 0, max_iface = 0;
+  int npad_max = 0, max_iface = 0, bmax = 0, chol_nb = 0;
   int64_t panel_entries = 0;
   std::vector<void*> allocs;
   // maps
@@ -373,12 +373,12 @@ int factorize(tfeti_handle* h) {
   HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
   if (h->prec == TFETI_PREC_FP64) {
     launch_convert_band<double>(h->d_band, (double*)h->d_work, M.band_entries, h->st);
-    launch_band_cholesky<double>(h->d_subs, M.n_sub, (double*)h->d_work, h->d_fail, h->st);
+    launch_band_cholesky<double>(h->d_subs, M.n_sub, (double*)h->d_work, h->d_fail, h->bmax, h->chol_nb, h->st);
     launch_pack_panels<double>(h->d_subs, M.n_sub, (const double*)h->d_work, (double*)h->d_F, (double*)h->d_B,
                                h->TS, h->st);
   } else {
     launch_convert_band<float>(h->d_band, (float*)h->d_work, M.band_entries, h->st);
-    launch_band_cholesky<float>(h->d_subs, M.n_sub, (float*)h->d_work, h->d_fail, h->st);
+    launch_band_cholesky<float>(h->d_subs, M.n_sub, (float*)h->d_work, h->d_fail, h->bmax, h->chol_nb, h->st);
     launch_pack_panels<float>(h->d_subs, M.n_sub, (const float*)h->d_work, (float*)h->d_F, (float*)h->d_B, h->TS,
                               h->st);
   }
@@ -441,6 +441,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   for (const SubDev& s : M.subs) {
     h->npad_max = std::max(h->npad_max, s.npad);
     h->max_iface = std::max(h->max_iface, s.n_iface);
+    h->bmax = std::max(h->bmax, s.b);
   }
   // schedule: longest subdomain first (stable)
   std::vector<int32_t> order(M.n_sub);
@@ -573,7 +574,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     SubDev* d_cs = nullptr;
     RC(upload(h, &d_cs, csv));
     HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
-    launch_band_cholesky<double>(d_cs, 1, d_cb, h->d_fail, h->st);
+    launch_band_cholesky<double>(d_cs, 1, d_cb, h->d_fail, M.bc, 0, h->st);
     launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));

@@ -1,0 +1,205 @@
+// Batched band Cholesky of the regularized subdomain tangents (Remark 1:
+// once regularized, each block is factorized by a standard Cholesky method
+// for nonsingular matrices).
+//
+// Storage: row-band, row r holds columns r-b..r (entry (r, k) is column
+// r-b+k, k = b the diagonal); rows are the subdomain DOFs in the factor
+// ordering, padded with identity rows to a multiple of 64.
+//
+// One workgroup (256 threads) per band matrix, right-looking by block
+// columns of NB: the panel (the NB block columns of every row the band
+// reaches, at most NB + b rows) is staged in LDS; wave 0 factors the
+// diagonal tile in registers (lane = row, lane broadcasts); the rows below
+// are solved against it in LDS; the panel is written back and the trailing
+// band window is updated in 64 x 64 tiles straight from the LDS panel (each
+// thread owns a 4 x 4 block of outputs), so global traffic is one
+// read-modify-write of the window per block column.
+#include "kernels.h"
+
+namespace tfeti {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T bcast_lane(T v, int l);
+template <>
+__device__ __forceinline__ float bcast_lane<float>(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <>
+__device__ __forceinline__ double bcast_lane<double>(double v, int l) {
+  long long x = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), l);
+  int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int TT = 64;  // trailing-update tile edge
+
+}  // namespace
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t nsub,
+                                                            T* __restrict__ W, int32_t* __restrict__ fail) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* Lp = reinterpret_cast<T*>(smem);          // panel rows x (NB + 1)
+  constexpr int LS = NB + 1;
+  __shared__ int s_fail;
+  const int64_t p = blockIdx.x;
+  if (p >= nsub) return;
+  const int b = subs[p].b, Wb = subs[p].Wb, n = subs[p].npad;
+  T* A = W + subs[p].band_off;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_fail = 0;
+
+  for (int J = 0; J < n; J += NB) {
+    const int jb = (n - J) < NB ? (n - J) : NB;
+    int rend = J + jb + b;
+    if (rend > n) rend = n;
+    const int nr = rend - J;                      // panel rows (>= jb)
+    // ---- stage the panel ----
+    for (int q = tid; q < nr * NB; q += blockDim.x) {
+      const int r = q / NB, j = q - (q / NB) * NB;
+      T v = T(0);
+      if (j < jb && j <= r && r - j <= b) v = A[(int64_t)(J + r) * Wb + (j - r + b)];
+      Lp[r * LS + j] = v;
+    }
+    __syncthreads();
+    // ---- diagonal tile: wave 0, lane = row, in registers ----
+    if (tid < 64) {
+      const int i = tid;
+      T a[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) a[j] = (i < jb) ? Lp[i * LS + j] : T(0);
+      bool bad = false;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (k < jb) {
+          T dkk = bcast_lane(a[k], k);
+          if (!(dkk > T(0))) {
+            bad = true;
+            dkk = T(1);
+          }
+          const T lkk = sqrt(dkk);
+          if (i == k) a[k] = lkk;
+          if (i > k) a[k] = a[k] / lkk;
+#pragma unroll
+          for (int j = k + 1; j < NB; ++j) {
+            const T ljk = bcast_lane(a[k], j);
+            if (i >= j && j < jb) a[j] -= a[k] * ljk;
+          }
+        }
+      }
+      if (bad && i == 0) s_fail = 1;
+      if (i < jb) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) Lp[i * LS + j] = a[j];
+      }
+    }
+    __syncthreads();
+    // ---- rows below: x := x L_JJ^{-T} in LDS ----
+    for (int r = jb + tid; r < nr; r += blockDim.x) {
+      T* row = Lp + r * LS;
+      for (int j = 0; j < jb; ++j) {
+        T v = row[j];
+        const T* lj = Lp + j * LS;
+        for (int k = 0; k < j; ++k) v -= row[k] * lj[k];
+        row[j] = v / lj[j];
+      }
+    }
+    __syncthreads();
+    // ---- write the panel back ----
+    for (int q = tid; q < nr * NB; q += blockDim.x) {
+      const int r = q / NB, j = q - (q / NB) * NB;
+      if (j < jb && j <= r && r - j <= b) A[(int64_t)(J + r) * Wb + (j - r + b)] = Lp[r * LS + j];
+    }
+    // ---- trailing update from the LDS panel (columns >= J + jb only) ----
+    const int rbeg = J + jb;
+    const int ty = tid / 16, tx = tid % 16;
+    for (int RT = rbeg; RT < rend; RT += TT) {
+      for (int CT = rbeg; CT <= RT; CT += TT) {
+        if (RT - (CT + TT - 1) > b) continue;
+        int ri[4], ci[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int r = RT + ty * 4 + u - J;
+          ri[u] = (r < nr ? r : nr - 1) * LS;
+          int c = CT + tx + 16 * u - J;
+          ci[u] = (c < nr ? c : nr - 1) * LS;
+        }
+        T acc[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
+        for (int k = 0; k < jb; ++k) {
+          T ra[4], cb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) ra[u] = Lp[ri[u] + k];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) cb[v] = Lp[ci[v] + k];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += ra[u] * cb[v];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = RT + ty * 4 + u, c = CT + tx + 16 * v;
+            if (r < rend && c <= r && r - c <= b) A[(int64_t)r * Wb + (c - r + b)] -= acc[u][v];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && s_fail) atomicOr(fail, 1);
+}
+
+namespace {
+int g_smem_limit = 0;
+}
+
+int band_cholesky_nb(int bmax, size_t elem) {
+  if (g_smem_limit == 0) {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 65536;
+    g_smem_limit = v;
+  }
+  for (int nb : {32, 16, 8})
+    if ((size_t)(nb + bmax) * (nb + 1) * elem <= (size_t)g_smem_limit) return nb;
+  return 0;
+}
+
+template <typename T, int NB>
+static int launch_nb(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, int bmax, hipStream_t st) {
+  size_t shm = (size_t)(NB + bmax) * (NB + 1) * sizeof(T);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)band_cholesky_kernel<T, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)shm);
+  band_cholesky_kernel<T, NB><<<dim3((unsigned)nsub), dim3(256), shm, st>>>(subs, nsub, band, fail);
+  return 0;
+}
+
+template <typename T>
+int launch_band_cholesky(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, int bmax, int nb,
+                         hipStream_t st) {
+  if (nb <= 0) nb = band_cholesky_nb(bmax, sizeof(T));
+  switch (nb) {
+    case 32:
+      return launch_nb<T, 32>(subs, nsub, band, fail, bmax, st);
+    case 16:
+      return launch_nb<T, 16>(subs, nsub, band, fail, bmax, st);
+    case 8:
+      return launch_nb<T, 8>(subs, nsub, band, fail, bmax, st);
+    default:
+      return -1;
+  }
+}
+template int launch_band_cholesky<double>(const SubDev*, int64_t, double*, int32_t*, int, int, hipStream_t);
+template int launch_band_cholesky<float>(const SubDev*, int64_t, float*, int32_t*, int, int, hipStream_t);
+
+}  // namespace tfeti

@@ -169,19 +169,27 @@ __global__ __launch_bounds__(RB) void lumped_kernel(DualMaps M, const double* __
   extern __shared__ double vloc[];
   if (done && *done) return;
   const int64_t p = blockIdx.x;
-  const SubDev s = M.subs[p];
-  for (int t = threadIdx.x; t < s.n_iface; t += RB) {
-    const int64_t it = s.iface_off + t;
+  const int32_t nif = M.subs[p].n_iface;
+  const int64_t ioff = M.subs[p].iface_off;
+  for (int t = threadIdx.x; t < nif; t += RB) {
+    const int64_t it = ioff + t;
     double v = 0.0;
     for (int e = M.if_rp[it]; e < M.if_rp[it + 1]; ++e) v += M.if_coef[e] * w[M.if_row[e]];
     vloc[t] = v;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < s.n_iface; t += RB) {
-    const int64_t it = s.iface_off + t;
+  // K_bb rows: a group of 16 lanes per row streams the row's entries
+  // (coalesced), then reduces by shuffles in a fixed order
+  constexpr int G = 16;
+  const int lane = threadIdx.x % G;
+  for (int t = threadIdx.x / G; t < nif; t += RB / G) {
+    const int64_t it = ioff + t;
+    const int q0 = M.kbb_rp[it], q1 = M.kbb_rp[it + 1];
     double y = 0.0;
-    for (int q = M.kbb_rp[it]; q < M.kbb_rp[it + 1]; ++q) y += kv[q] * vloc[M.kbb_col[q] - s.iface_off];
-    out[it] = y;
+    for (int q = q0 + lane; q < q1; q += G) y += kv[q] * vloc[M.kbb_col[q] - ioff];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) y += __shfl_down(y, off, G);
+    if (lane == 0) out[it] = y;
   }
 }
 

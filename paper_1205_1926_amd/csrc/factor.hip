@@ -1,7 +1,5 @@
-// Batched band Cholesky of the regularized subdomain tangents (Remark 1:
-// regularized blocks factorized by a standard Cholesky method for
-// nonsingular matrices), panel packing for the triangular solves, and the
-// dense inverse of the coarse matrix G G^T.
+// Factor format conversion, panel packing for the triangular solves, and
+// the dense inverse of the coarse matrix G G^T.
 //
 // Storage: row-band, row r holds columns r-b..r (entry (r, k) is column
 // r-b+k, k = b the diagonal); rows are the subdomain DOFs in the factor
@@ -9,155 +7,6 @@
 #include "kernels.h"
 
 namespace tfeti {
-
-namespace {
-
-template <typename T>
-__device__ __forceinline__ T bcast_lane(T v, int l);
-
-template <>
-__device__ __forceinline__ float bcast_lane<float>(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-template <>
-__device__ __forceinline__ double bcast_lane<double>(double v, int l) {
-  long long x = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), l);
-  int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-constexpr int NB = 32;     // factorization block (diagonal tile) size
-constexpr int TT = 64;     // trailing-update tile edge
-
-}  // namespace
-
-// One workgroup (256 threads) per band matrix; right-looking blocked
-// algorithm: Cholesky of the NB x NB diagonal tile by one wave in registers,
-// triangular solve of the rows below it that lie in the band, then the
-// symmetric rank-NB update of the trailing band window in 64 x 64 tiles.
-template <typename T>
-__global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t nsub,
-                                                            T* __restrict__ W, int32_t* __restrict__ fail) {
-  __shared__ T sL[NB][NB + 1];
-  __shared__ T sR[TT][NB + 1];
-  __shared__ T sC[TT][NB + 1];
-  __shared__ int s_fail;
-  const int64_t p = blockIdx.x;
-  if (p >= nsub) return;
-  const SubDev s = subs[p];
-  T* A = W + s.band_off;
-  const int b = s.b, Wb = s.Wb, n = s.npad;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_fail = 0;
-  __syncthreads();
-  auto at = [&](int r, int c) -> T& { return A[(int64_t)r * Wb + (c - r + b)]; };
-
-  for (int J = 0; J < n; J += NB) {
-    const int jb = (n - J) < NB ? (n - J) : NB;
-    // ---- 1. diagonal tile by wave 0, lane = row ----
-    if (tid < 64) {
-      const int i = tid;
-      T a[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) a[j] = (i < jb && j <= i && (i - j) <= b) ? at(J + i, J + j) : T(0);
-      bool bad = false;
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        if (k < jb) {
-          T dkk = bcast_lane(a[k], k);
-          if (!(dkk > T(0))) {
-            bad = true;
-            dkk = T(1);
-          }
-          T lkk = sqrt(dkk);
-          if (i == k) a[k] = lkk;
-          if (i > k) a[k] = a[k] / lkk;
-#pragma unroll
-          for (int j = k + 1; j < NB; ++j) {
-            T ljk = bcast_lane(a[k], j);
-            if (i >= j && j < jb) a[j] -= a[k] * ljk;
-          }
-        }
-      }
-      if (bad && i == 0) s_fail = 1;
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (i < jb && j <= i && (i - j) <= b) at(J + i, J + j) = a[j];
-        if (i < NB) sL[i][j] = a[j];
-      }
-    }
-    __syncthreads();
-    const int rbeg = J + jb;
-    int rend = J + jb + b;        // rows r with r - b <= J + jb - 1
-    if (rend > n) rend = n;
-    // ---- 2. rows below: x := x L_JJ^{-T} ----
-    for (int r = rbeg + tid; r < rend; r += blockDim.x) {
-      T x[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = (j < jb && r - (J + j) <= b) ? at(r, J + j) : T(0);
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < jb) {
-          T v = x[j];
-#pragma unroll
-          for (int k = 0; k < j; ++k) v -= x[k] * sL[j][k];
-          x[j] = v / sL[j][j];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-        if (j < jb && r - (J + j) <= b) at(r, J + j) = x[j];
-    }
-    __syncthreads();
-    // ---- 3. trailing update of the band window ----
-    for (int RT = rbeg; RT < rend; RT += TT) {
-      for (int CT = rbeg; CT <= RT; CT += TT) {
-        if (RT - (CT + TT - 1) > b) continue;
-        for (int q = tid; q < TT * NB; q += blockDim.x) {
-          int i = q / NB, k = q % NB;
-          int r = RT + i, c = CT + i;
-          sR[i][k] = (k < jb && r < rend && r - (J + k) <= b) ? at(r, J + k) : T(0);
-          sC[i][k] = (k < jb && c < rend && c - (J + k) <= b) ? at(c, J + k) : T(0);
-        }
-        __syncthreads();
-        const int ty = tid / 16, tx = tid % 16;
-        T acc[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-        for (int k = 0; k < NB; ++k) {
-          T ra[4], cb[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) ra[u] = sR[ty * 4 + u][k];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) cb[v] = sC[tx + 16 * v][k];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += ra[u] * cb[v];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            int r = RT + ty * 4 + u, c = CT + tx + 16 * v;
-            if (r < rend && c <= r && r - c <= b) at(r, c) -= acc[u][v];
-          }
-        __syncthreads();
-      }
-    }
-  }
-  if (tid == 0 && s_fail) atomicOr(fail, 1);
-}
-
-template <typename T>
-void launch_band_cholesky(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, hipStream_t st) {
-  band_cholesky_kernel<T><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, fail);
-}
-template void launch_band_cholesky<double>(const SubDev*, int64_t, double*, int32_t*, hipStream_t);
-template void launch_band_cholesky<float>(const SubDev*, int64_t, float*, int32_t*, hipStream_t);
 
 template <typename T>
 __global__ void convert_band_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {

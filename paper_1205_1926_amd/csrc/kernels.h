@@ -37,8 +37,10 @@ void launch_regularize(const SubDev* subs, int64_t nsub, const double* QQt, doub
 
 // ---- factorization -------------------------------------------------------
 // In-place band Cholesky of every subdomain's row-band matrix (type T).
+// bmax: largest half bandwidth; nb: block columns (0 = largest that fits LDS).
 template <typename T>
-void launch_band_cholesky(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, hipStream_t st);
+int launch_band_cholesky(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, int bmax, int nb, hipStream_t st);
+int band_cholesky_nb(int bmax, size_t elem);
 // Convert the FP64 row-band K_reg into the factor work buffer of type T.
 template <typename T>
 void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st);

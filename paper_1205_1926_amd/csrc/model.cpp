@@ -130,6 +130,9 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
         int ord[3] = {0, 1, 2};
         std::stable_sort(ord, ord + 3, [&](int x, int y) { return s.N[x] < s.N[y]; });
         for (int a = 0; a < 3; ++a) s.perm[a] = ord[a];
+        s.fs[ord[0]] = 1;
+        s.fs[ord[1]] = s.N[ord[0]];
+        s.fs[ord[2]] = s.N[ord[0]] * s.N[ord[1]];
         int64_t nn = (int64_t)s.N[0] * s.N[1] * s.N[2];
         s.ndof = (int32_t)(3 * nn);
         s.npad = (s.ndof + kPadRows - 1) / kPadRows * kPadRows;

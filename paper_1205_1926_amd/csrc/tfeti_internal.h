@@ -19,6 +19,7 @@ struct SubDev {
   int32_t n[3];        // elements per local axis (x, y, z)
   int32_t N[3];        // nodes per local axis
   int32_t perm[3];     // factor ordering: perm[0] is the fastest axis
+  int32_t fs[3];       // factor node stride of each local axis (x, y, z)
   int32_t ndof;        // 3 * nodes
   int32_t npad;        // ndof rounded up to kPadRows
   int32_t b;           // half bandwidth in the factor ordering
@@ -26,7 +27,7 @@ struct SubDev {
   int32_t bo;          // off-diagonal panel width (b rounded up to 4)
   int32_t n_iface;     // B-touched local DOFs
   int32_t n_elem;
-  int32_t pad0;
+  int32_t spare;
   int64_t dof_off;     // torn DOF offset
   int64_t elem_off;    // first element (global index)
   int64_t band_off;    // offset of the row-band matrices (entries)
@@ -38,16 +39,14 @@ struct SubDev {
 };
 
 // Factor index of local DOF (natural order a = i + Ni (j + Nj k), comp c).
+// (fixed-index field accesses only, so device code keeps the struct in registers)
 __host__ __device__ inline int32_t factor_index(const SubDev& s, int32_t ldof) {
   int32_t a = ldof / 3, c = ldof - 3 * a;
-  int32_t ijk[3];
-  ijk[0] = a % s.N[0];
+  int32_t i = a % s.N[0];
   int32_t t = a / s.N[0];
-  ijk[1] = t % s.N[1];
-  ijk[2] = t / s.N[1];
-  int32_t p0 = s.perm[0], p1 = s.perm[1], p2 = s.perm[2];
-  int32_t fnode = ijk[p0] + s.N[p0] * (ijk[p1] + s.N[p1] * ijk[p2]);
-  return 3 * fnode + c;
+  int32_t j = t % s.N[1];
+  int32_t k = t / s.N[1];
+  return 3 * (i * s.fs[0] + j * s.fs[1] + k * s.fs[2]) + c;
 }
 
 // Panel geometry: entries of one layout for tile TS, vector width V.
