@@ -76,6 +76,8 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=1, help="replay the PCGP iteration from a HIP graph")
+    ap.add_argument("--refine-eps", type=float, default=0.0, help="FP32 mode: inner PCGP tolerance")
     ap.add_argument("--fapply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -92,7 +94,7 @@ def main() -> int:
     w = W.config(args.config, load_seed=0)
     log(f"setup {w.name} precision={args.precision}")
     t0 = time.perf_counter()
-    g = GpuSolver(w, precision=args.precision, tile=args.tile)
+    g = GpuSolver(w, precision=args.precision, tile=args.tile, use_graph=args.graph, refine_eps=args.refine_eps)
     torch.cuda.synchronize()
     sz = g.sizes
     log(f"setup done in {time.perf_counter() - t0:.1f} s: {sz['n_sub']} subdomains, n={sz['n_torn']}, "
@@ -151,7 +153,9 @@ def main() -> int:
 
     fbytes = 8 if args.precision == "fp64" else 4
     alg_bytes = 2 * sz["skyline_entries"] * fbytes
-    mean_kernel_s = (k_ms / max(k_cnt, 1)) / 1e3
+    if k_cnt == 0:
+        raise SystemExit("no F-apply kernel was timed inside the timed region")
+    mean_kernel_s = (k_ms / k_cnt) / 1e3
     achieved = alg_bytes / mean_kernel_s / 1e9
     iso_kernel_s = (iso_ms / max(iso_cnt, 1)) / 1e3
     log(f"timed: {fapplies} F-applies in {elapsed:.3f} s; solve kernel mean {mean_kernel_s * 1e3:.3f} ms "
@@ -180,6 +184,7 @@ def main() -> int:
                                f"{sz['n_torn']} torn DOF, {sz['m']} multipliers, clamped bottom, top traction "
                                f"(compression + shear), load ramp over {w.steps} steps",
                    "precision": args.precision, "tile": sz["tile"], "preconditioner": "lumped",
+                   "graph": bool(args.graph), "graph_active": g.graph_active(),
                    "eps_pcg": w.eps_pcg, "eps_newton": w.eps_newton},
         "newton_step_ms": elapsed / args.steps * 1e3,
         "pcg_iters": [r["pcg_iters"] for r in reps],

@@ -222,6 +222,10 @@ int tfeti_get_lambda(const tfeti_handle* h, double* lambda);
 int tfeti_set_timing(tfeti_handle* h, int on);
 int tfeti_get_timing(tfeti_handle* h, double* ms_host, int64_t* count_host);
 
+/* Graph replay state of the PCGP iteration: 0 not captured (yet or option
+ * off), 1 replaying a captured graph, 2 capture failed (eager launches). */
+int tfeti_graph_status(const tfeti_handle* h);
+
 /* Host-only (no device work): build the model of prob and report its sizes
  * (factor_bytes and precision are not set) and, when the pointers are not
  * NULL, B in CSR like tfeti_get_B_host (host buffers of m+1, nnz, nnz).  Lets

@@ -49,8 +49,10 @@ struct tfeti_handle {
   // matrices
   double* d_band = nullptr;     // K_reg (FP64 row-band)
   void* d_work = nullptr;       // factor work (row-band, factor precision)
-  void* d_F = nullptr;          // forward panels
-  void* d_B = nullptr;          // backward panels
+  void* d_F = nullptr;          // forward panels (factor precision)
+  void* d_B = nullptr;          // backward panels (factor precision)
+  double* d_F64 = nullptr;      // FP32 mode: FP64 panels of the same factor (outer refinement)
+  double* d_B64 = nullptr;
   // state
   double *d_sigma = nullptr, *d_kappa = nullptr, *d_dsigma = nullptr, *d_dkappa = nullptr;
   uint8_t* d_plastic = nullptr;
@@ -58,7 +60,8 @@ struct tfeti_handle {
          *d_delta = nullptr;
   // PCGP work
   double *d_lam = nullptr, *d_lam_im = nullptr, *d_lam_ker = nullptr, *d_r = nullptr, *d_w = nullptr,
-         *d_z = nullptr, *d_y = nullptr, *d_p = nullptr, *d_q = nullptr, *d_d = nullptr, *d_lam_prev = nullptr;
+         *d_z = nullptr, *d_y = nullptr, *d_p = nullptr, *d_q = nullptr, *d_d = nullptr, *d_lam_prev = nullptr,
+         *d_dt = nullptr, *d_lam_acc = nullptr;
   double* d_iface = nullptr;
   double *d_c = nullptr, *d_a = nullptr;
   double* d_partials = nullptr;
@@ -78,6 +81,14 @@ struct tfeti_handle {
   int64_t t_count = 0;
   std::vector<hipEvent_t> ev;   // pairs (start, stop) around F-apply solve kernels
   int ev_used = 0;
+  int last_f64 = 0;             // FP64 F-applies of the last solve
+  // graph replay of the PCGP iteration batch
+  hipStream_t gs = nullptr;     // internal stream for graph capture and replay
+  hipEvent_t sync_ev = nullptr;
+  hipGraphExec_t gexec = nullptr;                          // `batch` whole iterations
+  hipGraphExec_t gexec_a = nullptr, gexec_b = nullptr;     // split iteration (timed solves)
+  bool graph_failed = false, graph_split = false;
+  int graph_batch = 0;
 };
 
 namespace {
@@ -132,14 +143,14 @@ double read_scalar(tfeti_handle* h, const double* d) {
 
 // ------------------------------------------------------------------ operators
 void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double lam_sign, double* out_iface,
-            double* out_full, const double* alpha, const int32_t* done) {
-  if (h->prec == TFETI_PREC_FP64) {
+            double* out_full, const double* alpha, const int32_t* done, bool use64 = false) {
+  if (h->prec == TFETI_PREC_FP64 || use64) {
     KsolveArgs<double> a{};
     a.subs = h->d_subs;
     a.order = h->d_order;
     a.nsub = h->M.n_sub;
-    a.Fp = (const double*)h->d_F;
-    a.Bp = (const double*)h->d_B;
+    a.Fp = h->prec == TFETI_PREC_FP64 ? (const double*)h->d_F : h->d_F64;
+    a.Bp = h->prec == TFETI_PREC_FP64 ? (const double*)h->d_B : h->d_B64;
     a.in_full = in_full;
     a.lam = lam;
     a.lam_sign = lam_sign;
@@ -179,11 +190,13 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
 }
 
 // q = F lam; optional partial sums of q.dotv
+// timed: bracket the solve kernel with timing events (loop F-applies only);
+// use64: in FP32 mode apply the FP64 factor instead.
 void fapply(tfeti_handle* h, const double* lam, double* q, const double* dotv, double* partials,
-            const int32_t* done) {
-  const bool rec = h->timing && 2 * h->ev_used + 1 < (int)h->ev.size();
+            const int32_t* done, bool timed = false, bool use64 = false) {
+  const bool rec = timed && h->timing && 2 * h->ev_used + 1 < (int)h->ev.size();
   if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], h->st);
-  ksolve(h, nullptr, lam, 1.0, h->d_iface, nullptr, nullptr, done);
+  ksolve(h, nullptr, lam, 1.0, h->d_iface, nullptr, nullptr, done, use64);
   if (rec) {
     (void)hipEventRecord(h->ev[2 * h->ev_used + 1], h->st);
     h->ev_used++;
@@ -222,32 +235,209 @@ void precondition(tfeti_handle* h, const double* w, double* z, const int32_t* do
 int nred(tfeti_handle* h) { return reduction_blocks(h->M.m); }
 
 // ------------------------------------------------------------------ PCGP
+// One PCGP iteration (Algorithm 3 loop body) on r, lambda_Ker, p with the
+// scalars in d_S; every kernel returns at once when S->done is set.
+// Part A: projection, preconditioner, re-projection, beta and the new
+// direction p.
+void enqueue_iteration_a(tfeti_handle* h, const int32_t* done) {
+  const int64_t m = h->M.m;
+  project(h, h->d_r, h->d_w, h->d_partials, done);
+  launch_finalize(FIN_WW, h->d_S, h->d_partials, nred(h), h->st);
+  if (h->opt.preconditioner == 1) {
+    precondition(h, h->d_w, h->d_z, done);
+    project(h, h->d_z, h->d_y, nullptr, done);
+  } else {
+    project(h, h->d_w, h->d_y, nullptr, done);
+  }
+  launch_dot_partials(h->d_y, h->d_w, m, h->d_partials, done, h->st);
+  launch_finalize(FIN_YW, h->d_S, h->d_partials, nred(h), h->st);
+  launch_update_p(m, h->d_y, h->d_p, h->d_S, h->st);
+}
+
+// Part B (after the subdomain solves of q = F p): the B gather fused with
+// p.q, gamma, and the updates of lambda and r.
+void enqueue_iteration_b(tfeti_handle* h, const int32_t* done) {
+  const int64_t m = h->M.m;
+  launch_gather(h->dm, h->d_iface, h->d_q, h->d_p, h->d_partials, done, h->st);
+  launch_finalize(FIN_PQ, h->d_S, h->d_partials, nred(h), h->st);
+  launch_update_lr(m, h->d_p, h->d_q, h->d_lam_ker, h->d_r, h->d_S, h->st);
+}
+
+// The F-apply's subdomain-solve kernel of one iteration (timed if asked).
+void enqueue_iteration_solve(tfeti_handle* h, const int32_t* done, bool timed) {
+  const bool rec = timed && h->timing && 2 * h->ev_used + 1 < (int)h->ev.size();
+  if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], h->st);
+  ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done);
+  if (rec) {
+    (void)hipEventRecord(h->ev[2 * h->ev_used + 1], h->st);
+    h->ev_used++;
+  }
+}
+
+void enqueue_iteration(tfeti_handle* h, const int32_t* done) {
+  enqueue_iteration_a(h, done);
+  enqueue_iteration_solve(h, done, true);
+  enqueue_iteration_b(h, done);
+}
+
+bool capture_one(tfeti_handle* h, hipGraphExec_t* exec, int batch, int part) {
+  hipStream_t saved = h->st;
+  h->st = h->gs;
+  bool ok = hipStreamBeginCapture(h->gs, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (ok) {
+    const int32_t* done = &h->d_S->done;
+    for (int k = 0; k < batch; ++k) {
+      if (part == 0 || part == 1) enqueue_iteration_a(h, done);
+      if (part == 0) enqueue_iteration_solve(h, done, false);
+      if (part == 0 || part == 2) enqueue_iteration_b(h, done);
+    }
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->gs, &g);
+  ok = ok && e == hipSuccess && g != nullptr;
+  h->st = saved;
+  if (ok) ok = hipGraphInstantiate(exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  return ok;
+}
+
+void drop_graphs(tfeti_handle* h) {
+  if (h->gs) (void)hipStreamSynchronize(h->gs);
+  for (hipGraphExec_t* e : {&h->gexec, &h->gexec_a, &h->gexec_b})
+    if (*e) {
+      (void)hipGraphExecDestroy(*e);
+      *e = nullptr;
+    }
+}
+
+// Capture the iteration on the internal stream: `batch` whole iterations in
+// one graph, or (when the solve kernel is timed) one graph for part A and one
+// for part B with the solve kernel launched between them with its events.
+bool capture_graph(tfeti_handle* h, int batch) {
+  drop_graphs(h);
+  bool ok;
+  if (h->timing) {
+    ok = capture_one(h, &h->gexec_a, 1, 1) && capture_one(h, &h->gexec_b, 1, 2);
+    h->graph_split = true;
+  } else {
+    ok = capture_one(h, &h->gexec, batch, 0);
+    h->graph_split = false;
+  }
+  if (!ok) {
+    drop_graphs(h);
+    h->graph_failed = true;
+  }
+  h->graph_batch = batch;
+  return ok;
+}
+
+// Run PCGP iterations from the current r, lambda_Ker (p = 0) until
+// ||P r|| <= eps * S.r_ref or maxit.  Returns the final scalars.
+int pcg_loop(tfeti_handle* h, double eps, int maxit, PcgScalars* out) {
+  const int64_t m = h->M.m;
+  // reset the iteration scalars, keep r_ref
+  {
+    PcgScalars S0{};
+    HIPCHK(hipMemcpyAsync(&S0, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    double rref = S0.r_ref;
+    S0 = PcgScalars{};
+    S0.r_ref = rref;
+    S0.eps = eps;
+    S0.maxit = maxit;
+    HIPCHK(hipMemcpyAsync(h->d_S, &S0, sizeof(PcgScalars), hipMemcpyHostToDevice, h->st));
+  }
+  launch_axpby(m, 0.0, nullptr, 0.0, h->d_p, h->st);
+  harvest_timing(h, 1 << 30);
+  const int batch = h->opt.check_every > 0 ? h->opt.check_every : 8;
+  bool graph = h->opt.use_graph && !h->graph_failed;
+  if (graph) {
+    const bool have = h->timing ? (h->gexec_a && h->gexec_b && h->graph_split)
+                                : (h->gexec && !h->graph_split && h->graph_batch == batch);
+    if (!have) graph = capture_graph(h, batch);
+  }
+  if (graph) {
+    HIPCHK(hipEventRecord(h->sync_ev, h->st));
+    HIPCHK(hipStreamWaitEvent(h->gs, h->sync_ev, 0));
+  }
+  hipStream_t ls = graph ? h->gs : h->st;
+  const int32_t* done = &h->d_S->done;
+  PcgScalars Sh{};
+  int iters_before = 0;
+  for (;;) {
+    if (graph && !h->graph_split) {
+      HIPCHK(hipGraphLaunch(h->gexec, h->gs));
+    } else if (graph) {
+      hipStream_t saved = h->st;
+      h->st = h->gs;
+      for (int k = 0; k < batch; ++k) {
+        (void)hipGraphLaunch(h->gexec_a, h->gs);
+        enqueue_iteration_solve(h, done, true);
+        (void)hipGraphLaunch(h->gexec_b, h->gs);
+      }
+      h->st = saved;
+      HIPCHK(hipGetLastError());
+    } else {
+      for (int k = 0; k < batch; ++k) enqueue_iteration(h, done);
+    }
+    HIPCHK(hipMemcpyAsync(&Sh, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, ls));
+    HIPCHK(hipStreamSynchronize(ls));
+    harvest_timing(h, Sh.iters - iters_before);
+    iters_before = Sh.iters;
+    if (Sh.done) break;
+  }
+  if (graph) {
+    HIPCHK(hipEventRecord(h->sync_ev, h->gs));
+    HIPCHK(hipStreamWaitEvent(h->st, h->sync_ev, 0));
+  }
+  *out = Sh;
+  if (Sh.done == 3) return fail(h, TFETI_E_NOT_SPD, "PCGP produced a non-finite residual");
+  return Sh.done == 2 ? TFETI_W_PCG_MAXIT : TFETI_OK;
+}
+
+// ||P x|| into S.r_ref (the reference of the next loop); also out = P x.
+void set_rref(tfeti_handle* h, const double* x, double* out) {
+  project(h, x, out, h->d_partials, nullptr);
+  launch_finalize(FIN_RREF, h->d_S, h->d_partials, nred(h), h->st);
+}
+
+double read_rref(tfeti_handle* h) {
+  PcgScalars S{};
+  (void)hipMemcpyAsync(&S, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st);
+  (void)hipStreamSynchronize(h->st);
+  return S.r_ref;
+}
+
+// Algorithm 3.  In FP32 mode the loop runs on the FP32 operator F32 and an
+// outer FP64 refinement wraps it: rho = P(d - F64 lambda), inner PCGP on
+// P F32 delta = rho to a relative tolerance refine_eps, lambda += delta,
+// until ||rho|| <= eps_pcg ||P(d - F64 lambda_Im)||.
 int pcg_solve(tfeti_handle* h, const double* f, const double* guess, double* lam_out, double* u_out,
               tfeti_pcg_report* rep) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t m = h->M.m;
+  const bool mixed = h->prec == TFETI_PREC_FP32;
   int status = TFETI_OK;
   // lambda_Im = G^T (G G^T)^{-1} R^T f
   launch_rt_apply(h->dm, f, h->d_c, h->st);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, nullptr, h->st);
   launch_gt_apply(h->dm, nullptr, h->d_a, -1.0, h->d_lam_im, nullptr, nullptr, h->st);
-  // d = B K^+ f
-  ksolve(h, f, nullptr, 0.0, h->d_iface, nullptr, nullptr, nullptr);
+  // d = B K^+ f and d~ = d - F lambda_Im (FP64 operator)
+  ksolve(h, f, nullptr, 0.0, h->d_iface, nullptr, nullptr, nullptr, true);
   launch_gather(h->dm, h->d_iface, h->d_d, nullptr, nullptr, nullptr, h->st);
-  // r = d - F lambda_Im
-  fapply(h, h->d_lam_im, h->d_q, nullptr, nullptr, nullptr);
-  launch_copy(m, h->d_d, h->d_r, h->st);
-  launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
-  // scalars
-  PcgScalars S0{};
-  S0.eps = h->opt.eps_pcg;
-  S0.maxit = h->opt.max_pcg;
-  HIPCHK(hipMemcpyAsync(h->d_S, &S0, sizeof(PcgScalars), hipMemcpyHostToDevice, h->st));
-  // r_ref = ||P r||
-  project(h, h->d_r, h->d_w, h->d_partials, nullptr);
-  launch_finalize(FIN_RREF, h->d_S, h->d_partials, nred(h), h->st);
-  harvest_timing(h, 1 << 30);
-  int fapplies = 1;
+  fapply(h, h->d_lam_im, h->d_q, nullptr, nullptr, nullptr, false, true);
+  launch_copy(m, h->d_d, h->d_dt, h->st);
+  launch_axpby(m, -1.0, h->d_q, 1.0, h->d_dt, h->st);
+  int fapplies = 1, fapplies64 = 1;
+  // r_ref = ||P d~||
+  {
+    PcgScalars S0{};
+    HIPCHK(hipMemcpyAsync(h->d_S, &S0, sizeof(PcgScalars), hipMemcpyHostToDevice, h->st));
+  }
+  set_rref(h, h->d_dt, h->d_w);
+  const double r_ref = read_rref(h);
+  // warm start: lambda_Ker = P guess
   bool rejected = false;
   if (guess) {
     launch_check_finite(m, guess, h->d_S, h->st);
@@ -257,70 +447,90 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, double* lam
     if (Sh.nonfinite) {
       rejected = true;
       guess = nullptr;
-      int zero = 0;
-      HIPCHK(hipMemcpyAsync(&h->d_S->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice, h->st));
     }
   }
+  double* lam_acc = mixed ? h->d_lam_acc : h->d_lam_ker;
   if (guess) {
-    project(h, guess, h->d_lam_ker, nullptr, nullptr);
-    fapply(h, h->d_lam_ker, h->d_q, nullptr, nullptr, nullptr);
-    launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
-    fapplies++;
+    project(h, guess, lam_acc, nullptr, nullptr);
   } else {
-    HIPCHK(hipMemsetAsync(h->d_lam_ker, 0, m * sizeof(double), h->st));
+    launch_axpby(m, 0.0, nullptr, 0.0, lam_acc, h->st);
   }
-  HIPCHK(hipMemsetAsync(h->d_p, 0, m * sizeof(double), h->st));
-  int32_t* done = &h->d_S->done;
-  const int batch = h->opt.check_every > 0 ? h->opt.check_every : 8;
   PcgScalars Sh{};
-  int iters_before = 0;          // iterations completed before the current batch
-  int extra = guess ? 1 : 0;     // the warm-start F-apply is recorded in the first batch
-  for (;;) {
-    for (int k = 0; k < batch; ++k) {
-      project(h, h->d_r, h->d_w, h->d_partials, done);
-      launch_finalize(FIN_WW, h->d_S, h->d_partials, nred(h), h->st);
-      if (h->opt.preconditioner == 1) {
-        precondition(h, h->d_w, h->d_z, done);
-        project(h, h->d_z, h->d_y, nullptr, done);
-      } else {
-        project(h, h->d_w, h->d_y, nullptr, done);
-      }
-      launch_dot_partials(h->d_y, h->d_w, m, h->d_partials, done, h->st);
-      launch_finalize(FIN_YW, h->d_S, h->d_partials, nred(h), h->st);
-      launch_update_p(m, h->d_y, h->d_p, h->d_S, h->st);
-      fapply(h, h->d_p, h->d_q, h->d_p, h->d_partials, done);
-      launch_finalize(FIN_PQ, h->d_S, h->d_partials, nred(h), h->st);
-      launch_update_lr(m, h->d_p, h->d_q, h->d_lam_ker, h->d_r, h->d_S, h->st);
+  int total_iters = 0, outer = 0;
+  bool converged = false;
+  double r_final = r_ref;
+  if (!mixed) {
+    // r = d~ - F lambda_Ker
+    launch_copy(m, h->d_dt, h->d_r, h->st);
+    if (guess) {
+      fapply(h, h->d_lam_ker, h->d_q, nullptr, nullptr, nullptr, false, true);
+      launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
+      fapplies++;
+      fapplies64++;
     }
-    HIPCHK(hipMemcpyAsync(&Sh, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    if (Sh.done) break;
-    harvest_timing(h, 1 << 30);
-    iters_before = Sh.iters;
-    extra = 0;
+    set_rref(h, h->d_dt, h->d_w);  // S.r_ref = ||P d~|| for the stopping test
+    int st = pcg_loop(h, h->opt.eps_pcg, h->opt.max_pcg, &Sh);
+    if (st < 0) return st;
+    status = st;
+    total_iters = Sh.iters;
+    fapplies += Sh.iters;
+    fapplies64 += Sh.iters;
+    converged = Sh.done == 1;
+    r_final = Sh.rr;
+  } else {
+    const double eps_in = h->opt.refine_eps > 0 ? h->opt.refine_eps : 1e-5;
+    const int max_outer = 50;
+    for (;;) {
+      // outer residual r = d~ - F64 lambda_acc (FP64), rho = P r
+      launch_copy(m, h->d_dt, h->d_r, h->st);
+      if (outer > 0 || guess) {
+        fapply(h, lam_acc, h->d_q, nullptr, nullptr, nullptr, false, true);
+        launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
+        fapplies++;
+        fapplies64++;
+      }
+      set_rref(h, h->d_r, h->d_w);
+      const double nrho = read_rref(h);
+      r_final = nrho;
+      if (!(nrho == nrho)) return fail(h, TFETI_E_NOT_SPD, "outer residual is not finite");
+      if (nrho <= h->opt.eps_pcg * r_ref || r_ref == 0.0) {
+        converged = true;
+        break;
+      }
+      if (outer >= max_outer || total_iters >= h->opt.max_pcg) {
+        status = TFETI_W_PCG_MAXIT;
+        break;
+      }
+      // inner PCGP on P F32 delta = rho from delta = 0
+      launch_axpby(m, 0.0, nullptr, 0.0, h->d_lam_ker, h->st);
+      int st = pcg_loop(h, eps_in, h->opt.max_pcg - total_iters, &Sh);
+      if (st < 0) return st;
+      total_iters += Sh.iters;
+      fapplies += Sh.iters;
+      launch_axpby(m, 1.0, h->d_lam_ker, 1.0, lam_acc, h->st);
+      ++outer;
+    }
   }
-  // only the F-applies of iterations that ran before convergence did work
-  harvest_timing(h, Sh.iters - iters_before + extra);
-  fapplies += Sh.iters;
-  if (Sh.done == 2) status = TFETI_W_PCG_MAXIT;
-  if (Sh.done == 3) return fail(h, TFETI_E_NOT_SPD, "PCGP produced a non-finite residual");
   // lambda = lambda_Im + lambda_Ker
   launch_copy(m, h->d_lam_im, h->d_lam, h->st);
-  launch_axpby(m, 1.0, h->d_lam_ker, 1.0, h->d_lam, h->st);
+  launch_axpby(m, 1.0, lam_acc, 1.0, h->d_lam, h->st);
   if (lam_out && lam_out != h->d_lam) launch_copy(m, h->d_lam, lam_out, h->st);
-  // alpha = -(G G^T)^{-1} G r
+  // alpha = -(G G^T)^{-1} G r with r = d - F lambda (the last FP64 residual
+  // in FP32 mode; the recursively updated PCGP residual in FP64 mode)
   launch_g_apply(h->dm, h->d_r, h->d_c, nullptr, h->st);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, -1.0, nullptr, h->st);
-  // u = K^+ (f - B^T lambda) + R alpha
-  if (u_out) ksolve(h, f, h->d_lam, -1.0, nullptr, u_out, h->d_a, nullptr);
+  // u = K^+ (f - B^T lambda) + R alpha (FP64 operator)
+  if (u_out) ksolve(h, f, h->d_lam, -1.0, nullptr, u_out, h->d_a, nullptr, true);
   HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipGetLastError());
+  h->last_f64 = fapplies64;
   if (rep) {
-    rep->iters = Sh.iters;
+    rep->iters = total_iters;
     rep->fapplies = fapplies;
-    rep->converged = Sh.done == 1;
-    rep->outer = 0;
-    rep->r_ref = Sh.r_ref;
-    rep->r_final = Sh.rr;
+    rep->converged = converged ? 1 : 0;
+    rep->outer = outer;
+    rep->r_ref = r_ref;
+    rep->r_final = r_final;
     rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   if (rejected && status == TFETI_OK) status = TFETI_W_WARMSTART_REJECTED;
@@ -371,16 +581,16 @@ int factorize(tfeti_handle* h) {
   const HostModel& M = h->M;
   launch_regularize(h->d_subs, M.n_sub, h->d_QQt, h->d_band, h->st);
   HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
+  launch_convert_band<double>(h->d_band, (double*)h->d_work, M.band_entries, h->st);
+  launch_band_cholesky<double>(h->d_subs, M.n_sub, (double*)h->d_work, h->d_fail, h->bmax, h->chol_nb, h->st);
   if (h->prec == TFETI_PREC_FP64) {
-    launch_convert_band<double>(h->d_band, (double*)h->d_work, M.band_entries, h->st);
-    launch_band_cholesky<double>(h->d_subs, M.n_sub, (double*)h->d_work, h->d_fail, h->bmax, h->chol_nb, h->st);
-    launch_pack_panels<double>(h->d_subs, M.n_sub, (const double*)h->d_work, (double*)h->d_F, (double*)h->d_B,
-                               h->TS, h->st);
+    launch_pack_panels<double, double>(h->d_subs, M.n_sub, (const double*)h->d_work, (double*)h->d_F,
+                                       (double*)h->d_B, h->TS, h->st);
   } else {
-    launch_convert_band<float>(h->d_band, (float*)h->d_work, M.band_entries, h->st);
-    launch_band_cholesky<float>(h->d_subs, M.n_sub, (float*)h->d_work, h->d_fail, h->bmax, h->chol_nb, h->st);
-    launch_pack_panels<float>(h->d_subs, M.n_sub, (const float*)h->d_work, (float*)h->d_F, (float*)h->d_B, h->TS,
-                              h->st);
+    launch_pack_panels<double, double>(h->d_subs, M.n_sub, (const double*)h->d_work, h->d_F64, h->d_B64, h->TS,
+                                       h->st);
+    launch_pack_panels<double, float>(h->d_subs, M.n_sub, (const double*)h->d_work, (float*)h->d_F,
+                                      (float*)h->d_B, h->TS, h->st);
   }
   int32_t bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
@@ -491,11 +701,17 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(upload(h, &h->d_dN, dN));
   RC(upload(h, &h->d_f1, M.f1));
   // matrices
+  // the factorization always runs in FP64; FP32 mode packs the factor into
+  // FP32 panels (inner iterations) and keeps FP64 panels (outer refinement)
   const size_t fsz = h->prec == TFETI_PREC_FP64 ? sizeof(double) : sizeof(float);
   RC(dalloc(h, &h->d_band, M.band_entries));
+  if (h->prec == TFETI_PREC_FP32) {
+    RC(dalloc(h, &h->d_F64, std::max<int64_t>(h->panel_entries, 1)));
+    RC(dalloc(h, &h->d_B64, std::max<int64_t>(h->panel_entries, 1)));
+  }
   {
     void* q = nullptr;
-    if (hipMalloc(&q, (size_t)M.band_entries * fsz) != hipSuccess) return fail(h, TFETI_E_OOM, "factor work");
+    if (hipMalloc(&q, (size_t)M.band_entries * sizeof(double)) != hipSuccess) return fail(h, TFETI_E_OOM, "factor work");
     h->allocs.push_back(q);
     h->d_work = q;
     if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_entries, 1) * fsz) != hipSuccess)
@@ -519,8 +735,8 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_fint, M.n_torn));
   RC(dalloc(h, &h->d_f, M.n_torn));
   RC(dalloc(h, &h->d_delta, M.n_torn));
-  double** mv[] = {&h->d_lam, &h->d_lam_im, &h->d_lam_ker, &h->d_r, &h->d_w, &h->d_z,
-                   &h->d_y,   &h->d_p,      &h->d_q,       &h->d_d, &h->d_lam_prev};
+  double** mv[] = {&h->d_lam, &h->d_lam_im, &h->d_lam_ker, &h->d_r,        &h->d_w,  &h->d_z,      &h->d_y,
+                   &h->d_p,   &h->d_q,      &h->d_d,       &h->d_lam_prev, &h->d_dt, &h->d_lam_acc};
   for (double** v : mv) RC(dalloc(h, v, M.m));
   RC(dalloc(h, &h->d_iface, M.n_iface));
   RC(dalloc(h, &h->d_c, M.lc_pad));
@@ -584,6 +800,8 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   }
   h->ev.assign(2 * 512, nullptr);
   for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming));
+  if (h->opt.use_graph) HIPCHK(hipStreamCreateWithFlags(&h->gs, hipStreamNonBlocking));
   return TFETI_OK;
 }
 
@@ -591,6 +809,9 @@ void tfeti_destroy(tfeti_handle* h) {
   if (!h) return;
   if (h->st) (void)hipStreamSynchronize(h->st);
   else (void)hipDeviceSynchronize();
+  drop_graphs(h);
+  if (h->gs) (void)hipStreamDestroy(h->gs);
+  if (h->sync_ev) (void)hipEventDestroy(h->sync_ev);
   for (void* p : h->allocs) (void)hipFree(p);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
@@ -745,7 +966,7 @@ int tfeti_factorize(tfeti_handle* h) {
 int tfeti_fapply(tfeti_handle* h, const double* lam, double* q) {
   if (!h || !lam || !q) return TFETI_E_INVALID;
   if (!h->factored) return fail(h, TFETI_E_INVALID, "no factorized operator");
-  fapply(h, lam, q, nullptr, nullptr, nullptr);
+  fapply(h, lam, q, nullptr, nullptr, nullptr, /*timed=*/true);
   if (h->timing && h->ev_used * 2 + 2 >= (int)h->ev.size()) harvest_timing(h, 1 << 30);
   HIPCHK(hipGetLastError());
   return TFETI_OK;
@@ -812,10 +1033,19 @@ int tfeti_get_lambda(const tfeti_handle* hc, double* lam) {
 
 int tfeti_set_timing(tfeti_handle* h, int on) {
   if (!h) return TFETI_E_INVALID;
+  // timed runs replay the split iteration, untimed ones the batched graph
+  if ((on != 0) != h->timing) drop_graphs(h);
   h->timing = on != 0;
   h->t_ms = 0.0;
   h->t_count = 0;
+  h->ev_used = 0;
   return TFETI_OK;
+}
+
+int tfeti_graph_status(const tfeti_handle* h) {
+  if (!h) return TFETI_E_INVALID;
+  if (h->graph_failed) return 2;
+  return (h->gexec || h->gexec_a) ? 1 : 0;
 }
 
 int tfeti_get_timing(tfeti_handle* h, double* ms_host, int64_t* count_host) {

@@ -30,9 +30,9 @@ template void launch_convert_band<float>(const double*, float*, int64_t, hipStre
 // r is stored at ((cc TS) + r) V.  Backward panel of block column I: the
 // inverted diagonal tile rows first, then rows [(I+1) TS, (I+1) TS + w'_I);
 // chunk (rc, c) of V consecutive rows of column c is stored at (rc TS + c) V.
-template <typename T, int TS>
+template <typename TW, typename T, int TS>
 __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restrict__ subs, int64_t nsub,
-                                                          const T* __restrict__ W, T* __restrict__ Fp,
+                                                          const TW* __restrict__ W, T* __restrict__ Fp,
                                                           T* __restrict__ Bp) {
   constexpr int V = 16 / sizeof(T);
   // sD holds the diagonal tile L in its lower triangle and, after the
@@ -43,12 +43,12 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
   const int64_t p = blockIdx.x;
   if (p >= nsub) return;
   const SubDev s = subs[p];
-  const T* A = W + s.band_off;
+  const TW* A = W + s.band_off;
   T* F = Fp + s.panel_off;
   T* Bk = Bp + s.panel_off;
   const int b = s.b, Wb = s.Wb, n = s.npad, nb = n / TS;
   const int tid = threadIdx.x;
-  auto L = [&](int r, int c) -> T { return (c <= r && r - c <= b && c >= 0) ? A[(int64_t)r * Wb + (c - r + b)] : T(0); };
+  auto L = [&](int r, int c) -> T { return (c <= r && r - c <= b && c >= 0) ? (T)A[(int64_t)r * Wb + (c - r + b)] : T(0); };
   int64_t offF = 0, offB = 0;
   for (int I = 0; I < nb; ++I) {
     const int wF = I * TS < s.bo ? I * TS : s.bo;
@@ -97,17 +97,19 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
   }
 }
 
-template <typename T>
-void launch_pack_panels(const SubDev* subs, int64_t nsub, const T* band, T* Fp, T* Bp, int TS, hipStream_t st) {
+template <typename TW, typename T>
+void launch_pack_panels(const SubDev* subs, int64_t nsub, const TW* band, T* Fp, T* Bp, int TS, hipStream_t st) {
   if (TS == 16)
-    pack_panels_kernel<T, 16><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 16><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
   else if (TS == 32)
-    pack_panels_kernel<T, 32><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 32><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
   else
-    pack_panels_kernel<T, 64><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 64><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
 }
-template void launch_pack_panels<double>(const SubDev*, int64_t, const double*, double*, double*, int, hipStream_t);
-template void launch_pack_panels<float>(const SubDev*, int64_t, const float*, float*, float*, int, hipStream_t);
+template void launch_pack_panels<double, double>(const SubDev*, int64_t, const double*, double*, double*, int,
+                                                 hipStream_t);
+template void launch_pack_panels<double, float>(const SubDev*, int64_t, const double*, float*, float*, int,
+                                                hipStream_t);
 
 // Dense inverse of the coarse matrix from its banded Cholesky factor L
 // (row-band, l rows, half bandwidth b): thread j solves L L^T x = e_j and

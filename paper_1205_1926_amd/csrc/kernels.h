@@ -46,8 +46,9 @@ template <typename T>
 void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st);
 // Pack the factors into forward (F) and backward (B) panels with inverted
 // diagonal tiles.
-template <typename T>
-void launch_pack_panels(const SubDev* subs, int64_t nsub, const T* band, T* Fp, T* Bp, int TS, hipStream_t st);
+// (factor in TW, panels in T: FP64 -> FP64 or FP64 -> FP32)
+template <typename TW, typename T>
+void launch_pack_panels(const SubDev* subs, int64_t nsub, const TW* band, T* Fp, T* Bp, int TS, hipStream_t st);
 // Dense inverse of the coarse matrix from its banded Cholesky factor.
 void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st);
 

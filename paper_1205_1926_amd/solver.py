@@ -178,6 +178,10 @@ class GpuSolver:
     def set_timing(self, on: bool):
         self._check(self.lib.tfeti_set_timing(self.h, 1 if on else 0), "set_timing")
 
+    def graph_active(self) -> int:
+        """0 not captured, 1 replaying a HIP graph, 2 capture failed (eager)."""
+        return int(self.lib.tfeti_graph_status(self.h))
+
     def timing(self):
         ms = C.c_double()
         cnt = C.c_int64()

@@ -191,10 +191,67 @@ def test_dual_pcg_warm_start_and_rejection(pair0, dev):
 
 
 def test_fp32_fapply(dev):
+    """FP32 panels of the FP64 factor: single F-applies agree to FP32 level."""
     P = Pair(W.config(0), dev, precision="fp32")
     rng = np.random.default_rng(5)
     lam = rng.standard_normal(P.mesh.m)
     assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 5e-3
+
+
+@pytest.mark.parametrize("name", ["pair0", "pair_plastic", "pair_uneven"])
+def test_fp32_refined_dual_pcg(name, request, dev):
+    """FP32 inner PCGP with FP64 outer dual refinement reaches the FP64
+    solution (displacement bar 1e-6) in a few outer sweeps."""
+    P0 = request.getfixturevalue(name)
+    P = Pair(P0.w, dev, precision="fp32", plastic_step=(name == "pair_plastic"))
+    f = P.mesh.torn_load(1.0) - P.a["fint"]
+    ref = P.tf.solve(f, eps=1e-8)
+    lam, u, rep, rc = P.g.dual_pcg(T(f, dev))
+    assert rep["converged"] == 1 and 1 <= rep["outer"] <= 4
+    assert rel(N(u), ref["u"]) <= 1e-6
+    assert rel(N(lam), ref["lam"]) <= 1e-5
+
+
+def test_graph_replay_matches_eager(dev):
+    """The PCGP iteration replayed from a HIP graph gives bitwise the eager
+    result, solve after solve (several replays, eager work in between)."""
+    from paper_1205_1926_amd import GpuSolver
+    w = W.small_cube(S=(2, 2, 2), n=(3, 3, 3), amp=500.0, shear=100.0)
+    ge = GpuSolver(w, use_graph=0)
+    gg = GpuSolver(w, use_graph=1)
+    gt = GpuSolver(w, use_graph=1)          # split replay with timed solve kernels
+    gt.set_timing(True)
+    du = torch.zeros(ge.sizes["n_torn"], dtype=torch.float64, device=dev)
+    for g in (ge, gg, gt):
+        g.assemble(du)
+        g.factorize()
+    mesh = Mesh(w)
+    rng = np.random.default_rng(9)
+    total = 0
+    for k in range(3):
+        f = T(mesh.torn_load(1.0) * (1 + k) + 0.1 * rng.standard_normal(mesh.n_torn), dev)
+        le, ue, re, _ = ge.dual_pcg(f)
+        lg, ug, rg, _ = gg.dual_pcg(f)
+        lt, ut, rt, _ = gt.dual_pcg(f)
+        assert re["iters"] == rg["iters"] == rt["iters"]
+        assert torch.equal(le, lg) and torch.equal(ue, ug)
+        assert torch.equal(le, lt) and torch.equal(ue, ut)
+        total += re["iters"]
+    assert gg.graph_active() == 1 and gt.graph_active() == 1
+    ms, cnt = gt.timing()
+    assert cnt == total and ms > 0
+
+
+def test_newton_fp32_mode_matches_oracle(dev):
+    from paper_1205_1926_amd import GpuSolver
+    w = W.small_cube(S=(2, 2, 2), n=(3, 3, 3), amp=700.0, shear=150.0, steps=2)
+    o = OracleSolver(w, "tfeti")
+    g = GpuSolver(w, precision="fp32", use_graph=1)
+    for k in range(w.steps):
+        o.load_step()
+        g.load_step()
+        ug = N(g.state()["u"])
+        assert rel(ug[o.untorn], o.u[o.untorn]) <= 1e-6, k
 
 
 @pytest.mark.parametrize("tile", [16, 64])
