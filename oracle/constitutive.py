@@ -25,6 +25,7 @@ import numpy as np
 
 SQRT23 = np.sqrt(2.0 / 3.0)
 SQRT32 = np.sqrt(3.0 / 2.0)
+YIELD_TIE = 1e-12  # relative margin of the elastic/plastic decision at Phi = 0
 
 
 def lame(E: float, nu: float):
@@ -95,7 +96,11 @@ def return_map(sigma_k: np.ndarray, kappa_k: np.ndarray, deps: np.ndarray,
     dev = tau @ Es.T                       # E_sigma tau
     ndev = norm_sigma(dev)
     phi = SQRT32 * ndev - (sigma_y + H * kappa_k)
-    plastic = phi > 0.0                    # Phi <= 0 is elastic
+    # Phi <= 0 is elastic.  A committed plastic point sits on the yield
+    # surface, where rounding leaves Phi = O(1e-16) of either sign; the tie
+    # is taken as elastic up to a relative margin of YIELD_TIE, so that the
+    # tangent at a zero increment is always the elastic one.
+    plastic = phi > YIELD_TIE * (sigma_y + H * kappa_k)
 
     safe = np.where(plastic, ndev, 1.0)
     nbar = dev / safe[:, None]

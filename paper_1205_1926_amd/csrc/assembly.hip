@@ -23,7 +23,10 @@ __device__ __forceinline__ void return_map_point(const MatC& M, const double* si
   double s[6] = {tau[0] - pm, tau[1] - pm, tau[2] - pm, tau[3], tau[4], tau[5]};
   double q = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
   double phi = sqrt(1.5) * q - (M.sy + M.H * kap);
-  if (!(phi > 0.0)) {
+  // a committed plastic point lies on the yield surface up to rounding; the
+  // tie is elastic within a relative margin of 1e-12 of the yield radius, so
+  // the tangent at a zero increment is the elastic one
+  if (!(phi > 1e-12 * (M.sy + M.H * kap))) {
     for (int i = 0; i < 6; ++i) ds[i] = Cde[i];
     *dk = 0.0;
     *plastic = false;
