@@ -87,7 +87,14 @@ typedef struct {
   double eps_newton;            /* Newton relative-residual tolerance           */
   int32_t max_pcg;              /* PCGP iteration cap (default 5000)            */
   int32_t max_newton;           /* Newton iteration cap per load step (50)      */
-  int32_t warm_start;           /* 0 cold; 1 previous Newton iteration's lambda */
+  int32_t warm_start;           /* 0 cold; 1 warm.  First Newton iteration of a
+                                   load step: the previous step's first-iteration
+                                   lambda scaled by the load-increment ratio.
+                                   Later iterations: the previous iteration's
+                                   lambda and, while it keeps winning, the
+                                   learned candidate if one is set; the
+                                   one with the smaller projected initial residual
+                                   is used, and cold start if both are not finite */
   int32_t use_graph;            /* replay the PCGP iteration as a HIP graph     */
   int32_t tile;                 /* factor tile rows 16/32/64; 0 = autotuned     */
   double refine_eps;            /* FP32 mode: inner PCGP tolerance (0 = 1e-4)   */
@@ -103,6 +110,8 @@ typedef struct {
   double r_ref;                 /* ||P (d - F lambda_Im)||                      */
   double r_final;               /* last ||P r||                                 */
   double ms;                    /* wall time of the call                        */
+  int32_t warm_choice;          /* 0 cold start, 1 first guess, 2 second guess   */
+  int32_t pad;
 } tfeti_pcg_report;
 
 typedef struct {
@@ -114,6 +123,8 @@ typedef struct {
   double relres;                /* ||assembled residual|| / ||assembled df||, free DOFs */
   double crit;                  /* the paper's increment criterion (Algorithm 2)*/
   double ms_assembly, ms_factor, ms_pcg, ms_total;
+  int32_t warm_choice;          /* 0 cold, 1 fallback lambda, 2 learned         */
+  int32_t pad;
 } tfeti_newton_report;
 
 typedef struct {
@@ -233,10 +244,76 @@ int tfeti_graph_status(const tfeti_handle* h);
 int tfeti_model_host(const tfeti_problem* prob_host, int32_t tile, tfeti_sizes* sizes_host, int64_t* nnz_host,
                      int64_t* rowptr_host, int64_t* col_host, double* val_host);
 
+/* ---- learned warm start: network kernels ------------------------------- */
+
+/* A 3-layer perceptron h1 = relu(x W1^T + b1), h2 = relu(h1 W2^T + b2),
+ * y = h2 W3^T + b3 with FP32 master weights, bfloat16 copies used by the
+ * products and bfloat16 activations, FP32 accumulation.  All pointers are
+ * device buffers owned by the caller; W[l] is row-major (out x in). */
+typedef struct {
+  int32_t d_in, d_h, d_out;     /* 31, 256, 21 for the warm start            */
+  float* W[3];                  /* master weights                            */
+  float* b[3];
+  uint16_t* Wb[3];              /* bfloat16 copies of W                      */
+  float* gW[3];                 /* gradients (written by tfeti_mlp_loss_grad) */
+  float* gb[3];
+  float* mW[3];                 /* Adam first and second moments             */
+  float* vW[3];
+  float* mb[3];
+  float* vb[3];
+} tfeti_mlp;
+
+/* Floats of device workspace needed for a batch of n rows. */
+int tfeti_mlp_work_size(const tfeti_mlp* net_host, int64_t n, int64_t* floats_host);
+/* Wb = bf16(W) (after initializing or loading W). */
+int tfeti_mlp_sync_bf16(const tfeti_mlp* net_host, void* stream);
+/* Y (n x d_out, FP32) = network(X (n x d_in, FP32, rounded to bf16)). */
+int tfeti_mlp_forward(const tfeti_mlp* net_host, int64_t n, const float* X, float* Y, float* work, void* stream);
+/* Forward, masked mean squared error L = 1/(2n) sum M (Y - T)^2 into *loss
+ * (device scalar), and the gradients of L into gW, gb. */
+int tfeti_mlp_loss_grad(const tfeti_mlp* net_host, int64_t n, const float* X, const float* T, const float* M,
+                        float* Y, float* loss, float* work, void* stream);
+/* One Adam step (step = 1, 2, ...) on W, b from gW, gb; refreshes Wb. */
+int tfeti_mlp_adam(const tfeti_mlp* net_host, int32_t step, float lr, float beta1, float beta2, float eps,
+                   void* stream);
+
+/* ---- learned warm start: features, targets and candidate ------------- */
+
+/* The interface nodes (mesh nodes carrying multiplier rows) of the handle's
+ * model; each holds up to 21 rows: 7 slots per displacement component (the
+ * orthonormal gluing rows of a node shared by up to 8 subdomains, or one
+ * Dirichlet row per copy).  s_lam = |dload| * |traction at factor 1| * element
+ * face area of the loaded face is the nodal force scale of a load increment
+ * dload (1 if zero).  Buffers below are device memory owned by the caller and
+ * work on the handle's stream; they are asynchronous. */
+int tfeti_warm_nodes(const tfeti_handle* h, int64_t* n_host);
+/* X (n x 31, FP32): load direction (3), lambda_prev of the node's rows / s_lam
+ * (21, 0 on empty slots), mean committed hardening kappa of the elements around
+ * the node times H/sigma_y (1), one-hot node class (6: gluing over 2/4/8
+ * copies, Dirichlet with 1/2/4 copies).  lambda_prev (m) may be NULL (zero).
+ * M (n x 21, may be NULL) receives 1 on used slots, 0 on empty ones. */
+int tfeti_warm_features(tfeti_handle* h, const double* lambda_prev, double dload, float* X, float* M);
+/* T (n x 21, FP32) = (lambda_next - lambda_prev) / s_lam on used slots, 0 else. */
+int tfeti_warm_targets(tfeti_handle* h, const double* lambda_prev, const double* lambda_next, double dload,
+                       float* T);
+/* lambda_out (m) = lambda_prev + s_lam * Y on every row (Y: n x 21 FP32). */
+int tfeti_warm_candidate(tfeti_handle* h, const double* lambda_prev, const float* Y, double dload,
+                         double* lambda_out);
+/* Offer lambda (m, device, copied) as the second warm-start candidate at the
+ * Newton iterations i >= 2 of the current (or next) load step, until it loses
+ * to the previous iteration's multipliers once; NULL withdraws it.
+ * tfeti_commit_load_step clears it; used only when warm_start is on. */
+int tfeti_set_learned_guess(tfeti_handle* h, const double* lambda);
+/* Multipliers of the final Newton iteration of the last committed load step
+ * (m, device): the interface-force increment of that step.  *available_host = 0
+ * and zeros if none was committed yet. */
+int tfeti_get_converged_lambda(const tfeti_handle* h, double* lambda, int32_t* available_host);
+
 /* ---- stateless return map (Section 2.4, Voigt form of Section 3.1) ----- */
 
-/* For npts points: trial = sigma_k + C deps; if Phi(trial, kappa_k) <= 0 the
- * step is elastic (dsigma = C deps, dkappa = 0, D = C); otherwise
+/* For npts points: trial = sigma_k + C deps; if Phi(trial, kappa_k) <=
+ * 1e-12 (sigma_y + H kappa_k) (a committed point on the yield surface counts
+ * as elastic whatever the sign of its rounding) the step is elastic (dsigma = C deps, dkappa = 0, D = C); otherwise
  * dkappa = Phi/(3mu+H), dsigma = C deps - 3mu/(3mu+H) sqrt(2/3) Phi n with n
  * the unit deviator of the trial stress, and D the generalized derivative
  * C - 2mu beta E_eps - 2mu beta sqrt(2/3) (sigma_y + H kappa_k)/|dev trial|

@@ -34,17 +34,6 @@ def bf16(x: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def init(seed: int = 0, dims=DIMS):
-    """He-style initialization from a seeded numpy generator."""
-    rng = np.random.default_rng(seed)
-    params = {}
-    for l in range(3):
-        fan_in, fan_out = dims[l], dims[l + 1]
-        params[f"W{l + 1}"] = rng.standard_normal((fan_out, fan_in)) * np.sqrt(2.0 / fan_in)
-        params[f"b{l + 1}"] = np.zeros(fan_out)
-    return params
-
-
 def forward(p, X, round_bf16: bool = False):
     r = bf16 if round_bf16 else (lambda a: a)
     a1 = X @ p["W1"].T + p["b1"]

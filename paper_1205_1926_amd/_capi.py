@@ -39,14 +39,16 @@ class Options(C.Structure):
 
 class PcgReport(C.Structure):
     _fields_ = [("iters", C.c_int32), ("fapplies", C.c_int32), ("converged", C.c_int32), ("outer", C.c_int32),
-                ("r_ref", C.c_double), ("r_final", C.c_double), ("ms", C.c_double)]
+                ("r_ref", C.c_double), ("r_final", C.c_double), ("ms", C.c_double),
+                ("warm_choice", C.c_int32), ("pad", C.c_int32)]
 
 
 class NewtonReport(C.Structure):
     _fields_ = [("iteration", C.c_int32), ("pcg_iters", C.c_int32), ("fapplies", C.c_int32),
                 ("plastic_gp", C.c_int32), ("plastic_elements", C.c_int32), ("relres", C.c_double),
                 ("crit", C.c_double), ("ms_assembly", C.c_double), ("ms_factor", C.c_double),
-                ("ms_pcg", C.c_double), ("ms_total", C.c_double)]
+                ("ms_pcg", C.c_double), ("ms_total", C.c_double), ("warm_choice", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -54,6 +56,11 @@ class Sizes(C.Structure):
                 ("m_U", C.c_int64), ("l", C.c_int64), ("n_elem", C.c_int64), ("n_gp", C.c_int64),
                 ("n_gdof", C.c_int64), ("skyline_entries", C.c_int64), ("factor_entries", C.c_int64),
                 ("factor_bytes", C.c_int64), ("tile", C.c_int32), ("precision", C.c_int32)]
+
+
+class Mlp(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("d_h", C.c_int32), ("d_out", C.c_int32)] + [
+        (name, C.c_void_p * 3) for name in ("W", "b", "Wb", "gW", "gb", "mW", "vW", "mb", "vb")]
 
 
 def struct_dict(s) -> dict:
@@ -88,6 +95,17 @@ SIGNATURES = {
     "tfeti_graph_status": (I32, [P]),
     "tfeti_model_host": (I32, [C.POINTER(Problem), I32, C.POINTER(Sizes), C.POINTER(I64), P, P, P]),
     "return_map": (I32, [C.POINTER(Material), I64, P, P, P, P, P, P, P, P]),
+    "tfeti_warm_nodes": (I32, [P, C.POINTER(I64)]),
+    "tfeti_warm_features": (I32, [P, P, D, P, P]),
+    "tfeti_warm_targets": (I32, [P, P, P, D, P]),
+    "tfeti_warm_candidate": (I32, [P, P, P, D, P]),
+    "tfeti_set_learned_guess": (I32, [P, P]),
+    "tfeti_get_converged_lambda": (I32, [P, P, C.POINTER(I32)]),
+    "tfeti_mlp_work_size": (I32, [C.POINTER(Mlp), I64, C.POINTER(I64)]),
+    "tfeti_mlp_sync_bf16": (I32, [C.POINTER(Mlp), P]),
+    "tfeti_mlp_forward": (I32, [C.POINTER(Mlp), I64, P, P, P, P]),
+    "tfeti_mlp_loss_grad": (I32, [C.POINTER(Mlp), I64, P, P, P, P, P, P, P]),
+    "tfeti_mlp_adam": (I32, [C.POINTER(Mlp), I32, C.c_float, C.c_float, C.c_float, C.c_float, P]),
 }
 
 _lib = None

@@ -70,6 +70,17 @@ struct tfeti_handle {
   int32_t* d_fail = nullptr;
   unsigned long long* d_plcount = nullptr;
   DualMaps dm{};
+  // warm start: candidate pairs (projected guess, residual), the converged
+  // multipliers of the last committed load step and the learned candidate
+  double *d_cl[2] = {}, *d_cr[2] = {};
+  double *d_lam_conv = nullptr, *d_lam_learn = nullptr;  // final-iteration lambda of the last step; learned
+  double *d_lam_first = nullptr, *d_lam_first_prev = nullptr, *d_lam_guess = nullptr;
+  double first_dlf_prev = 0.0;                             // load increment of d_lam_first_prev
+  bool have_conv = false, learn_set = false, have_first_prev = false;
+  int32_t* d_wn_rows = nullptr;
+  int8_t* d_wn_class = nullptr;
+  int32_t *d_wn_erp = nullptr, *d_wn_elems = nullptr;
+  WarmMaps wm{};
   // Newton state
   double dlf = 0.0, df_norm = 0.0;
   int newton_i = 0;
@@ -413,8 +424,8 @@ double read_rref(tfeti_handle* h) {
 // outer FP64 refinement wraps it: rho = P(d - F64 lambda), inner PCGP on
 // P F32 delta = rho to a relative tolerance refine_eps, lambda += delta,
 // until ||rho|| <= eps_pcg ||P(d - F64 lambda_Im)||.
-int pcg_solve(tfeti_handle* h, const double* f, const double* guess, double* lam_out, double* u_out,
-              tfeti_pcg_report* rep) {
+int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const double* guess2, double* lam_out,
+              double* u_out, tfeti_pcg_report* rep) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t m = h->M.m;
   const bool mixed = h->prec == TFETI_PREC_FP32;
@@ -437,37 +448,52 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, double* lam
   }
   set_rref(h, h->d_dt, h->d_w);
   const double r_ref = read_rref(h);
-  // warm start: lambda_Ker = P guess
+  // warm start (safeguarded): each finite candidate g gives lambda_Ker = P g
+  // and r = d~ - F lambda_Ker; the candidate with the smaller ||P r|| wins
   bool rejected = false;
-  if (guess) {
-    launch_check_finite(m, guess, h->d_S, h->st);
-    PcgScalars Sh;
-    HIPCHK(hipMemcpyAsync(&Sh, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
+  const double* cands[2] = {guess, guess2};
+  double best = -1.0;
+  int choice = 0;
+  double* lam_acc = mixed ? h->d_lam_acc : h->d_lam_ker;
+  for (int c = 0; c < 2; ++c) {
+    if (!cands[c]) continue;
+    {
+      int zero = 0;
+      HIPCHK(hipMemcpyAsync(&h->d_S->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice, h->st));
+    }
+    launch_check_finite(m, cands[c], h->d_S, h->st);
+    PcgScalars Sc;
+    HIPCHK(hipMemcpyAsync(&Sc, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
-    if (Sh.nonfinite) {
+    if (Sc.nonfinite) {
       rejected = true;
-      guess = nullptr;
+      continue;
+    }
+    project(h, cands[c], h->d_cl[c], nullptr, nullptr);
+    fapply(h, h->d_cl[c], h->d_q, nullptr, nullptr, nullptr, false, true);
+    launch_copy(m, h->d_dt, h->d_cr[c], h->st);
+    launch_axpby(m, -1.0, h->d_q, 1.0, h->d_cr[c], h->st);
+    fapplies++;
+    fapplies64++;
+    set_rref(h, h->d_cr[c], h->d_w);
+    const double nr = read_rref(h);
+    if (nr == nr && (best < 0.0 || nr < best)) {
+      best = nr;
+      choice = c + 1;
     }
   }
-  double* lam_acc = mixed ? h->d_lam_acc : h->d_lam_ker;
-  if (guess) {
-    project(h, guess, lam_acc, nullptr, nullptr);
+  if (choice) {
+    launch_copy(m, h->d_cl[choice - 1], lam_acc, h->st);
+    launch_copy(m, h->d_cr[choice - 1], h->d_r, h->st);
   } else {
     launch_axpby(m, 0.0, nullptr, 0.0, lam_acc, h->st);
+    launch_copy(m, h->d_dt, h->d_r, h->st);
   }
   PcgScalars Sh{};
   int total_iters = 0, outer = 0;
   bool converged = false;
   double r_final = r_ref;
   if (!mixed) {
-    // r = d~ - F lambda_Ker
-    launch_copy(m, h->d_dt, h->d_r, h->st);
-    if (guess) {
-      fapply(h, h->d_lam_ker, h->d_q, nullptr, nullptr, nullptr, false, true);
-      launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
-      fapplies++;
-      fapplies64++;
-    }
     set_rref(h, h->d_dt, h->d_w);  // S.r_ref = ||P d~|| for the stopping test
     int st = pcg_loop(h, h->opt.eps_pcg, h->opt.max_pcg, &Sh);
     if (st < 0) return st;
@@ -481,9 +507,10 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, double* lam
     const double eps_in = h->opt.refine_eps > 0 ? h->opt.refine_eps : 1e-5;
     const int max_outer = 50;
     for (;;) {
-      // outer residual r = d~ - F64 lambda_acc (FP64), rho = P r
-      launch_copy(m, h->d_dt, h->d_r, h->st);
-      if (outer > 0 || guess) {
+      // outer residual r = d~ - F64 lambda_acc (FP64), rho = P r (already in
+      // d_r before the first sweep)
+      if (outer > 0) {
+        launch_copy(m, h->d_dt, h->d_r, h->st);
         fapply(h, lam_acc, h->d_q, nullptr, nullptr, nullptr, false, true);
         launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
         fapplies++;
@@ -532,6 +559,7 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, double* lam
     rep->r_ref = r_ref;
     rep->r_final = r_final;
     rep->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    rep->warm_choice = choice;
   }
   if (rejected && status == TFETI_OK) status = TFETI_W_WARMSTART_REJECTED;
   return status;
@@ -736,8 +764,19 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_f, M.n_torn));
   RC(dalloc(h, &h->d_delta, M.n_torn));
   double** mv[] = {&h->d_lam, &h->d_lam_im, &h->d_lam_ker, &h->d_r,        &h->d_w,  &h->d_z,      &h->d_y,
-                   &h->d_p,   &h->d_q,      &h->d_d,       &h->d_lam_prev, &h->d_dt, &h->d_lam_acc};
+                   &h->d_p,   &h->d_q,      &h->d_d,       &h->d_lam_prev, &h->d_dt, &h->d_lam_acc,
+                   &h->d_cl[0], &h->d_cl[1], &h->d_cr[0],  &h->d_cr[1],   &h->d_lam_conv, &h->d_lam_learn,
+                   &h->d_lam_first, &h->d_lam_first_prev, &h->d_lam_guess};
   for (double** v : mv) RC(dalloc(h, v, M.m));
+  RC(upload(h, &h->d_wn_rows, M.wn_rows));
+  RC(upload(h, &h->d_wn_class, M.wn_class));
+  RC(upload(h, &h->d_wn_erp, M.wn_erp));
+  RC(upload(h, &h->d_wn_elems, M.wn_elems));
+  h->wm.n = M.n_wnodes;
+  h->wm.rows = h->d_wn_rows;
+  h->wm.cls = h->d_wn_class;
+  h->wm.erp = h->d_wn_erp;
+  h->wm.elems = h->d_wn_elems;
   RC(dalloc(h, &h->d_iface, M.n_iface));
   RC(dalloc(h, &h->d_c, M.lc_pad));
   RC(dalloc(h, &h->d_a, M.lc_pad));
@@ -898,13 +937,38 @@ int tfeti_newton_step(tfeti_handle* h, tfeti_newton_report* rep) {
   r.ms_factor = ms_since(t1);
   auto t2 = std::chrono::steady_clock::now();
   tfeti_pcg_report pr{};
-  const double* guess = (h->opt.warm_start && h->have_lambda) ? h->d_lam_prev : nullptr;
-  int st = pcg_solve(h, h->d_f, guess, h->d_lam_prev, h->d_delta, &pr);
+  // warm-start candidates.  First Newton iteration: the tangent at a zero
+  // increment is the elastic one and the right-hand side is the load
+  // increment, so the previous step's first-iteration multipliers scaled by
+  // the ratio of the load increments solve it up to points that sit exactly
+  // on the yield surface.  Later iterations: the torn residual is about
+  // B^T lambda_{i-1}, so the previous iteration's multipliers, and beside
+  // them the learned candidate of the step if one was set, for as long as it
+  // keeps winning (once the previous iteration's multipliers are closer, the
+  // Newton contraction keeps them closer).
+  const double* guess = nullptr;
+  const double* guess2 = nullptr;
+  if (h->opt.warm_start) {
+    if (r.iteration == 1) {
+      if (h->have_first_prev && h->first_dlf_prev != 0.0) {
+        launch_copy(M.m, h->d_lam_first_prev, h->d_lam_guess, h->st);
+        launch_axpby(M.m, 0.0, nullptr, h->dlf / h->first_dlf_prev, h->d_lam_guess, h->st);
+        guess = h->d_lam_guess;
+      }
+    } else {
+      guess = h->d_lam_prev;
+      if (h->learn_set) guess2 = h->d_lam_learn;
+    }
+  }
+  int st = pcg_solve(h, h->d_f, guess, guess2, h->d_lam_prev, h->d_delta, &pr);
   if (st < 0) return st;
+  if (guess2 && pr.warm_choice != 2) h->learn_set = false;
+  if (r.iteration == 1) launch_copy(M.m, h->d_lam_prev, h->d_lam_first, h->st);
   h->have_lambda = true;
   r.ms_pcg = ms_since(t2);
   r.pcg_iters = pr.iters;
   r.fapplies = pr.fapplies;
+  r.warm_choice = pr.warm_choice;
   // the paper's increment criterion, untorn norms
   double nd = untorn_norm(h, h->d_delta);
   double nold = untorn_norm(h, h->d_du);
@@ -938,8 +1002,81 @@ int tfeti_commit_load_step(tfeti_handle* h) {
   launch_axpby(6 * M.n_gp, 1.0, h->d_dsigma, 1.0, h->d_sigma, h->st);
   launch_axpby(M.n_gp, 1.0, h->d_dkappa, 1.0, h->d_kappa, h->st);
   launch_axpby(M.n_torn, 1.0, h->d_du, 1.0, h->d_u, h->st);
+  if (h->have_lambda) {
+    launch_copy(M.m, h->d_lam_prev, h->d_lam_conv, h->st);
+    launch_copy(M.m, h->d_lam_first, h->d_lam_first_prev, h->st);
+    h->first_dlf_prev = h->dlf;
+    h->have_conv = true;
+    h->have_first_prev = true;
+  }
+  h->learn_set = false;
   HIPCHK(hipStreamSynchronize(h->st));
   h->step_active = false;
+  return TFETI_OK;
+}
+
+int tfeti_get_converged_lambda(const tfeti_handle* hc, double* lam, int32_t* available_host) {
+  tfeti_handle* h = const_cast<tfeti_handle*>(hc);
+  if (!h || !lam) return TFETI_E_INVALID;
+  if (available_host) *available_host = h->have_conv ? 1 : 0;
+  if (h->have_conv)
+    HIPCHK(hipMemcpyAsync(lam, h->d_lam_conv, h->M.m * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  else
+    HIPCHK(hipMemsetAsync(lam, 0, h->M.m * sizeof(double), h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return TFETI_OK;
+}
+
+int tfeti_set_learned_guess(tfeti_handle* h, const double* lam) {
+  if (!h) return TFETI_E_INVALID;
+  if (!lam) {
+    h->learn_set = false;
+    return TFETI_OK;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_lam_learn, lam, h->M.m * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  h->learn_set = true;
+  return TFETI_OK;
+}
+
+int tfeti_warm_nodes(const tfeti_handle* h, int64_t* n_host) {
+  if (!h || !n_host) return TFETI_E_INVALID;
+  *n_host = h->M.n_wnodes;
+  return TFETI_OK;
+}
+
+// s_lam = |load increment| * element face area; returns 1 if the increment is 0
+static double warm_scale(const tfeti_handle* h, double dload, double dir[3]) {
+  const HostModel& M = h->M;
+  double n = std::sqrt(M.load_dir[0] * M.load_dir[0] + M.load_dir[1] * M.load_dir[1] + M.load_dir[2] * M.load_dir[2]);
+  for (int c = 0; c < 3; ++c) dir[c] = n > 0 ? M.load_dir[c] / n * (dload >= 0 ? 1.0 : -1.0) : 0.0;
+  double s = std::fabs(dload) * n * M.load_area;
+  return s > 0 ? s : 1.0;
+}
+
+int tfeti_warm_features(tfeti_handle* h, const double* lam_prev, double dload, float* X, float* Mk) {
+  if (!h || !X) return TFETI_E_INVALID;
+  double dir[3];
+  const double s = warm_scale(h, dload, dir);
+  launch_warm_features(h->wm, h->d_kappa, lam_prev, dir, 1.0 / s, h->M.mat.H / h->M.mat.sigma_y, X, Mk, h->st);
+  HIPCHK(hipGetLastError());
+  return TFETI_OK;
+}
+
+int tfeti_warm_targets(tfeti_handle* h, const double* lam_prev, const double* lam_next, double dload, float* T) {
+  if (!h || !lam_next || !T) return TFETI_E_INVALID;
+  double dir[3];
+  const double s = warm_scale(h, dload, dir);
+  launch_warm_targets(h->wm, lam_prev, lam_next, 1.0 / s, T, h->st);
+  HIPCHK(hipGetLastError());
+  return TFETI_OK;
+}
+
+int tfeti_warm_candidate(tfeti_handle* h, const double* lam_prev, const float* Y, double dload, double* lam_out) {
+  if (!h || !Y || !lam_out) return TFETI_E_INVALID;
+  double dir[3];
+  const double s = warm_scale(h, dload, dir);
+  launch_warm_apply(h->wm, lam_prev, Y, s, lam_out, h->st);
+  HIPCHK(hipGetLastError());
   return TFETI_OK;
 }
 
@@ -947,7 +1084,7 @@ int tfeti_dual_pcg(tfeti_handle* h, const double* f, const double* guess, double
                    tfeti_pcg_report* rep) {
   if (!h || !f) return TFETI_E_INVALID;
   if (!h->factored) return fail(h, TFETI_E_INVALID, "no factorized operator: call tfeti_assemble and tfeti_factorize");
-  return pcg_solve(h, f, guess, lam_out, u_out, rep);
+  return pcg_solve(h, f, guess, nullptr, lam_out, u_out, rep);
 }
 
 int tfeti_assemble(tfeti_handle* h, const double* du, double* fint, int64_t* plastic_count) {

@@ -277,7 +277,8 @@ void launch_sum_partials(const double* partials, int n, double* out, hipStream_t
 // ---------------------------------------------------------------- vector updates
 __global__ void axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * (x ? x[i] : 0.0) + b * y[i];
+  // b == 0 does not read y (it may hold anything, NaN included)
+  if (i < n) y[i] = a * (x ? x[i] : 0.0) + (b != 0.0 ? b * y[i] : 0.0);
 }
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
   if (n > 0) axpby_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, a, x, b, y);

@@ -140,4 +140,19 @@ void launch_assembled_sq(int64_t n_gdof, const int32_t* g_rp, const int64_t* g_c
 void launch_untorn_sq(int64_t n_gdof, const int64_t* g_first, const double* v, double* partials, hipStream_t st);
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
 
+// ---- learned warm start ---------------------------------------------------------
+struct WarmMaps {
+  int64_t n;                  // interface nodes
+  const int32_t* rows;        // n * 21
+  const int8_t* cls;
+  const int32_t* erp;
+  const int32_t* elems;
+};
+void launch_warm_features(const WarmMaps& W, const double* kappa, const double* lam_prev, const double dir[3],
+                          double inv_slam, double kscale, float* X, float* Mk, hipStream_t st);
+void launch_warm_targets(const WarmMaps& W, const double* lam_prev, const double* lam_next, double inv_slam, float* T,
+                         hipStream_t st);
+void launch_warm_apply(const WarmMaps& W, const double* lam_prev, const float* Y, double slam, double* out,
+                       hipStream_t st);
+
 }  // namespace tfeti

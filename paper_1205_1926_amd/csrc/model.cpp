@@ -220,6 +220,8 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   };
   std::vector<int64_t> rpG{0}, rpU{0};
   std::vector<Ent> eG, eU;
+  std::vector<int64_t> rnodeG, rnodeU;   // global node of each row
+  std::vector<int8_t> rslotG, rslotU;    // slot 7 c + index within the node
   M.g_free.assign(M.n_gdof, 1);
   for (int64_t g = 0; g < M.n_gnodes; ++g) {
     int32_t k = cnt[g + 1] - cnt[g];
@@ -229,6 +231,8 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
         for (int32_t t = 0; t < k; ++t) {
           eU.push_back({cp_sub[cnt[g] + t], cp_loc[cnt[g] + t], c, 1.0});
           rpU.push_back((int64_t)eU.size());
+          rnodeU.push_back(g);
+          rslotU.push_back((int8_t)(7 * c + t));
         }
       } else if (k > 1) {
         for (int32_t j = 1; j < k; ++j) {
@@ -236,6 +240,8 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
           for (int32_t t = 0; t < j; ++t) eG.push_back({cp_sub[cnt[g] + t], cp_loc[cnt[g] + t], c, cj});
           eG.push_back({cp_sub[cnt[g] + j], cp_loc[cnt[g] + j], c, -(double)j * cj});
           rpG.push_back((int64_t)eG.size());
+          rnodeG.push_back(g);
+          rslotG.push_back((int8_t)(7 * c + (j - 1)));
         }
       }
     }
@@ -482,6 +488,68 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   }
   for (int64_t i = M.lc; i < M.lc_pad; ++i) M.GGt_band[i * Wc + M.bc] = 1.0;
 
+  // ---- interface nodes of the learned warm start ----
+  {
+    std::vector<int32_t> node_of(M.n_gnodes, -1);
+    std::vector<int64_t> wn_g;
+    auto visit = [&](int64_t g) {
+      if (node_of[g] < 0) {
+        node_of[g] = (int32_t)wn_g.size();
+        wn_g.push_back(g);
+      }
+      return node_of[g];
+    };
+    for (int64_t r = 0; r < M.mG; ++r) visit(rnodeG[r]);
+    for (int64_t r = 0; r < M.mU; ++r) visit(rnodeU[r]);
+    M.n_wnodes = (int64_t)wn_g.size();
+    M.wn_rows.assign(21 * M.n_wnodes, -1);
+    M.wn_class.assign(M.n_wnodes, 0);
+    std::vector<uint8_t> has_dir(M.n_wnodes, 0);
+    for (int64_t r = 0; r < M.mG; ++r) M.wn_rows[21 * node_of[rnodeG[r]] + rslotG[r]] = (int32_t)r;
+    for (int64_t r = 0; r < M.mU; ++r) {
+      M.wn_rows[21 * node_of[rnodeU[r]] + rslotU[r]] = (int32_t)(M.mG + r);
+      has_dir[node_of[rnodeU[r]]] = 1;
+    }
+    M.wn_erp.assign(M.n_wnodes + 1, 0);
+    M.wn_elems.clear();
+    for (int64_t q = 0; q < M.n_wnodes; ++q) {
+      const int64_t g = wn_g[q];
+      const int32_t k = cnt[g + 1] - cnt[g];
+      int8_t cls;
+      if (has_dir[q])
+        cls = (int8_t)(k >= 4 ? 5 : (k >= 2 ? 4 : 3));
+      else
+        cls = (int8_t)(k >= 8 ? 2 : (k >= 4 ? 1 : 0));
+      M.wn_class[q] = cls;
+      for (int32_t t = cnt[g]; t < cnt[g + 1]; ++t) {
+        const SubDev& s = M.subs[cp_sub[t]];
+        const int32_t a = cp_loc[t];
+        const int32_t i = a % s.N[0], j = (a / s.N[0]) % s.N[1], kk = a / (s.N[0] * s.N[1]);
+        for (int dk = 0; dk < 2; ++dk)
+          for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+              int32_t ei = i - di, ej = j - dj, ek = kk - dk;
+              if (ei < 0 || ej < 0 || ek < 0 || ei >= s.n[0] || ej >= s.n[1] || ek >= s.n[2]) continue;
+              M.wn_elems.push_back((int32_t)(s.elem_off + ei + s.n[0] * (ej + s.n[1] * ek)));
+            }
+      }
+      M.wn_erp[q + 1] = (int32_t)M.wn_elems.size();
+    }
+    // load scale: traction of the loaded face (the largest one) and its element face area
+    double best = 0.0;
+    for (int f = 0; f < 6; ++f) {
+      double n2 = M.trac[f][0] * M.trac[f][0] + M.trac[f][1] * M.trac[f][1] + M.trac[f][2] * M.trac[f][2];
+      if (n2 > best) {
+        best = n2;
+        for (int c = 0; c < 3; ++c) M.load_dir[c] = M.trac[f][c];
+        int ax = f / 2;
+        int a1 = ax == 0 ? 1 : 0, a2 = ax == 2 ? 1 : 2;
+        M.load_area = M.h[a1] * M.h[a2];
+      }
+    }
+    if (best == 0.0) M.load_area = M.h[0] * M.h[1];
+  }
+
   // ---- sanity checks of every index map against its target ----
   for (int64_t e = 0; e < nnz; ++e)
     if (M.b_col[e] < 0 || M.b_col[e] >= M.n_torn || M.b_iface[e] < 0 || M.b_iface[e] >= M.n_iface)
@@ -497,6 +565,10 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   }
   for (size_t q = 0; q < M.kbb_band.size(); ++q)
     if (M.kbb_band[q] < 0 || M.kbb_band[q] >= M.band_entries) return "internal: K_bb map out of range";
+  for (size_t q = 0; q < M.wn_rows.size(); ++q)
+    if (M.wn_rows[q] < -1 || M.wn_rows[q] >= M.m) return "internal: warm-start row map out of range";
+  for (size_t q = 0; q < M.wn_elems.size(); ++q)
+    if (M.wn_elems[q] < 0 || M.wn_elems[q] >= M.n_elem) return "internal: warm-start element map out of range";
   return "";
 }
 

@@ -64,6 +64,14 @@ struct HostModel {
   // coarse matrix G G^T in lower row-band form
   int32_t lc = 0, bc = 0, lc_pad = 0;
   std::vector<double> GGt_band;         // lc_pad rows of (bc + 1)
+  // interface nodes of the learned warm start: nodes carrying multiplier rows
+  int64_t n_wnodes = 0;
+  std::vector<int32_t> wn_rows;         // n_wnodes * 21: row in slot 7 c + j, or -1
+  std::vector<int8_t> wn_class;         // glue k = 2/4/8 -> 0/1/2, Dirichlet copies 1/2/4 -> 3/4/5
+  std::vector<int32_t> wn_erp;          // n_wnodes + 1
+  std::vector<int32_t> wn_elems;        // elements containing the node (all copies)
+  double load_dir[3] = {0, 0, 0};       // traction of the loaded face at factor 1
+  double load_area = 0.0;               // element face area of that face
   // sizes
   int64_t band_entries = 0;             // sum npad * Wb
   int64_t skyline_entries = 0;          // sum of envelope widths of the factors

@@ -174,6 +174,52 @@ class GpuSolver:
         n = self.w.steps if steps is None else steps
         return [self.load_step() for _ in range(n)]
 
+    # ------------------------------------------------------------------ learned warm start
+    def warm_nodes(self) -> int:
+        n = C.c_int64()
+        self._check(self.lib.tfeti_warm_nodes(self.h, C.byref(n)), "warm_nodes")
+        return n.value
+
+    def warm_features(self, lam_prev, dload, X=None, M=None, want_mask=True):
+        """Features (n x 31, FP32) of every interface node; mask (n x 21) if wanted."""
+        torch = _torch()
+        n = self.warm_nodes()
+        if X is None:
+            X = torch.empty((n, 31), dtype=torch.float32, device=self.device)
+        if want_mask and M is None:
+            M = torch.empty((n, 21), dtype=torch.float32, device=self.device)
+        self._check(self.lib.tfeti_warm_features(self.h, _ptr(lam_prev), C.c_double(dload), _ptr(X),
+                                                 _ptr(M) if want_mask else None), "warm_features")
+        return X, M
+
+    def warm_targets(self, lam_prev, lam_next, dload, T=None):
+        torch = _torch()
+        if T is None:
+            T = torch.empty((self.warm_nodes(), 21), dtype=torch.float32, device=self.device)
+        self._check(self.lib.tfeti_warm_targets(self.h, _ptr(lam_prev), _ptr(lam_next), C.c_double(dload),
+                                                _ptr(T)), "warm_targets")
+        return T
+
+    def warm_candidate(self, lam_prev, Y, dload, out=None):
+        if out is None:
+            out = self.zeros(self.sizes["m"])
+        self._check(self.lib.tfeti_warm_candidate(self.h, _ptr(lam_prev), _ptr(Y), C.c_double(dload), _ptr(out)),
+                    "warm_candidate")
+        return out
+
+    def set_learned_guess(self, lam):
+        self._check(self.lib.tfeti_set_learned_guess(self.h, _ptr(lam)), "set_learned_guess")
+
+    def converged_lambda(self):
+        lam = self.zeros(self.sizes["m"])
+        ok = C.c_int32()
+        self._check(self.lib.tfeti_get_converged_lambda(self.h, _ptr(lam), C.byref(ok)), "get_converged_lambda")
+        return lam, bool(ok.value)
+
+    def load_increment(self, k=None):
+        k = self.k if k is None else k
+        return self.w.load_factor(k + 1) - self.w.load_factor(k)
+
     # ------------------------------------------------------------------ timing
     def set_timing(self, on: bool):
         self._check(self.lib.tfeti_set_timing(self.h, 1 if on else 0), "set_timing")

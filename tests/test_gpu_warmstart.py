@@ -1,0 +1,246 @@
+"""GPU tests of the learned warm start: the perceptron's forward pass,
+gradients and Adam step against the FP64 oracle on the same bf16-rounded
+inputs and weights, the interface-node maps, the safeguard that chooses
+between the fallback and the learned candidate, and what a trained network
+gains on unseen loads.
+
+Tolerances: the products accumulate in FP32 over at most 256 terms of
+bf16-rounded operands; intermediate activations are rounded to bf16 on both
+sides, but an FP32 accumulation that lands next to a bf16 rounding boundary
+can round the other way than the FP64 one, so single activations may differ by
+one bf16 ulp (2^-8 relative).  Outputs and gradients are compared in the
+relative Frobenius norm at 1e-2; the loss at 1e-3.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1205_1926_amd", "weights", "warmstart_cube8x8x8_uneven.safetensors")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1205_1926_amd import load
+    load()
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def F32(x, dev):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+
+
+def problem(n, seed=3):
+    rng = np.random.default_rng(seed)
+    p = W.mlp_init(seed)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.1
+    X = rng.standard_normal((n, 31))
+    Tt = rng.standard_normal((n, 21))
+    M = (rng.random((n, 21)) > 0.25).astype(np.float64)
+    return p, X, Tt, M
+
+
+def oracle_view(net, p, X):
+    """The oracle's parameters and inputs as the GPU sees them: bf16 weights
+    and inputs, FP32 biases."""
+    q = dict(p)
+    q.update(net.bf16_weights())
+    for l in range(3):
+        q[f"b{l + 1}"] = p[f"b{l + 1}"].astype(np.float32).astype(np.float64)
+    return q, mlp.bf16(X)
+
+
+@pytest.mark.parametrize("n", [1, 65, 300, 4096])
+def test_mlp_forward_matches_oracle(n, dev):
+    from paper_1205_1926_amd.warmstart import WarmNet
+    p, X, _, _ = problem(n)
+    net = WarmNet(p, device=str(dev))
+    Y = net.forward(F32(X, dev)).cpu().numpy()
+    q, Xb = oracle_view(net, p, X)
+    Yo, _ = mlp.forward(q, Xb, round_bf16=True)
+    assert rel(Y, Yo) <= 1e-2
+
+
+@pytest.mark.parametrize("n", [65, 1000])
+def test_mlp_gradients_match_oracle(n, dev):
+    from paper_1205_1926_amd.warmstart import WarmNet
+    p, X, Tt, M = problem(n, seed=4)
+    net = WarmNet(p, device=str(dev))
+    loss, Y = net.loss_grad(F32(X, dev), F32(Tt, dev), F32(M, dev))
+    g = net.grads()
+    q, Xb = oracle_view(net, p, X)
+    Yo, cache = mlp.forward(q, Xb, round_bf16=True)
+    go = mlp.backward(q, cache, Yo, Tt, M)
+    assert abs(float(loss) - mlp.loss(Yo, Tt, M)) <= 1e-3 * mlp.loss(Yo, Tt, M)
+    for k in go:
+        assert rel(g[k], go[k]) <= 1e-2, k
+
+
+def test_mlp_adam_matches_oracle(dev):
+    from paper_1205_1926_amd.warmstart import WarmNet
+    p, X, Tt, M = problem(200, seed=5)
+    net = WarmNet(p, device=str(dev))
+    net.loss_grad(F32(X, dev), F32(Tt, dev), F32(M, dev))
+    g = net.grads()
+    before = net.params()
+    net.adam(lr=1e-3)
+    after = net.params()
+    st = {}
+    ref = {k: v.copy() for k, v in before.items()}
+    mlp.adam(ref, g, st, lr=1e-3)
+    for k in ref:
+        step_o = ref[k] - before[k]
+        step_g = after[k] - before[k]
+        assert np.abs(step_g - step_o).max() <= 1e-3 * 1e-3 + 1e-6 * np.abs(before[k]).max(), k
+    # the bf16 shadows follow the masters
+    for k, wb in net.bf16_weights().items():
+        assert np.array_equal(wb, mlp.bf16(after[k]))
+
+
+def test_mlp_training_reduces_loss(dev):
+    from paper_1205_1926_amd.warmstart import WarmNet
+    rng = np.random.default_rng(9)
+    n = 2048
+    X = rng.standard_normal((n, 31))
+    A = rng.standard_normal((31, 21)) * 0.3
+    Tt = np.tanh(X @ A)
+    M = np.ones((n, 21))
+    net = WarmNet(W.mlp_init(1), device=str(dev))
+    Xd, Td, Md = F32(X, dev), F32(Tt, dev), F32(M, dev)
+    l0 = float(net.loss_grad(Xd, Td, Md)[0])
+    for _ in range(200):
+        net.loss_grad(Xd, Td, Md)
+        net.adam(lr=2e-3)
+    l1 = float(net.loss_grad(Xd, Td, Md)[0])
+    assert l1 < 0.1 * l0
+
+
+def test_mlp_rejects_bad_arguments(dev):
+    from paper_1205_1926_amd import _capi as A
+    from paper_1205_1926_amd.warmstart import WarmNet
+    net = WarmNet(W.mlp_init(0), device=str(dev))
+    lib = A.load()
+    bad = A.Mlp()
+    assert lib.tfeti_mlp_sync_bf16(None, None) == A.TFETI_E_INVALID
+    assert lib.tfeti_mlp_forward(bad, 4, None, None, None, None) == A.TFETI_E_INVALID
+    assert lib.tfeti_mlp_adam(net.s, 0, 1e-3, 0.9, 0.999, 1e-8, None) == A.TFETI_E_INVALID
+
+
+# ---------------------------------------------------------------- interface-node maps
+def test_warm_maps_cover_every_row_once(dev):
+    """Targets of lambda_next = 1..m (lambda_prev = 0) hold every multiplier
+    row exactly once; features carry lambda_prev on the same slots, a one-hot
+    class and the load direction."""
+    from paper_1205_1926_amd import GpuSolver
+    w = W.config(0)
+    g = GpuSolver(w)
+    m = g.sizes["m"]
+    n = g.warm_nodes()
+    assert n > 0
+    lam = torch.arange(1, m + 1, dtype=torch.float64, device=dev)
+    Tt = g.warm_targets(None, lam, 1.0).cpu().numpy()
+    X, M = g.warm_features(lam, 1.0)
+    X, M = X.cpu().numpy(), M.cpu().numpy()
+    assert int(M.sum()) == m
+    vals = Tt[M > 0]
+    s = vals.min()  # row 1 scaled by 1 / s_lam
+    assert np.array_equal(np.sort(np.rint(vals / s)).astype(np.int64), np.arange(1, m + 1))
+    assert np.all(Tt[M == 0] == 0)
+    assert np.allclose(X[:, 3:24][M > 0], vals, rtol=1e-6)
+    assert np.all(X[:, 25:31].sum(axis=1) == 1)
+    d = np.array(w.traction[5]) / np.linalg.norm(w.traction[5])
+    assert np.allclose(X[:, :3], d, atol=1e-7)
+    # the candidate is lambda_prev + s_lam * Y on every row
+    Y = torch.ones((n, 21), dtype=torch.float32, device=dev)
+    cand = g.warm_candidate(lam, Y, 1.0).cpu().numpy()
+    assert np.allclose(cand - np.arange(1, m + 1), 1.0 / s, rtol=1e-6)  # s is FP32
+
+
+# ---------------------------------------------------------------- safeguard and fallback
+def test_first_iteration_fallback_is_exact(dev):
+    """Equal load increments: the first Newton solve of every step after the
+    first starts from the previous step's first-iteration multipliers and
+    needs at most one PCGP iteration."""
+    from paper_1205_1926_amd import GpuSolver
+    w = W.config(0)
+    g = GpuSolver(w)
+    hs = g.run()
+    for k, h in enumerate(hs):
+        if k == 0:
+            assert h[0]["warm_choice"] == 0 and h[0]["pcg_iters"] > 5
+        else:
+            assert h[0]["warm_choice"] == 1 and h[0]["pcg_iters"] <= 1, (k, h[0])
+
+
+def test_learned_candidate_chosen_when_better(dev):
+    """A candidate equal to the step's converged multipliers wins over the
+    previous Newton iteration's at the second iteration and needs no more PCGP
+    iterations; a non-finite one is rejected and the step still converges to
+    the same displacements."""
+    from paper_1205_1926_amd import GpuSolver
+    w = W.small_cube(S=(2, 2, 2), n=(3, 3, 3), amp=700.0, shear=150.0, steps=3)
+    a = GpuSolver(w)
+    finals, hist_a = [], []
+    for _ in range(w.steps):
+        hist_a.append(a.load_step())
+        finals.append(a.converged_lambda()[0].clone())
+    b = GpuSolver(w)
+    hist_b = []
+    for k in range(w.steps):
+        b.set_learned_guess(finals[k])
+        hist_b.append(b.load_step())
+    ua, ub = a.state()["u"].cpu().numpy(), b.state()["u"].cpu().numpy()
+    assert rel(ub, ua) <= 1e-6
+    plastic = [k for k in range(w.steps) if len(hist_a[k]) >= 2]
+    assert plastic
+    for k in plastic:
+        assert hist_b[k][1]["warm_choice"] == 2
+        assert hist_b[k][1]["pcg_iters"] <= hist_a[k][1]["pcg_iters"]
+    c = GpuSolver(w)
+    for k in range(w.steps):
+        c.set_learned_guess(torch.full_like(finals[k], float("nan")))
+        h = c.load_step()
+        assert all(r["warm_choice"] != 2 for r in h)
+    assert rel(c.state()["u"].cpu().numpy(), ua) <= 1e-6
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights in the tree")
+def test_trained_network_on_unseen_load(dev):
+    """The trained network on a load seed outside its training set: the
+    displacements match the fallback run to the 1e-6 bar, and the PCGP
+    iterations and F-applies of both runs per Newton iteration index are
+    printed (the gain is measured, not assumed: the safeguard picks the
+    candidate with the smaller initial residual, which bounds the start but
+    not the iteration count)."""
+    from paper_1205_1926_amd import GpuSolver
+    from paper_1205_1926_amd.warmstart import WarmNet, path_stats, run_step
+    w = W.config(3, load_seed=1001)
+    steps = 8
+    net = WarmNet.load(WEIGHTS, device=str(dev))
+    out = {}
+    for name, use in (("fallback", None), ("learned", net)):
+        g = GpuSolver(w, use_graph=1)
+        hs = [run_step(g, net=use)[0] for _ in range(steps)]
+        out[name] = (path_stats(hs), g.state()["u"].cpu().numpy())
+        g.close()
+    assert rel(out["learned"][1], out["fallback"][1]) <= 1e-6
+    for name in out:
+        print(name, out[name][0]["total"], {i: (v["pcg_iters"], v["learned"])
+                                             for i, v in out[name][0]["by_iteration"].items()})

@@ -5,12 +5,13 @@ Adam reduces the loss on a fixed batch."""
 import numpy as np
 
 from oracle import mlp
+import workloads
 
 
 def small_problem(seed=0, n=12):
     rng = np.random.default_rng(seed)
     dims = (5, 7, 6, 4)
-    p = mlp.init(seed, dims)
+    p = workloads.mlp_init(seed, dims)
     for k in p:
         if k.startswith("b"):
             p[k] = rng.standard_normal(p[k].shape) * 0.1

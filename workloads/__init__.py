@@ -157,3 +157,17 @@ def small_cube(S=(2, 2, 2), n=(2, 2, 2), amp: float = 400.0, steps: int = 1,
                  dirichlet=_clamped_bottom(), steps=steps)
     w.traction[FACE_Z1] = [shear, 0.0, -amp]
     return w
+
+
+def mlp_init(seed: int = 0, dims=(31, 256, 256, 21)):
+    """Seeded He-style initial weights of the warm-start perceptron: W_l
+    (out x in) normal with variance 2 / in, zero biases.  These are random
+    inputs of the training run, shared by the oracle and the GPU path."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    params = {}
+    for l in range(3):
+        fan_in, fan_out = dims[l], dims[l + 1]
+        params[f"W{l + 1}"] = rng.standard_normal((fan_out, fan_in)) * np.sqrt(2.0 / fan_in)
+        params[f"b{l + 1}"] = np.zeros(fan_out)
+    return params
