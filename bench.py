@@ -1,13 +1,15 @@
 """Benchmark: F-lambda applies/s and Newton-step time of the TFETI path on one GPU.
 
-A step is one Newton iteration of the elastoplastic time stepping with a
-linear solve: return map + tangent assembly at every Gauss point, fixing-node
-regularization, batched band Cholesky, panel packing, and the whole PCGP
-(Algorithm 3) with its F-applies, projections and lumped preconditioner.
-When a load step converges (residual test, no solve) it is committed and the
-next load step starts, so every timed step contains exactly one linear solve.
+A step is one load step of the elastoplastic time stepping (Algorithm 4):
+Newton iterations until convergence, each with the return map and tangent
+assembly at every Gauss point, fixing-node regularization, batched band
+Cholesky of the subdomains whose tangent changed, panel packing and the whole
+PCGP (Algorithm 3) with its F-applies, projections and lumped preconditioner;
+then the commit.  The default times load steps 2..30 of the 10x10x10
+benchmark after one untimed load step.
 
-value = F-applies executed inside the K timed steps / wall time of the steps.
+value = F-applies executed inside the K timed load steps / their wall time.
+newton_step_ms = wall time / Newton iterations with a linear solve.
 roofline: the subdomain-solve kernel of the F-apply, algorithmic bytes = two
 passes over the skyline (envelope) of every subdomain factor, divided by the
 kernel's mean duration from HIP events on the library's stream.
@@ -68,11 +70,40 @@ def cpu_baseline(seconds: float = 12.0):
                       f"BLAS limited to 1 thread"}
 
 
+def counter_probe(g, reps: int) -> int:
+    """Kernels of known traffic for FETCH_SIZE / WRITE_SIZE runs: the F-apply
+    on the factors of the first Newton iteration, then a plain device copy of
+    1 GiB (reads 1 GiB, writes 1 GiB) that calibrates the counters."""
+    import torch
+    g.begin_load_step()
+    du = g.zeros(g.sizes["n_torn"])
+    g.assemble(du)
+    g.factorize()
+    sz = g.refresh_sizes()
+    lam = torch.randn(sz["m"], dtype=torch.float64, device=g.device)
+    q = torch.empty_like(lam)
+    for _ in range(reps):
+        g.fapply(lam, q)
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 27, dtype=torch.float64, device=g.device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    fb = 8 if sz["precision"] == 0 else 4
+    print(json.dumps({"probe": "counters", "fapply_reps": reps, "tile": sz["tile"], "schedule": sz["schedule"],
+                      "skyline_bytes_per_apply": 2 * sz["skyline_entries"] * fb,
+                      "stored_panel_bytes_per_apply": 2 * sz["factor_entries"] * fb,
+                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
+    g.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=29, help="timed load steps")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed load steps before them")
+    ap.add_argument("--learned", default=None, help="safetensors weights of the warm-start network")
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tile", type=int, default=0)
@@ -80,6 +111,9 @@ def main() -> int:
     ap.add_argument("--refine-eps", type=float, default=0.0, help="FP32 mode: inner PCGP tolerance")
     ap.add_argument("--fapply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counter-probe", action="store_true",
+                    help="for hardware-counter runs: factorize once, run --fapply-reps F-applies and one "
+                         "device copy of 1 GiB (the scale reference of the byte counters), print sizes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -100,44 +134,50 @@ def main() -> int:
     log(f"setup done in {time.perf_counter() - t0:.1f} s: {sz['n_sub']} subdomains, n={sz['n_torn']}, "
         f"m={sz['m']}, tile={sz['tile']}")
 
-    state = {"active": False}
+    if args.counter_probe:
+        return counter_probe(g, args.fapply_reps)
 
-    def solve_step():
-        """One Newton iteration with a linear solve; returns its report."""
-        while True:
-            if not state["active"]:
-                g.begin_load_step()
-                state["active"] = True
-            rc, rep = g.newton_step()
-            if rc == _capi.TFETI_CONVERGED or rc == _capi.TFETI_W_NEWTON_MAXIT:
-                g.commit()
-                state["active"] = False
-                log(f"load step {g.k} converged")
-                continue
-            return rep
+    net = None
+    if args.learned:
+        from paper_1205_1926_amd.warmstart import WarmNet
+        net = WarmNet.load(args.learned, device="cuda:0")
+
+    def load_step():
+        """Newton iterations to convergence and the commit; returns the
+        reports of the iterations that solved."""
+        from paper_1205_1926_amd.warmstart import run_step
+        hist, _ = run_step(g, net=net)
+        return hist
 
     for i in range(args.warmup):
-        rep = solve_step()
-        log(f"warmup step {i}: pcg {rep['pcg_iters']} it, {rep['ms_total']:.1f} ms")
+        hist = load_step()
+        log(f"warmup load step {g.k}: {len(hist)} Newton solves, pcg {[r['pcg_iters'] for r in hist]}")
 
     g.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
     for i in range(args.steps):
-        rep = solve_step()
-        reps.append(rep)
-        log(f"step {i}: newton it {rep['iteration']}, pcg {rep['pcg_iters']} it, fapplies {rep['fapplies']}, "
-            f"relres {rep['relres']:.2e}, plastic gp {rep['plastic_gp']}, {rep['ms_total']:.1f} ms "
-            f"(assembly {rep['ms_assembly']:.1f}, factor {rep['ms_factor']:.1f}, pcg {rep['ms_pcg']:.1f})")
+        hist = load_step()
+        reps.extend(hist)
+        log(f"load step {g.k}: " + ", ".join(
+            f"it {r['iteration']}: pcg {r['pcg_iters']} ({r['warm_choice']}), refac {r['refactored']}, "
+            f"pl {r['plastic_gp']}, {r['ms_total']:.1f} ms" for r in hist))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     k_ms, k_cnt = g.timing()
+    graph_state = g.graph_active()
     g.set_timing(False)
     fapplies = sum(r["fapplies"] for r in reps)
+    pcg_iters = sum(r["pcg_iters"] for r in reps)
     value = fapplies / elapsed
+    sz = g.refresh_sizes()  # tile and schedule chosen by the autotuner
 
-    # isolated F-apply throughput on the last factors
+    # isolated F-apply throughput on the factors of the next load step's
+    # first tangent (the committed state stays as it is)
+    g.begin_load_step()
+    g.assemble(g.zeros(sz["n_torn"]))
+    g.factorize()
     lam = torch.randn(sz["m"], dtype=torch.float64, device="cuda:0")
     q = torch.empty_like(lam)
     g.fapply(lam, q)
@@ -174,7 +214,7 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": elapsed / max(args.steps, 1) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -183,11 +223,19 @@ def main() -> int:
         "config": {"workload": f"{w.name}: unit cube, {sz['n_sub']} box subdomains of 8^3 Q1 hexahedra, "
                                f"{sz['n_torn']} torn DOF, {sz['m']} multipliers, clamped bottom, top traction "
                                f"(compression + shear), load ramp over {w.steps} steps",
-                   "precision": args.precision, "tile": sz["tile"], "preconditioner": "lumped",
-                   "graph": bool(args.graph), "graph_active": g.graph_active(),
+                   "precision": args.precision, "tile": sz["tile"], "schedule": sz["schedule"],
+                   "autotuned": sz["autotuned"], "preconditioner": "lumped",
+                   "graph": bool(args.graph), "graph_active": graph_state,
                    "eps_pcg": w.eps_pcg, "eps_newton": w.eps_newton},
-        "newton_step_ms": elapsed / args.steps * 1e3,
-        "pcg_iters": [r["pcg_iters"] for r in reps],
+        "newton_step_ms": elapsed / max(len(reps), 1) * 1e3,
+        "newton_solves": len(reps),
+        "pcg_iters_total": pcg_iters,
+        "pcg_iters_per_s": pcg_iters / elapsed,
+        "fapplies_total": fapplies,
+        "learned_warm_start": args.learned,
+        "steps_detail": [{k: r[k] for k in ("iteration", "pcg_iters", "fapplies", "refactored", "warm_choice",
+                                             "plastic_gp", "ms_assembly", "ms_factor", "ms_pcg", "ms_total")}
+                         for r in reps],
         "fapply_isolated": {"ms": iso * 1e3, "kernel_ms": iso_kernel_s * 1e3,
                             "applies_per_s": 1.0 / iso,
                             "GB_s_algorithmic": alg_bytes / iso_kernel_s / 1e9},

@@ -96,9 +96,19 @@ typedef struct {
                                    one with the smaller projected initial residual
                                    is used, and cold start if both are not finite */
   int32_t use_graph;            /* replay the PCGP iteration as a HIP graph     */
-  int32_t tile;                 /* factor tile rows 16/32/64; 0 = autotuned     */
+  int32_t tile;                 /* factor tile rows 16/32/64; 0 = autotuned: at
+                                   the first factorization, every tile 16/32/64
+                                   with either subdomain order is timed over 20
+                                   F-applies and the fastest (median) is kept;
+                                   the choice is cached in the file named by the
+                                   environment variable TFETI_AUTOTUNE_CACHE (if
+                                   set), keyed by GPU architecture, precision and
+                                   subdomain-size histogram                      */
   double refine_eps;            /* FP32 mode: inner PCGP tolerance (0 = 1e-4)   */
   int32_t check_every;          /* host polls convergence every N iterations    */
+  int32_t refactor_all;         /* 1: factorize every subdomain each Newton
+                                   iteration; 0: keep the factor of a subdomain
+                                   whose tangent is and was the elastic one      */
 } tfeti_options;
 
 /* ---- reports (host structs) ------------------------------------------- */
@@ -124,7 +134,9 @@ typedef struct {
   double crit;                  /* the paper's increment criterion (Algorithm 2)*/
   double ms_assembly, ms_factor, ms_pcg, ms_total;
   int32_t warm_choice;          /* 0 cold, 1 fallback lambda, 2 learned         */
-  int32_t pad;
+  int32_t refactored;           /* subdomains factorized in this iteration (the
+                                   others kept the factor of their unchanged
+                                   elastic tangent)                              */
 } tfeti_newton_report;
 
 typedef struct {
@@ -134,6 +146,10 @@ typedef struct {
   int64_t factor_bytes;         /* bytes read by one pass over all factors       */
   int32_t tile;                 /* factor tile rows in use                       */
   int32_t precision;
+  int32_t schedule;             /* subdomain order of the solve launch: 0 longest
+                                   first, 1 natural                              */
+  int32_t autotuned;            /* 0 tile fixed by the options, 1 searched by the
+                                   autotuner, 2 taken from its cache             */
 } tfeti_sizes;
 
 typedef struct tfeti_handle tfeti_handle;
@@ -200,7 +216,9 @@ int tfeti_dual_pcg(tfeti_handle* h, const double* f, const double* lambda_guess,
  * the number of plastic Gauss points. */
 int tfeti_assemble(tfeti_handle* h, const double* du, double* fint, int64_t* plastic_count_host);
 
-/* Regularize (fixing nodes, Remark 1) and factorize the assembled tangents. */
+/* Regularize (fixing nodes, Remark 1) and factorize the assembled tangents
+ * (of the subdomains that have a plastic Gauss point or whose factor is not
+ * of the elastic tangent, unless options.refactor_all). */
 int tfeti_factorize(tfeti_handle* h);
 
 /* q = F lambda = B K^+ B^T lambda (m -> m, FP64) with the current factors in

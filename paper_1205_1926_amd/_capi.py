@@ -34,7 +34,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("preconditioner", C.c_int32), ("eps_pcg", C.c_double),
                 ("eps_newton", C.c_double), ("max_pcg", C.c_int32), ("max_newton", C.c_int32),
                 ("warm_start", C.c_int32), ("use_graph", C.c_int32), ("tile", C.c_int32),
-                ("refine_eps", C.c_double), ("check_every", C.c_int32)]
+                ("refine_eps", C.c_double), ("check_every", C.c_int32), ("refactor_all", C.c_int32)]
 
 
 class PcgReport(C.Structure):
@@ -48,14 +48,15 @@ class NewtonReport(C.Structure):
                 ("plastic_gp", C.c_int32), ("plastic_elements", C.c_int32), ("relres", C.c_double),
                 ("crit", C.c_double), ("ms_assembly", C.c_double), ("ms_factor", C.c_double),
                 ("ms_pcg", C.c_double), ("ms_total", C.c_double), ("warm_choice", C.c_int32),
-                ("pad", C.c_int32)]
+                ("refactored", C.c_int32)]
 
 
 class Sizes(C.Structure):
     _fields_ = [("n_sub", C.c_int64), ("n_torn", C.c_int64), ("m", C.c_int64), ("m_G", C.c_int64),
                 ("m_U", C.c_int64), ("l", C.c_int64), ("n_elem", C.c_int64), ("n_gp", C.c_int64),
                 ("n_gdof", C.c_int64), ("skyline_entries", C.c_int64), ("factor_entries", C.c_int64),
-                ("factor_bytes", C.c_int64), ("tile", C.c_int32), ("precision", C.c_int32)]
+                ("factor_bytes", C.c_int64), ("tile", C.c_int32), ("precision", C.c_int32),
+                ("schedule", C.c_int32), ("autotuned", C.c_int32)]
 
 
 class Mlp(C.Structure):
@@ -152,7 +153,8 @@ def make_problem(w):
 
 
 def make_options(w=None, precision=None, eps_pcg=None, eps_newton=None, preconditioner=1, max_pcg=5000,
-                 max_newton=50, warm_start=1, use_graph=0, tile=0, refine_eps=0.0, check_every=8):
+                 max_newton=50, warm_start=1, use_graph=0, tile=0, refine_eps=0.0, check_every=8,
+                 refactor_all=0):
     o = Options()
     prec = precision if precision is not None else (w.precision if w is not None else "fp64")
     o.precision = PREC_FP32 if prec in ("fp32", PREC_FP32) else PREC_FP64
@@ -166,4 +168,5 @@ def make_options(w=None, precision=None, eps_pcg=None, eps_newton=None, precondi
     o.tile = tile
     o.refine_eps = refine_eps
     o.check_every = check_every
+    o.refactor_all = refactor_all
     return o

@@ -250,11 +250,12 @@ void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, double
 }
 
 // K_reg = K + rho Q Q^T at the fixing DOFs, rho = max_j K[j, j] (Remark 1)
-__global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restrict__ subs, int64_t nsub,
+__global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restrict__ subs, int64_t count,
+                                                         const int32_t* __restrict__ list,
                                                          const double* __restrict__ QQt, double* __restrict__ band) {
   __shared__ double red[256];
-  int64_t p = blockIdx.x;
-  if (p >= nsub) return;
+  if ((int64_t)blockIdx.x >= count) return;
+  const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
   const int32_t ndof = subs[p].ndof, Wb = subs[p].Wb, b = subs[p].b;
   const int64_t boff = subs[p].band_off;
   double mx = 0.0;
@@ -277,8 +278,26 @@ __global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restric
   }
 }
 
-void launch_regularize(const SubDev* subs, int64_t nsub, const double* QQt, double* band, hipStream_t st) {
-  regularize_kernel<<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, QQt, band);
+void launch_regularize(const SubDev* subs, int64_t count, const int32_t* list, const double* QQt, double* band,
+                       hipStream_t st) {
+  if (count > 0) regularize_kernel<<<dim3((unsigned)count), dim3(256), 0, st>>>(subs, count, list, QQt, band);
+}
+
+// flags[p] = 1 if a Gauss point of subdomain p is on the plastic branch
+__global__ __launch_bounds__(256) void sub_plastic_kernel(const SubDev* __restrict__ subs, int64_t nsub,
+                                                          const uint8_t* __restrict__ plastic,
+                                                          int32_t* __restrict__ flags) {
+  const int64_t p = blockIdx.x;
+  if (p >= nsub) return;
+  const int64_t g0 = 8 * subs[p].elem_off, ng = 8 * (int64_t)subs[p].n_elem;
+  int any = 0;
+  for (int64_t g = threadIdx.x; g < ng; g += blockDim.x) any |= plastic[g0 + g] != 0;
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) flags[p] = any ? 1 : 0;
+}
+
+void launch_sub_plastic(const SubDev* subs, int64_t nsub, const uint8_t* plastic, int32_t* flags, hipStream_t st) {
+  if (nsub > 0) sub_plastic_kernel<<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, plastic, flags);
 }
 
 }  // namespace tfeti

@@ -5,12 +5,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <string>
 #include <vector>
 
+#include "autotune.h"
 #include "kernels.h"
 #include "model.h"
 
@@ -22,6 +24,16 @@ struct tfeti_handle {
   tfeti_options opt;
   hipStream_t st = nullptr;
   int TS = 32;
+  int natural = 0;              // subdomain schedule: 0 longest first, 1 natural order
+  int tuned = 0;                // 0 fixed tile, 1 searched, 2 from the autotuner cache
+  bool tune_pending = false;
+  double tune_ms = 0.0;
+  int64_t panel_alloc = 0;      // panel storage (entries per layout) allocated
+  // factor reuse: subdomains whose current factor is of the elastic tangent
+  std::vector<uint8_t> fact_elastic;
+  std::vector<int32_t> subpl, flist;
+  int32_t *d_subpl = nullptr, *d_flist = nullptr;
+  int64_t last_refactored = 0;
   int prec = 0;
   int npad_max = 0, max_iface = 0, bmax = 0, chol_nb = 0;
   int64_t panel_entries = 0;
@@ -605,27 +617,156 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   return 0;
 }
 
-int factorize(tfeti_handle* h) {
-  const HostModel& M = h->M;
-  launch_regularize(h->d_subs, M.n_sub, h->d_QQt, h->d_band, h->st);
-  HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
-  launch_convert_band<double>(h->d_band, (double*)h->d_work, M.band_entries, h->st);
-  launch_band_cholesky<double>(h->d_subs, M.n_sub, (double*)h->d_work, h->d_fail, h->bmax, h->chol_nb, h->st);
+// Pack the FP64 band factors of the listed subdomains (all if list is
+// NULL) into the solve panels of the current tile.
+void pack(tfeti_handle* h, int64_t count, const int32_t* list) {
   if (h->prec == TFETI_PREC_FP64) {
-    launch_pack_panels<double, double>(h->d_subs, M.n_sub, (const double*)h->d_work, (double*)h->d_F,
+    launch_pack_panels<double, double>(h->d_subs, count, list, (const double*)h->d_work, (double*)h->d_F,
                                        (double*)h->d_B, h->TS, h->st);
   } else {
-    launch_pack_panels<double, double>(h->d_subs, M.n_sub, (const double*)h->d_work, h->d_F64, h->d_B64, h->TS,
+    launch_pack_panels<double, double>(h->d_subs, count, list, (const double*)h->d_work, h->d_F64, h->d_B64, h->TS,
                                        h->st);
-    launch_pack_panels<double, float>(h->d_subs, M.n_sub, (const double*)h->d_work, (float*)h->d_F,
+    launch_pack_panels<double, float>(h->d_subs, count, list, (const double*)h->d_work, (float*)h->d_F,
                                       (float*)h->d_B, h->TS, h->st);
   }
-  int32_t bad = 0;
-  HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
+}
+
+// Subdomain schedule: longest panel first (stable), or natural order.
+std::vector<int32_t> schedule(const HostModel& M, int natural) {
+  std::vector<int32_t> order(M.n_sub);
+  std::iota(order.begin(), order.end(), 0);
+  if (!natural)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return M.subs[a].panel_len > M.subs[b].panel_len; });
+  return order;
+}
+
+// Re-pack the current factor for tile TS and the given schedule.
+int retile(tfeti_handle* h, int TS, int natural) {
+  HostModel& M = h->M;
+  const int64_t pe = assign_panels(M, TS);
+  if (pe > h->panel_alloc) return fail(h, TFETI_E_INVALID, "internal: panel storage too small for the tile");
+  drop_graphs(h);
+  h->panel_entries = pe;
+  h->TS = TS;
+  h->natural = natural;
+  const std::vector<int32_t> order = schedule(M, natural);
+  HIPCHK(hipMemcpyAsync(h->d_subs, M.subs.data(), M.subs.size() * sizeof(SubDev), hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(h->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
+  pack(h, M.n_sub, nullptr);
   HIPCHK(hipStreamSynchronize(h->st));
   HIPCHK(hipGetLastError());
-  if (bad) return fail(h, TFETI_E_NOT_SPD, "a subdomain factorization met a pivot <= 0");
+  return 0;
+}
+
+// Median duration (ms) of `reps` F-applies in the inner precision, each
+// bracketed by events, after two untimed ones.
+double time_fapply(tfeti_handle* h, int reps) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  std::vector<float> t;
+  for (int r = 0; r < reps + 2; ++r) {
+    (void)hipEventRecord(e0, h->st);
+    fapply(h, h->d_lam, h->d_q, nullptr, nullptr, nullptr);
+    (void)hipEventRecord(e1, h->st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (r >= 2 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (t.empty()) return -1.0;
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+// Autotuner: on the first factorization of a handle set up with tile 0,
+// search tile x schedule by the measured F-apply time, or take the choice
+// cached for the same architecture, precision and subdomain-size histogram
+// (file named by TFETI_AUTOTUNE_CACHE, if set).
+int autotune(tfeti_handle* h) {
+  const HostModel& M = h->M;
+  std::vector<int32_t> nd(M.n_sub);
+  for (int64_t p = 0; p < M.n_sub; ++p) nd[p] = M.subs[p].ndof;
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  const std::string key = tune_key(arch, h->prec, nd);
+  const char* env = std::getenv("TFETI_AUTOTUNE_CACHE");
+  const std::string path = env ? env : "";
+  TuneChoice c;
+  if (!path.empty() && tune_cache_lookup(path, key, &c)) {
+    RC(retile(h, c.tile, c.natural));
+    h->tuned = 2;
+    h->tune_ms = c.ms;
+    return 0;
+  }
+  launch_axpby(M.m, 0.0, nullptr, 0.0, h->d_lam, h->st);
+  TuneChoice best;
+  best.ms = -1.0;
+  for (int TS : {32, 64, 16})
+    for (int nat : {0, 1}) {
+      RC(retile(h, TS, nat));
+      const double ms = time_fapply(h, 20);
+      if (ms > 0 && (best.ms < 0 || ms < best.ms)) {
+        best.tile = TS;
+        best.natural = nat;
+        best.ms = ms;
+      }
+    }
+  if (best.ms < 0) return fail(h, TFETI_E_HIP, "autotuner: no F-apply could be timed");
+  RC(retile(h, best.tile, best.natural));
+  h->tuned = 1;
+  h->tune_ms = best.ms;
+  if (!path.empty()) (void)tune_cache_store(path, key, best);
+  return 0;
+}
+
+// Regularize, factorize and pack.  The tangent of a subdomain without a
+// plastic Gauss point is the elastic stiffness, which depends on geometry and
+// material only; a subdomain whose current factor is of that matrix keeps it
+// (same kernels on the same input: bit-identical), and only the others are
+// factorized again.
+int factorize(tfeti_handle* h) {
+  const HostModel& M = h->M;
+  std::vector<int32_t>& list = h->flist;
+  list.clear();
+  if (h->opt.refactor_all) {
+    for (int64_t p = 0; p < M.n_sub; ++p) list.push_back((int32_t)p);
+  } else {
+    launch_sub_plastic(h->d_subs, M.n_sub, h->d_plastic, h->d_subpl, h->st);
+    HIPCHK(hipMemcpyAsync(h->subpl.data(), h->d_subpl, M.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int64_t p = 0; p < M.n_sub; ++p)
+      if (h->subpl[p] || !h->fact_elastic[p]) list.push_back((int32_t)p);
+  }
+  h->last_refactored = (int64_t)list.size();
+  if (!list.empty()) {
+    HIPCHK(hipMemcpyAsync(h->d_flist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
+    const int64_t cnt = (int64_t)list.size();
+    launch_regularize(h->d_subs, cnt, h->d_flist, h->d_QQt, h->d_band, h->st);
+    HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
+    launch_copy_band(h->d_subs, cnt, h->d_flist, h->d_band, (double*)h->d_work, h->st);
+    launch_band_cholesky<double>(h->d_subs, cnt, h->d_flist, (double*)h->d_work, h->d_fail, h->bmax, h->chol_nb,
+                                 h->st);
+    pack(h, cnt, h->d_flist);
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    HIPCHK(hipGetLastError());
+    if (bad) {
+      for (int32_t p : list) h->fact_elastic[p] = 0;
+      h->factored = false;
+      return fail(h, TFETI_E_NOT_SPD, "a subdomain factorization met a pivot <= 0");
+    }
+    for (int32_t p : list) h->fact_elastic[p] = h->opt.refactor_all ? 0 : (h->subpl[p] ? 0 : 1);
+  }
   h->factored = true;
+  if (h->tune_pending) {
+    h->tune_pending = false;
+    RC(autotune(h));
+  }
   return 0;
 }
 
@@ -669,23 +810,26 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     return fail(h, TFETI_E_INVALID, "precision must be TFETI_PREC_FP64 or TFETI_PREC_FP32");
   h->prec = h->opt.precision;
   int TS = h->opt.tile;
+  h->tune_pending = TS == 0;
   if (TS == 0) TS = 32;
   if (TS != 16 && TS != 32 && TS != 64) return fail(h, TFETI_E_INVALID, "tile must be 0, 16, 32 or 64");
   h->TS = TS;
   std::string msg = build_model(*prob, h->M);
   if (!msg.empty()) return fail(h, TFETI_E_INVALID, msg);
   HostModel& M = h->M;
+  // panel storage: the largest layout among the tiles the autotuner may pick
+  h->panel_alloc = 0;
+  if (h->tune_pending)
+    for (int T : {16, 64}) h->panel_alloc = std::max(h->panel_alloc, assign_panels(M, T));
   h->panel_entries = assign_panels(M, TS);
+  h->panel_alloc = std::max(h->panel_alloc, h->panel_entries);
   for (const SubDev& s : M.subs) {
     h->npad_max = std::max(h->npad_max, s.npad);
     h->max_iface = std::max(h->max_iface, s.n_iface);
     h->bmax = std::max(h->bmax, s.b);
   }
   // schedule: longest subdomain first (stable)
-  std::vector<int32_t> order(M.n_sub);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return M.subs[a].panel_len > M.subs[b].panel_len; });
+  const std::vector<int32_t> order = schedule(M, 0);
   // if_sub map
   std::vector<int32_t> if_sub(M.n_iface);
   for (int64_t p = 0; p < M.n_sub; ++p)
@@ -734,19 +878,19 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   const size_t fsz = h->prec == TFETI_PREC_FP64 ? sizeof(double) : sizeof(float);
   RC(dalloc(h, &h->d_band, M.band_entries));
   if (h->prec == TFETI_PREC_FP32) {
-    RC(dalloc(h, &h->d_F64, std::max<int64_t>(h->panel_entries, 1)));
-    RC(dalloc(h, &h->d_B64, std::max<int64_t>(h->panel_entries, 1)));
+    RC(dalloc(h, &h->d_F64, std::max<int64_t>(h->panel_alloc, 1)));
+    RC(dalloc(h, &h->d_B64, std::max<int64_t>(h->panel_alloc, 1)));
   }
   {
     void* q = nullptr;
     if (hipMalloc(&q, (size_t)M.band_entries * sizeof(double)) != hipSuccess) return fail(h, TFETI_E_OOM, "factor work");
     h->allocs.push_back(q);
     h->d_work = q;
-    if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_entries, 1) * fsz) != hipSuccess)
+    if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_alloc, 1) * fsz) != hipSuccess)
       return fail(h, TFETI_E_OOM, "forward panels");
     h->allocs.push_back(q);
     h->d_F = q;
-    if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_entries, 1) * fsz) != hipSuccess)
+    if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_alloc, 1) * fsz) != hipSuccess)
       return fail(h, TFETI_E_OOM, "backward panels");
     h->allocs.push_back(q);
     h->d_B = q;
@@ -785,6 +929,11 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_S, 1));
   RC(dalloc(h, &h->d_fail, 1));
   RC(dalloc(h, &h->d_plcount, 1));
+  RC(dalloc(h, &h->d_subpl, M.n_sub));
+  RC(dalloc(h, &h->d_flist, M.n_sub));
+  h->fact_elastic.assign(M.n_sub, 0);
+  h->subpl.assign(M.n_sub, 0);
+  h->flist.reserve(M.n_sub);
   RC(dalloc(h, &h->d_Ginv, (int64_t)M.lc * M.lc));
   HIPCHK(hipMemsetAsync(h->d_sigma, 0, 6 * M.n_gp * sizeof(double), h->st));
   HIPCHK(hipMemsetAsync(h->d_kappa, 0, M.n_gp * sizeof(double), h->st));
@@ -829,7 +978,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     SubDev* d_cs = nullptr;
     RC(upload(h, &d_cs, csv));
     HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
-    launch_band_cholesky<double>(d_cs, 1, d_cb, h->d_fail, M.bc, 0, h->st);
+    launch_band_cholesky<double>(d_cs, 1, nullptr, d_cb, h->d_fail, M.bc, 0, h->st);
     launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
@@ -876,6 +1025,8 @@ int tfeti_get_sizes(const tfeti_handle* h, tfeti_sizes* o) {
   o->factor_bytes = h->panel_entries * (h->prec == TFETI_PREC_FP64 ? 8 : 4);
   o->tile = h->TS;
   o->precision = h->prec;
+  o->schedule = h->natural;
+  o->autotuned = h->tuned;
   return TFETI_OK;
 }
 
@@ -935,6 +1086,7 @@ int tfeti_newton_step(tfeti_handle* h, tfeti_newton_report* rep) {
   auto t1 = std::chrono::steady_clock::now();
   RC(factorize(h));
   r.ms_factor = ms_since(t1);
+  r.refactored = (int32_t)h->last_refactored;
   auto t2 = std::chrono::steady_clock::now();
   tfeti_pcg_report pr{};
   // warm-start candidates.  First Newton iteration: the tangent at a zero
@@ -1229,6 +1381,8 @@ extern "C" int tfeti_model_host(const tfeti_problem* prob, int32_t tile, tfeti_s
   sizes->factor_bytes = 0;
   sizes->tile = tile;
   sizes->precision = -1;
+  sizes->schedule = 0;
+  sizes->autotuned = 0;
   if (nnz) *nnz = (int64_t)M.b_col.size();
   if (rowptr) std::memcpy(rowptr, M.b_rowptr.data(), M.b_rowptr.size() * sizeof(int64_t));
   if (col) std::memcpy(col, M.b_col.data(), M.b_col.size() * sizeof(int64_t));

@@ -39,14 +39,15 @@ constexpr int TT = 64;  // trailing-update tile edge
 }  // namespace
 
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t nsub,
+__global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t count,
+                                                            const int32_t* __restrict__ list,
                                                             T* __restrict__ W, int32_t* __restrict__ fail) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* Lp = reinterpret_cast<T*>(smem);          // panel rows x (NB + 1)
   constexpr int LS = NB + 1;
   __shared__ int s_fail;
-  const int64_t p = blockIdx.x;
-  if (p >= nsub) return;
+  if ((int64_t)blockIdx.x >= count) return;
+  const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
   const int b = subs[p].b, Wb = subs[p].Wb, n = subs[p].npad;
   T* A = W + subs[p].band_off;
   const int tid = threadIdx.x;
@@ -175,31 +176,34 @@ int band_cholesky_nb(int bmax, size_t elem) {
 }
 
 template <typename T, int NB>
-static int launch_nb(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, int bmax, hipStream_t st) {
+static int launch_nb(const SubDev* subs, int64_t nsub, const int32_t* list, T* band, int32_t* fail, int bmax,
+                     hipStream_t st) {
   size_t shm = (size_t)(NB + bmax) * (NB + 1) * sizeof(T);
   if (shm > 65536)
     (void)hipFuncSetAttribute((const void*)band_cholesky_kernel<T, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shm);
-  band_cholesky_kernel<T, NB><<<dim3((unsigned)nsub), dim3(256), shm, st>>>(subs, nsub, band, fail);
+  if (nsub > 0) band_cholesky_kernel<T, NB><<<dim3((unsigned)nsub), dim3(256), shm, st>>>(subs, nsub, list, band, fail);
   return 0;
 }
 
 template <typename T>
-int launch_band_cholesky(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, int bmax, int nb,
-                         hipStream_t st) {
+int launch_band_cholesky(const SubDev* subs, int64_t nsub, const int32_t* list, T* band, int32_t* fail, int bmax,
+                         int nb, hipStream_t st) {
   if (nb <= 0) nb = band_cholesky_nb(bmax, sizeof(T));
   switch (nb) {
     case 32:
-      return launch_nb<T, 32>(subs, nsub, band, fail, bmax, st);
+      return launch_nb<T, 32>(subs, nsub, list, band, fail, bmax, st);
     case 16:
-      return launch_nb<T, 16>(subs, nsub, band, fail, bmax, st);
+      return launch_nb<T, 16>(subs, nsub, list, band, fail, bmax, st);
     case 8:
-      return launch_nb<T, 8>(subs, nsub, band, fail, bmax, st);
+      return launch_nb<T, 8>(subs, nsub, list, band, fail, bmax, st);
     default:
       return -1;
   }
 }
-template int launch_band_cholesky<double>(const SubDev*, int64_t, double*, int32_t*, int, int, hipStream_t);
-template int launch_band_cholesky<float>(const SubDev*, int64_t, float*, int32_t*, int, int, hipStream_t);
+template int launch_band_cholesky<double>(const SubDev*, int64_t, const int32_t*, double*, int32_t*, int, int,
+                                          hipStream_t);
+template int launch_band_cholesky<float>(const SubDev*, int64_t, const int32_t*, float*, int32_t*, int, int,
+                                         hipStream_t);
 
 }  // namespace tfeti

@@ -24,6 +24,21 @@ void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st) {
 template void launch_convert_band<double>(const double*, double*, int64_t, hipStream_t);
 template void launch_convert_band<float>(const double*, float*, int64_t, hipStream_t);
 
+// Copy the row-band matrices of the listed subdomains (one workgroup each).
+__global__ __launch_bounds__(256) void copy_band_kernel(const SubDev* __restrict__ subs, int64_t count,
+                                                        const int32_t* __restrict__ list,
+                                                        const double* __restrict__ src, double* __restrict__ dst) {
+  if ((int64_t)blockIdx.x >= count) return;
+  const int64_t p = list[blockIdx.x];
+  const int64_t off = subs[p].band_off, len = (int64_t)subs[p].npad * subs[p].Wb;
+  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) dst[off + i] = src[off + i];
+}
+
+void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, const double* src, double* dst,
+                      hipStream_t st) {
+  if (count > 0) copy_band_kernel<<<dim3((unsigned)count), dim3(256), 0, st>>>(subs, count, list, src, dst);
+}
+
 // Panels.  Tile rows TS, vector width V = 16 bytes / sizeof(T).
 // Forward panel of block row I: off-diagonal columns [I TS - w_I, I TS) then
 // the inverted diagonal tile; chunk (cc, r) of V consecutive columns of row
@@ -31,7 +46,8 @@ template void launch_convert_band<float>(const double*, float*, int64_t, hipStre
 // inverted diagonal tile rows first, then rows [(I+1) TS, (I+1) TS + w'_I);
 // chunk (rc, c) of V consecutive rows of column c is stored at (rc TS + c) V.
 template <typename TW, typename T, int TS>
-__global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restrict__ subs, int64_t nsub,
+__global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restrict__ subs, int64_t count,
+                                                          const int32_t* __restrict__ list,
                                                           const TW* __restrict__ W, T* __restrict__ Fp,
                                                           T* __restrict__ Bp) {
   constexpr int V = 16 / sizeof(T);
@@ -40,8 +56,8 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
   // (sD[c][r] = X[r][c], r > c); sXd holds the diagonal of X.
   __shared__ double sD[TS][TS + 1];
   __shared__ double sXd[TS];
-  const int64_t p = blockIdx.x;
-  if (p >= nsub) return;
+  if ((int64_t)blockIdx.x >= count) return;
+  const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
   const SubDev s = subs[p];
   const TW* A = W + s.band_off;
   T* F = Fp + s.panel_off;
@@ -98,18 +114,21 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
 }
 
 template <typename TW, typename T>
-void launch_pack_panels(const SubDev* subs, int64_t nsub, const TW* band, T* Fp, T* Bp, int TS, hipStream_t st) {
+void launch_pack_panels(const SubDev* subs, int64_t count, const int32_t* list, const TW* band, T* Fp, T* Bp, int TS,
+                        hipStream_t st) {
+  if (count <= 0) return;
+  dim3 grid((unsigned)count);
   if (TS == 16)
-    pack_panels_kernel<TW, T, 16><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 16><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp);
   else if (TS == 32)
-    pack_panels_kernel<TW, T, 32><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 32><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp);
   else
-    pack_panels_kernel<TW, T, 64><<<dim3((unsigned)nsub), dim3(256), 0, st>>>(subs, nsub, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 64><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp);
 }
-template void launch_pack_panels<double, double>(const SubDev*, int64_t, const double*, double*, double*, int,
-                                                 hipStream_t);
-template void launch_pack_panels<double, float>(const SubDev*, int64_t, const double*, float*, float*, int,
-                                                hipStream_t);
+template void launch_pack_panels<double, double>(const SubDev*, int64_t, const int32_t*, const double*, double*,
+                                                 double*, int, hipStream_t);
+template void launch_pack_panels<double, float>(const SubDev*, int64_t, const int32_t*, const double*, float*,
+                                                float*, int, hipStream_t);
 
 // Dense inverse of the coarse matrix from its banded Cholesky factor L
 // (row-band, l rows, half bandwidth b): thread j solves L L^T x = e_j and

@@ -33,13 +33,19 @@ void launch_return_map(const tfeti_material& mat, int64_t npts, const double* si
 void launch_assemble(const AssembleArgs& args, hipStream_t st);
 void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStream_t st);
 void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, double* out, hipStream_t st);
-void launch_regularize(const SubDev* subs, int64_t nsub, const double* QQt, double* band, hipStream_t st);
+// list: subdomain indices (count of them), or NULL for subdomains 0 .. count-1
+void launch_regularize(const SubDev* subs, int64_t count, const int32_t* list, const double* QQt, double* band,
+                       hipStream_t st);
+void launch_sub_plastic(const SubDev* subs, int64_t nsub, const uint8_t* plastic, int32_t* flags, hipStream_t st);
+void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, const double* src, double* dst,
+                      hipStream_t st);
 
 // ---- factorization -------------------------------------------------------
 // In-place band Cholesky of every subdomain's row-band matrix (type T).
 // bmax: largest half bandwidth; nb: block columns (0 = largest that fits LDS).
 template <typename T>
-int launch_band_cholesky(const SubDev* subs, int64_t nsub, T* band, int32_t* fail, int bmax, int nb, hipStream_t st);
+int launch_band_cholesky(const SubDev* subs, int64_t nsub, const int32_t* list, T* band, int32_t* fail, int bmax,
+                         int nb, hipStream_t st);
 int band_cholesky_nb(int bmax, size_t elem);
 // Convert the FP64 row-band K_reg into the factor work buffer of type T.
 template <typename T>
@@ -48,7 +54,8 @@ void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st);
 // diagonal tiles.
 // (factor in TW, panels in T: FP64 -> FP64 or FP64 -> FP32)
 template <typename TW, typename T>
-void launch_pack_panels(const SubDev* subs, int64_t nsub, const TW* band, T* Fp, T* Bp, int TS, hipStream_t st);
+void launch_pack_panels(const SubDev* subs, int64_t count, const int32_t* list, const TW* band, T* Fp, T* Bp, int TS,
+                        hipStream_t st);
 // Dense inverse of the coarse matrix from its banded Cholesky factor.
 void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st);
 

@@ -9,6 +9,14 @@
 // stream the off-diagonal panel chunks (16-byte loads, one output row per
 // lane, coalesced) and accumulate partial dot products; wave 0 reduces them
 // and applies the inverted diagonal tile with lane broadcasts.
+//
+// The panels are rectangles, but a factor row is zero left of the first
+// column of its envelope (Cholesky keeps the envelope of the node lattice:
+// row 3q + c starts at node q minus one step along every axis on which q is
+// not on the lower boundary), and the inverted diagonal tiles are
+// triangular.  Lanes skip the loads of chunks that lie entirely in those zero
+// parts (the backward pass with the interior envelope, a bound that is
+// monotone in the row), so the bytes read approach the envelope (skyline).
 #include "kernels.h"
 
 namespace tfeti {
@@ -58,6 +66,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
   constexpr int V = Vec<T>::V;
   constexpr int NT = 256;
   constexpr int RPT = NT / TS;           // threads per tile row
+  constexpr int UNR = 8;                 // panel chunks loaded back to back per lane
   extern __shared__ __align__(16) unsigned char smem[];
   T* xs = reinterpret_cast<T*>(smem);
   T* part = xs + A.part_off;             // after the largest subdomain vector
@@ -67,6 +76,11 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
   const int32_t p = A.order[blockIdx.x];
   const SubDev s = A.subs[p];
   const int n = s.npad, nb = n / TS;
+
+  // node counts along the two fastest axes of the factor ordering
+  const int pa = s.perm[0], pb = s.perm[1];
+  const int N0 = pa == 0 ? s.N[0] : (pa == 1 ? s.N[1] : s.N[2]);
+  const int N1 = pb == 0 ? s.N[0] : (pb == 1 ? s.N[1] : s.N[2]);
 
   // ---- input: x = in_full (factor order) + lam_sign B^T lam ----
   for (int i = tid; i < n; i += NT) xs[i] = T(0);
@@ -96,7 +110,25 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
       const int nco = w / V;
       const int c0 = I * TS - w;
       T acc = T(0);
-      for (int cc = tid / TS; cc < nco; cc += RPT) {
+      // first envelope column of the row (padding rows: the diagonal), and
+      // the first chunk holding a column at or after it
+      int fc = I * TS + r;
+      if (fc < s.ndof) {
+        const int q = fc / 3, i0 = q % N0, t = q / N0, i1 = t % N1, i2 = t / N1;
+        fc = 3 * (q - (i0 > 0) - (i1 > 0) * N0 - (i2 > 0) * N0 * N1);
+      }
+      const int cmin = fc > c0 ? (fc - c0) / V : 0;
+      int cc = tid / TS;
+      if (cc < cmin) cc += (cmin - cc + RPT - 1) / RPT * RPT;
+      // UNR chunk loads in flight per lane, then their products
+      for (; cc + (UNR - 1) * RPT < nco; cc += UNR * RPT) {
+        VT L[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) L[u] = *reinterpret_cast<const VT*>(P + off + ((int64_t)(cc + u * RPT) * TS + r) * V);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) acc += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs + c0 + (cc + u * RPT) * V));
+      }
+      for (; cc < nco; cc += RPT) {
         VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)cc * TS + r) * V);
         VT y = *reinterpret_cast<const VT*>(xs + c0 + cc * V);
         acc += vdot<VT, V>(L, y);
@@ -115,7 +147,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
 #pragma unroll
         for (int cc = 0; cc < TS / V; ++cc) {
           VT L;
-          if (tid < TS)
+          if (tid < TS && cc * V <= tid)  // the inverse of a lower triangle is lower
             L = *reinterpret_cast<const VT*>(P + off + ((int64_t)(nco + cc) * TS + tid) * V);
           else
             L = VT(T(0));
@@ -141,7 +173,30 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
       const int nco = w / V;
       const int rbase = (I + 1) * TS;
       T acc = T(0);
-      for (int rr = tid / TS; rr < nco; rr += RPT) {
+      // rows below the block that can reach column I TS + c: no row of node
+      // q starts before node q - 1 - N0 - N0 N1, so rows past the last DOF of
+      // node col/3 + 1 + N0 + N0 N1 are zero in this column, and so are the
+      // padding rows; rend = the chunks before that row
+      int rend;
+      {
+        const int col = I * TS + c;
+        int last = 3 * (col / 3 + 1 + N0 + N0 * N1) + 2;
+        if (last > s.ndof - 1) last = s.ndof - 1;
+        int cnt = last + 1 - rbase;
+        cnt = cnt < 0 ? 0 : (cnt > nco * V ? nco * V : cnt);
+        rend = (cnt + V - 1) / V;
+      }
+      int rr = tid / TS;
+      for (; rr + (UNR - 1) * RPT < rend; rr += UNR * RPT) {
+        VT L[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+          L[u] = *reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr + u * RPT) * TS + c) * V);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+          acc += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs + rbase + (rr + u * RPT) * V));
+      }
+      for (; rr < rend; rr += RPT) {
         VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr) * TS + c) * V);
         VT z = *reinterpret_cast<const VT*>(xs + rbase + rr * V);
         acc += vdot<VT, V>(L, z);
@@ -160,7 +215,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
 #pragma unroll
         for (int rc = 0; rc < TS / V; ++rc) {
           VT L;
-          if (tid < TS)
+          if (tid < TS && rc * V + V - 1 >= tid)  // the inverse transpose is upper
             L = *reinterpret_cast<const VT*>(P + off + ((int64_t)rc * TS + tid) * V);
           else
             L = VT(T(0));

@@ -43,9 +43,7 @@ class GpuSolver:
                 self.lib.tfeti_destroy(h)
             self.h = None
             raise A.TfetiError(f"tfeti_setup: {rc}: {msg}")
-        s = A.Sizes()
-        self._check(self.lib.tfeti_get_sizes(self.h, C.byref(s)), "get_sizes")
-        self.sizes = A.struct_dict(s)
+        self.refresh_sizes()
         self.k = 0
 
     # ------------------------------------------------------------------ plumbing
@@ -53,6 +51,14 @@ class GpuSolver:
         if rc < 0:
             raise A.TfetiError(f"{what}: {rc}: {self.lib.tfeti_last_error(self.h).decode()}")
         return rc
+
+    def refresh_sizes(self):
+        """Re-read the sizes (tile and schedule change when the autotuner runs
+        at the first factorization)."""
+        s = A.Sizes()
+        self._check(self.lib.tfeti_get_sizes(self.h, C.byref(s)), "get_sizes")
+        self.sizes = A.struct_dict(s)
+        return self.sizes
 
     def zeros(self, n, dtype=None):
         torch = _torch()

@@ -262,6 +262,46 @@ def test_other_tiles(tile, dev):
     assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-9
 
 
+def test_autotuner_choice_and_cache(tmp_path, monkeypatch, dev):
+    """tile = 0: the first factorization times every tile and schedule and
+    keeps the fastest; F still matches the oracle; the choice is written to
+    the cache and the next handle of the same problem takes it from there."""
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("TFETI_AUTOTUNE_CACHE", str(cache))
+    P = Pair(W.config(0), dev, tile=0)
+    sz = P.g.refresh_sizes()
+    assert sz["autotuned"] == 1 and sz["tile"] in (16, 32, 64) and sz["schedule"] in (0, 1)
+    rng = np.random.default_rng(12)
+    lam = rng.standard_normal(P.mesh.m)
+    assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-9
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and '"tile": %d' % sz["tile"] in lines[0]
+    Q = Pair(W.config(0), dev, tile=0)
+    sq = Q.g.refresh_sizes()
+    assert sq["autotuned"] == 2 and sq["tile"] == sz["tile"] and sq["schedule"] == sz["schedule"]
+    assert len(cache.read_text().splitlines()) == 1
+
+
+def test_elastic_factor_reuse_is_exact(dev):
+    """Keeping the factor of subdomains whose tangent is and was elastic gives
+    bit-identical results to factorizing every subdomain each iteration."""
+    from paper_1205_1926_amd import GpuSolver
+    w = W.small_cube(S=(3, 2, 2), n=(3, 3, 3), amp=650.0, shear=150.0, steps=3)
+    runs = {}
+    for flag in (0, 1):
+        g = GpuSolver(w, refactor_all=flag, tile=32)
+        hist = g.run()
+        runs[flag] = (hist, N(g.state()["u"]), N(g.lam()))
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.array_equal(runs[0][2], runs[1][2])
+    n_sub = 12
+    counts = [r["refactored"] for h in runs[0][0] for r in h]
+    assert counts[0] == n_sub
+    assert min(counts) < n_sub          # elastic subdomains kept their factors
+    assert all(r["refactored"] == n_sub for h in runs[1][0] for r in h)
+    assert [len(h) for h in runs[0][0]] == [len(h) for h in runs[1][0]]
+
+
 def test_fapply_deterministic(pair0, dev):
     rng = np.random.default_rng(8)
     lam = T(rng.standard_normal(pair0.mesh.m), dev)
