@@ -104,7 +104,10 @@ typedef struct {
                                    environment variable TFETI_AUTOTUNE_CACHE (if
                                    set), keyed by GPU architecture, precision and
                                    subdomain-size histogram                      */
-  double refine_eps;            /* FP32 mode: inner PCGP tolerance (0 = 1e-4)   */
+  double refine_eps;            /* FP32 mode: smallest inner PCGP tolerance
+                                   relative to the outer residual (0 = 1e-5);
+                                   each sweep aims at half the reduction still
+                                   needed, but not below this                    */
   int32_t check_every;          /* host polls convergence every N iterations    */
   int32_t refactor_all;         /* 1: factorize every subdomain each Newton
                                    iteration; 0: keep the factor of a subdomain

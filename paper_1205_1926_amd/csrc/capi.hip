@@ -516,7 +516,7 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
     converged = Sh.done == 1;
     r_final = Sh.rr;
   } else {
-    const double eps_in = h->opt.refine_eps > 0 ? h->opt.refine_eps : 1e-5;
+    const double eps_floor = h->opt.refine_eps > 0 ? h->opt.refine_eps : 1e-5;
     const int max_outer = 50;
     for (;;) {
       // outer residual r = d~ - F64 lambda_acc (FP64), rho = P r (already in
@@ -542,6 +542,9 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
       }
       // inner PCGP on P F32 delta = rho from delta = 0
       launch_axpby(m, 0.0, nullptr, 0.0, h->d_lam_ker, h->st);
+      // inner tolerance: the reduction still needed (with a factor 2 of
+      // margin), but not below what the FP32 operator can be trusted with
+      const double eps_in = std::min(0.5, std::max(eps_floor, 0.5 * h->opt.eps_pcg * r_ref / nrho));
       int st = pcg_loop(h, eps_in, h->opt.max_pcg - total_iters, &Sh);
       if (st < 0) return st;
       total_iters += Sh.iters;
@@ -624,10 +627,9 @@ void pack(tfeti_handle* h, int64_t count, const int32_t* list) {
     launch_pack_panels<double, double>(h->d_subs, count, list, (const double*)h->d_work, (double*)h->d_F,
                                        (double*)h->d_B, h->TS, h->st);
   } else {
+    // FP64 panels (outer refinement) and FP32 panels (inner iterations) in one pass
     launch_pack_panels<double, double>(h->d_subs, count, list, (const double*)h->d_work, h->d_F64, h->d_B64, h->TS,
-                                       h->st);
-    launch_pack_panels<double, float>(h->d_subs, count, list, (const double*)h->d_work, (float*)h->d_F,
-                                      (float*)h->d_B, h->TS, h->st);
+                                       h->st, (float*)h->d_F, (float*)h->d_B);
   }
 }
 

@@ -11,9 +11,9 @@
 // reaches, at most NB + b rows) is staged in LDS; wave 0 factors the
 // diagonal tile in registers (lane = row, lane broadcasts); the rows below
 // are solved against it in LDS; the panel is written back and the trailing
-// band window is updated in 64 x 64 tiles straight from the LDS panel (each
-// thread owns a 4 x 4 block of outputs), so global traffic is one
-// read-modify-write of the window per block column.
+// band window is updated from the LDS panel in 16 x 16 blocks on the FP64
+// matrix cores (FP32: 64 x 64 tiles, 4 x 4 outputs per thread), so global
+// traffic is one read-modify-write of the window per block column.
 #include "kernels.h"
 
 namespace tfeti {
@@ -58,12 +58,20 @@ __global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __rest
     int rend = J + jb + b;
     if (rend > n) rend = n;
     const int nr = rend - J;                      // panel rows (>= jb)
-    // ---- stage the panel ----
-    for (int q = tid; q < nr * NB; q += blockDim.x) {
-      const int r = q / NB, j = q - (q / NB) * NB;
-      T v = T(0);
-      if (j < jb && j <= r && r - j <= b) v = A[(int64_t)(J + r) * Wb + (j - r + b)];
-      Lp[r * LS + j] = v;
+    // ---- stage the panel (8 loads in flight per thread) ----
+    for (int q0 = tid; q0 < nr * NB; q0 += 8 * 256) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * 256;
+        const int r = q / NB, j = q - (q / NB) * NB;
+        v[u] = (q < nr * NB && j < jb && j <= r && r - j <= b) ? A[(int64_t)(J + r) * Wb + (j - r + b)] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + u * 256;
+        if (q < nr * NB) Lp[(q / NB) * LS + (q - (q / NB) * NB)] = v[u];
+      }
     }
     __syncthreads();
     // ---- diagonal tile: wave 0, lane = row, in registers ----
@@ -98,15 +106,23 @@ __global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __rest
       }
     }
     __syncthreads();
-    // ---- rows below: x := x L_JJ^{-T} in LDS ----
+    // ---- rows below: x := x L_JJ^{-T}, the row in registers, the tile
+    //      entries read by every lane at the same LDS address ----
     for (int r = jb + tid; r < nr; r += blockDim.x) {
-      T* row = Lp + r * LS;
-      for (int j = 0; j < jb; ++j) {
-        T v = row[j];
-        const T* lj = Lp + j * LS;
-        for (int k = 0; k < j; ++k) v -= row[k] * lj[k];
-        row[j] = v / lj[j];
+      T x[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) x[j] = Lp[r * LS + j];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < jb) {
+          T v = x[j];
+#pragma unroll
+          for (int k = 0; k < j; ++k) v -= x[k] * Lp[j * LS + k];
+          x[j] = v / Lp[j * LS + j];
+        }
       }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) Lp[r * LS + j] = x[j];
     }
     __syncthreads();
     // ---- write the panel back ----
@@ -115,42 +131,95 @@ __global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __rest
       if (j < jb && j <= r && r - j <= b) A[(int64_t)(J + r) * Wb + (j - r + b)] = Lp[r * LS + j];
     }
     // ---- trailing update from the LDS panel (columns >= J + jb only) ----
-    const int rbeg = J + jb;
-    const int ty = tid / 16, tx = tid % 16;
-    for (int RT = rbeg; RT < rend; RT += TT) {
-      for (int CT = rbeg; CT <= RT; CT += TT) {
-        if (RT - (CT + TT - 1) > b) continue;
-        int ri[4], ci[4];
+    if constexpr (sizeof(T) == 8) {
+      // 16 x 16 blocks of the lower band window on the FP64 matrix cores:
+      // block (RB, CB) accumulates P_R P_C^T over the panel columns, 4 at a
+      // time (lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; output r
+      // of lane l is D[l / 16 + 4 r][l % 16])
+      const int nwin = nr - jb, nbw = (nwin + 15) / 16;
+      const int wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
+      const int nblk = nbw * (nbw + 1) / 2;
+      typedef double d4 __attribute__((ext_vector_type(4)));
+      constexpr int BT = 4;  // blocks per batch: their window loads are in flight together
+      for (int q0 = wave; q0 < nblk; q0 += 4 * BT) {
+        int ra[BT], rb[BT], row0[BT], col[BT];
+        bool ok[BT];
+        T c[BT][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          int r = RT + ty * 4 + u - J;
-          ri[u] = (r < nr ? r : nr - 1) * LS;
-          int c = CT + tx + 16 * u - J;
-          ci[u] = (c < nr ? c : nr - 1) * LS;
+        for (int t = 0; t < BT; ++t) {
+          const int q = q0 + 4 * t;
+          int RB = (int)sqrtf(2.0f * (float)q);
+          while (RB * (RB + 1) / 2 > q) --RB;
+          while ((RB + 1) * (RB + 2) / 2 <= q) ++RB;
+          const int CB = q - RB * (RB + 1) / 2;
+          ok[t] = q < nblk && RB * 16 - (CB * 16 + 15) <= b;  // inside the band
+          ra[t] = jb + RB * 16 + li;
+          rb[t] = jb + CB * 16 + li;
+          row0[t] = J + jb + RB * 16 + lk;
+          col[t] = J + jb + CB * 16 + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = row0[t] + 4 * r;
+            const bool in = ok[t] && row < rend && col[t] <= row && row - col[t] <= b;
+            c[t][r] = in ? A[(int64_t)row * Wb + (col[t] - row + b)] : T(0);
+          }
         }
-        T acc[4][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int t = 0; t < BT; ++t) {
+          if (!ok[t]) continue;
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+          for (int k0 = 0; k0 < jb; k0 += 4) {
+            const int k = k0 + lk;
+            const double av = (ra[t] < nr && k < jb) ? (double)Lp[ra[t] * LS + k] : 0.0;
+            const double bv = (rb[t] < nr && k < jb) ? (double)Lp[rb[t] * LS + k] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+          }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-        for (int k = 0; k < jb; ++k) {
-          T ra[4], cb[4];
+          for (int r = 0; r < 4; ++r) {
+            const int row = row0[t] + 4 * r;
+            if (row < rend && col[t] <= row && row - col[t] <= b)
+              A[(int64_t)row * Wb + (col[t] - row + b)] = c[t][r] - (T)acc[r];
+          }
+        }
+      }
+    } else {
+      const int rbeg = J + jb;
+      const int ty = tid / 16, tx = tid % 16;
+      for (int RT = rbeg; RT < rend; RT += TT) {
+        for (int CT = rbeg; CT <= RT; CT += TT) {
+          if (RT - (CT + TT - 1) > b) continue;
+          int ri[4], ci[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) ra[u] = Lp[ri[u] + k];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) cb[v] = Lp[ci[v] + k];
+          for (int u = 0; u < 4; ++u) {
+            int r = RT + ty * 4 + u - J;
+            ri[u] = (r < nr ? r : nr - 1) * LS;
+            int c = CT + tx + 16 * u - J;
+            ci[u] = (c < nr ? c : nr - 1) * LS;
+          }
+          T acc[4][4];
 #pragma unroll
           for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] += ra[u] * cb[v];
-        }
+            for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
+          for (int k = 0; k < jb; ++k) {
+            T ra[4], cb[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) ra[u] = Lp[ri[u] + k];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = RT + ty * 4 + u, c = CT + tx + 16 * v;
-            if (r < rend && c <= r && r - c <= b) A[(int64_t)r * Wb + (c - r + b)] -= acc[u][v];
+            for (int v = 0; v < 4; ++v) cb[v] = Lp[ci[v] + k];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[u][v] += ra[u] * cb[v];
           }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int r = RT + ty * 4 + u, c = CT + tx + 16 * v;
+              if (r < rend && c <= r && r - c <= b) A[(int64_t)r * Wb + (c - r + b)] -= acc[u][v];
+            }
+        }
       }
     }
     __syncthreads();

@@ -24,19 +24,21 @@ void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st) {
 template void launch_convert_band<double>(const double*, double*, int64_t, hipStream_t);
 template void launch_convert_band<float>(const double*, float*, int64_t, hipStream_t);
 
-// Copy the row-band matrices of the listed subdomains (one workgroup each).
+// Copy the row-band matrices of the listed subdomains: blockIdx.y picks the
+// subdomain, the blockIdx.x slices stride over its entries.
 __global__ __launch_bounds__(256) void copy_band_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                         const int32_t* __restrict__ list,
                                                         const double* __restrict__ src, double* __restrict__ dst) {
-  if ((int64_t)blockIdx.x >= count) return;
-  const int64_t p = list[blockIdx.x];
+  if ((int64_t)blockIdx.y >= count) return;
+  const int64_t p = list[blockIdx.y];
   const int64_t off = subs[p].band_off, len = (int64_t)subs[p].npad * subs[p].Wb;
-  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) dst[off + i] = src[off + i];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    dst[off + i] = src[off + i];
 }
 
 void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, const double* src, double* dst,
                       hipStream_t st) {
-  if (count > 0) copy_band_kernel<<<dim3((unsigned)count), dim3(256), 0, st>>>(subs, count, list, src, dst);
+  if (count > 0) copy_band_kernel<<<dim3(32, (unsigned)count), dim3(256), 0, st>>>(subs, count, list, src, dst);
 }
 
 // Panels.  Tile rows TS, vector width V = 16 bytes / sizeof(T).
@@ -49,24 +51,41 @@ template <typename TW, typename T, int TS>
 __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                           const int32_t* __restrict__ list,
                                                           const TW* __restrict__ W, T* __restrict__ Fp,
-                                                          T* __restrict__ Bp) {
+                                                          T* __restrict__ Bp, float* __restrict__ Fq,
+                                                          float* __restrict__ Bq) {
   constexpr int V = 16 / sizeof(T);
   // sD holds the diagonal tile L in its lower triangle and, after the
   // inversion, X = L^{-1} transposed in its strict upper triangle
   // (sD[c][r] = X[r][c], r > c); sXd holds the diagonal of X.
   __shared__ double sD[TS][TS + 1];
   __shared__ double sXd[TS];
-  if ((int64_t)blockIdx.x >= count) return;
-  const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
+  if ((int64_t)blockIdx.y >= count) return;
+  const int64_t p = list ? list[blockIdx.y] : blockIdx.y;
   const SubDev s = subs[p];
   const TW* A = W + s.band_off;
   T* F = Fp + s.panel_off;
   T* Bk = Bp + s.panel_off;
+  // optional second copy in FP32 (its own chunk width V2) from the same pass
+  constexpr int V2 = 4;
+  float* F2 = Fq ? Fq + s.panel_off : nullptr;
+  float* B2 = Bq ? Bq + s.panel_off : nullptr;
   const int b = s.b, Wb = s.Wb, n = s.npad, nb = n / TS;
   const int tid = threadIdx.x;
   auto L = [&](int r, int c) -> T { return (c <= r && r - c <= b && c >= 0) ? (T)A[(int64_t)r * Wb + (c - r + b)] : T(0); };
-  int64_t offF = 0, offB = 0;
-  for (int I = 0; I < nb; ++I) {
+  // block rows I = blockIdx.x, blockIdx.x + gridDim.x, ...; the panel
+  // offsets of block row I are sums over the rows before it (closed form:
+  // widths min(I TS, bo) forward and min(n - (I+1) TS, bo) backward)
+  for (int I = blockIdx.x; I < nb; I += gridDim.x) {
+    int64_t offF = 0, offB = 0;
+    {
+      const int kF = (s.bo + TS - 1) / TS;  // block rows with I TS < bo
+      const int m1 = I < kF ? I : kF;
+      offF = (int64_t)TS * ((int64_t)TS * m1 * (m1 - 1) / 2 + (int64_t)(I - m1) * s.bo + (int64_t)I * TS);
+      for (int J = 0; J < I; ++J) {
+        const int remJ = n - (J + 1) * TS;
+        offB += (int64_t)TS * (TS + (remJ < s.bo ? remJ : s.bo));
+      }
+    }
     const int wF = I * TS < s.bo ? I * TS : s.bo;
     const int rem = n - (I + 1) * TS;
     const int wB = rem < s.bo ? rem : s.bo;
@@ -94,41 +113,47 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
       T v = (T)x;
       F[offF + ((int64_t)((wF + c) / V) * TS + r) * V + (c % V)] = v;
       Bk[offB + ((int64_t)(r / V) * TS + c) * V + (r % V)] = v;
+      if (F2) {
+        F2[offF + ((int64_t)((wF + c) / V2) * TS + r) * V2 + (c % V2)] = (float)x;
+        B2[offB + ((int64_t)(r / V2) * TS + c) * V2 + (r % V2)] = (float)x;
+      }
     }
     // off-diagonal part of the forward panel: columns I TS - wF .. I TS - 1
     for (int64_t q = tid; q < (int64_t)TS * wF; q += blockDim.x) {
       int r = (int)(q % TS), cc = (int)(q / TS);
       int col = I * TS - wF + cc;
-      F[offF + ((int64_t)(cc / V) * TS + r) * V + (cc % V)] = L(I * TS + r, col);
+      const T v = L(I * TS + r, col);
+      F[offF + ((int64_t)(cc / V) * TS + r) * V + (cc % V)] = v;
+      if (F2) F2[offF + ((int64_t)(cc / V2) * TS + r) * V2 + (cc % V2)] = (float)v;
     }
     // off-diagonal part of the backward panel: rows (I+1) TS .. + wB - 1
     for (int64_t q = tid; q < (int64_t)TS * wB; q += blockDim.x) {
       int c = (int)(q % TS), rr = (int)(q / TS);
       int row = (I + 1) * TS + rr;
-      Bk[offB + ((int64_t)((TS + rr) / V) * TS + c) * V + ((TS + rr) % V)] = L(row, I * TS + c);
+      const T v = L(row, I * TS + c);
+      Bk[offB + ((int64_t)((TS + rr) / V) * TS + c) * V + ((TS + rr) % V)] = v;
+      if (B2) B2[offB + ((int64_t)((TS + rr) / V2) * TS + c) * V2 + ((TS + rr) % V2)] = (float)v;
     }
-    offF += (int64_t)TS * (wF + TS);
-    offB += (int64_t)TS * (TS + wB);
     __syncthreads();
   }
 }
 
 template <typename TW, typename T>
 void launch_pack_panels(const SubDev* subs, int64_t count, const int32_t* list, const TW* band, T* Fp, T* Bp, int TS,
-                        hipStream_t st) {
+                        hipStream_t st, float* Fq, float* Bq) {
   if (count <= 0) return;
-  dim3 grid((unsigned)count);
+  dim3 grid(64, (unsigned)count);  // block rows x subdomains
   if (TS == 16)
-    pack_panels_kernel<TW, T, 16><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 16><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp, Fq, Bq);
   else if (TS == 32)
-    pack_panels_kernel<TW, T, 32><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 32><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp, Fq, Bq);
   else
-    pack_panels_kernel<TW, T, 64><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp);
+    pack_panels_kernel<TW, T, 64><<<grid, dim3(256), 0, st>>>(subs, count, list, band, Fp, Bp, Fq, Bq);
 }
 template void launch_pack_panels<double, double>(const SubDev*, int64_t, const int32_t*, const double*, double*,
-                                                 double*, int, hipStream_t);
+                                                 double*, int, hipStream_t, float*, float*);
 template void launch_pack_panels<double, float>(const SubDev*, int64_t, const int32_t*, const double*, float*,
-                                                float*, int, hipStream_t);
+                                                float*, int, hipStream_t, float*, float*);
 
 // Dense inverse of the coarse matrix from its banded Cholesky factor L
 // (row-band, l rows, half bandwidth b): thread j solves L L^T x = e_j and

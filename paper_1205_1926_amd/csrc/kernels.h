@@ -54,8 +54,9 @@ void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st);
 // diagonal tiles.
 // (factor in TW, panels in T: FP64 -> FP64 or FP64 -> FP32)
 template <typename TW, typename T>
+// Fq, Bq (optional): FP32 copies of the panels written in the same pass
 void launch_pack_panels(const SubDev* subs, int64_t count, const int32_t* list, const TW* band, T* Fp, T* Bp, int TS,
-                        hipStream_t st);
+                        hipStream_t st, float* Fq = nullptr, float* Bq = nullptr);
 // Dense inverse of the coarse matrix from its banded Cholesky factor.
 void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st);
 
