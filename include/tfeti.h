@@ -98,8 +98,9 @@ typedef struct {
   int32_t use_graph;            /* replay the PCGP iteration as a HIP graph     */
   int32_t tile;                 /* factor tile rows 16/32/64; 0 = autotuned: at
                                    the first factorization, every tile 16/32/64
-                                   with either subdomain order is timed over 20
-                                   F-applies and the fastest (median) is kept;
+                                   with either subdomain order is timed (median
+                                   of 20 F-applies x 40 + one panel packing) and
+                                   the cheapest is kept;
                                    the choice is cached in the file named by the
                                    environment variable TFETI_AUTOTUNE_CACHE (if
                                    set), keyed by GPU architecture, precision and

@@ -124,6 +124,12 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise TfetiError(f"{path} is missing: build it with paper_1205_1926_amd.build.build()")
+    # torch brings its own HIP runtime; load it first so that the library
+    # binds to the same one instead of starting a second runtime
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

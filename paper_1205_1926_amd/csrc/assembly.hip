@@ -239,15 +239,19 @@ void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStre
 }
 
 // K_bb values for the lumped preconditioner (before regularization)
+template <typename T>
 __global__ void gather_kbb_kernel(const int64_t* __restrict__ pos, int64_t n, const double* __restrict__ band,
-                                  double* __restrict__ out) {
+                                  T* __restrict__ out) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) out[q] = band[pos[q]];
+  if (q < n) out[q] = (T)band[pos[q]];
 }
 
-void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, double* out, hipStream_t st) {
-  if (n > 0) gather_kbb_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(pos, n, band, out);
+template <typename T>
+void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, T* out, hipStream_t st) {
+  if (n > 0) gather_kbb_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(pos, n, band, out);
 }
+template void launch_gather_kbb<double>(const int64_t*, int64_t, const double*, double*, hipStream_t);
+template void launch_gather_kbb<float>(const int64_t*, int64_t, const double*, float*, hipStream_t);
 
 // K_reg = K + rho Q Q^T at the fixing DOFs, rho = max_j K[j, j] (Remark 1)
 __global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restrict__ subs, int64_t count,

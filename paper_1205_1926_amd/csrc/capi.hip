@@ -47,9 +47,11 @@ struct tfeti_handle {
   int32_t* d_b_iface = nullptr;
   double* d_b_val = nullptr;
   double *d_R_full = nullptr, *d_R_iface = nullptr;
-  int32_t *d_kbb_rp = nullptr, *d_kbb_col = nullptr;
+  int32_t* d_kbb_rp = nullptr;
+  uint16_t* d_kbb_col = nullptr;  // local to the subdomain's touched DOFs
   int64_t* d_kbb_band = nullptr;
-  double* d_kbb_val = nullptr;
+  double* d_kbb_val = nullptr;    // FP64 mode
+  float* d_kbb_val32 = nullptr;   // FP32 mode
   int64_t* d_g_first = nullptr;
   int32_t* d_g_rp = nullptr;
   int64_t* d_g_copies = nullptr;
@@ -72,7 +74,7 @@ struct tfeti_handle {
          *d_delta = nullptr;
   // PCGP work
   double *d_lam = nullptr, *d_lam_im = nullptr, *d_lam_ker = nullptr, *d_r = nullptr, *d_w = nullptr,
-         *d_z = nullptr, *d_y = nullptr, *d_p = nullptr, *d_q = nullptr, *d_d = nullptr, *d_lam_prev = nullptr,
+         *d_z = nullptr, *d_y = nullptr, *d_p = nullptr, *d_q = nullptr, *d_lam_prev = nullptr,
          *d_dt = nullptr, *d_lam_acc = nullptr;
   double* d_iface = nullptr;
   double *d_c = nullptr, *d_a = nullptr;
@@ -243,7 +245,9 @@ void harvest_timing(tfeti_handle* h, int valid) {
   h->ev_used = 0;
 }
 
-// out = P x; optional partial sums of out.out
+// out = P x; optional partial sums of out.out.  The coarse solve stays in
+// FP64 in both modes: an FP32 copy of the explicit inverse of G G^T loses the
+// projector's accuracy in proportion to the coarse condition number.
 void project(tfeti_handle* h, const double* x, double* out, double* partials, const int32_t* done) {
   launch_g_apply(h->dm, x, h->d_c, done, h->st);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, done, h->st);
@@ -251,7 +255,10 @@ void project(tfeti_handle* h, const double* x, double* out, double* partials, co
 }
 
 void precondition(tfeti_handle* h, const double* w, double* z, const int32_t* done) {
-  launch_lumped(h->dm, w, h->d_kbb_val, h->d_iface, done, h->st);
+  if (h->prec == TFETI_PREC_FP64)
+    launch_lumped<double>(h->dm, w, h->d_kbb_val, h->d_iface, done, h->st);
+  else
+    launch_lumped<float>(h->dm, w, h->d_kbb_val32, h->d_iface, done, h->st);
   launch_gather(h->dm, h->d_iface, z, nullptr, nullptr, done, h->st);
 }
 
@@ -446,12 +453,10 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
   launch_rt_apply(h->dm, f, h->d_c, h->st);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, nullptr, h->st);
   launch_gt_apply(h->dm, nullptr, h->d_a, -1.0, h->d_lam_im, nullptr, nullptr, h->st);
-  // d = B K^+ f and d~ = d - F lambda_Im (FP64 operator)
-  ksolve(h, f, nullptr, 0.0, h->d_iface, nullptr, nullptr, nullptr, true);
-  launch_gather(h->dm, h->d_iface, h->d_d, nullptr, nullptr, nullptr, h->st);
-  fapply(h, h->d_lam_im, h->d_q, nullptr, nullptr, nullptr, false, true);
-  launch_copy(m, h->d_d, h->d_dt, h->st);
-  launch_axpby(m, -1.0, h->d_q, 1.0, h->d_dt, h->st);
+  // d~ = d - F lambda_Im = B K^+ (f - B^T lambda_Im) in one pass over the
+  // factors (FP64 operator)
+  ksolve(h, f, h->d_lam_im, -1.0, h->d_iface, nullptr, nullptr, nullptr, true);
+  launch_gather(h->dm, h->d_iface, h->d_dt, nullptr, nullptr, nullptr, h->st);
   int fapplies = 1, fapplies64 = 1;
   // r_ref = ||P d~||
   {
@@ -611,7 +616,10 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   }
   launch_pad_identity(h->d_subs, M.n_sub, h->d_band, h->st);
   // the lumped preconditioner uses the unregularized tangent
-  launch_gather_kbb(h->d_kbb_band, (int64_t)M.kbb_band.size(), h->d_band, h->d_kbb_val, h->st);
+  if (h->prec == TFETI_PREC_FP64)
+    launch_gather_kbb<double>(h->d_kbb_band, (int64_t)M.kbb_band.size(), h->d_band, h->d_kbb_val, h->st);
+  else
+    launch_gather_kbb<float>(h->d_kbb_band, (int64_t)M.kbb_band.size(), h->d_band, h->d_kbb_val32, h->st);
   unsigned long long cnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
@@ -682,10 +690,30 @@ double time_fapply(tfeti_handle* h, int reps) {
   return t[t.size() / 2];
 }
 
+// Duration (ms) of one packing of every subdomain's panels.
+double time_pack(tfeti_handle* h) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  (void)hipEventRecord(e0, h->st);
+  pack(h, h->M.n_sub, nullptr);
+  (void)hipEventRecord(e1, h->st);
+  (void)hipEventSynchronize(e1);
+  float ms = -1.f;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+
+// F-applies per factorization assumed by the autotuner's objective (a Newton
+// solve of these problems takes a few tens of PCGP iterations).
+constexpr double kAppliesPerFactor = 40.0;
+
 // Autotuner: on the first factorization of a handle set up with tile 0,
-// search tile x schedule by the measured F-apply time, or take the choice
-// cached for the same architecture, precision and subdomain-size histogram
-// (file named by TFETI_AUTOTUNE_CACHE, if set).
+// search tile x schedule by the measured cost kAppliesPerFactor x (median
+// F-apply time) + (packing time), or take the choice cached for the same
+// architecture, precision and subdomain-size histogram (file named by
+// TFETI_AUTOTUNE_CACHE, if set).
 int autotune(tfeti_handle* h) {
   const HostModel& M = h->M;
   std::vector<int32_t> nd(M.n_sub);
@@ -710,7 +738,9 @@ int autotune(tfeti_handle* h) {
   for (int TS : {32, 64, 16})
     for (int nat : {0, 1}) {
       RC(retile(h, TS, nat));
-      const double ms = time_fapply(h, 20);
+      const double tp = time_pack(h);
+      const double tf = time_fapply(h, 20);
+      const double ms = (tp >= 0 && tf > 0) ? kAppliesPerFactor * tf + tp : -1.0;
       if (ms > 0 && (best.ms < 0 || ms < best.ms)) {
         best.tile = TS;
         best.natural = nat;
@@ -859,9 +889,25 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(upload(h, &h->d_R_full, M.R_full));
   RC(upload(h, &h->d_R_iface, M.R_iface));
   RC(upload(h, &h->d_kbb_rp, M.kbb_rp));
-  RC(upload(h, &h->d_kbb_col, M.kbb_col));
+  {
+    // K_bb columns as indices local to the subdomain's touched DOFs (16 bits)
+    std::vector<uint16_t> col16(M.kbb_col.size());
+    for (int64_t p = 0; p < M.n_sub; ++p) {
+      const SubDev& sd = M.subs[p];
+      if (sd.n_iface > 65535) return fail(h, TFETI_E_INVALID, "a subdomain has more than 65535 touched DOFs");
+      for (int32_t t = 0; t < sd.n_iface; ++t) {
+        const int64_t it = sd.iface_off + t;
+        for (int32_t q = M.kbb_rp[it]; q < M.kbb_rp[it + 1]; ++q)
+          col16[q] = (uint16_t)(M.kbb_col[q] - sd.iface_off);
+      }
+    }
+    RC(upload(h, &h->d_kbb_col, col16));
+  }
   RC(upload(h, &h->d_kbb_band, M.kbb_band));
-  RC(dalloc(h, &h->d_kbb_val, (int64_t)M.kbb_band.size()));
+  if (h->prec == TFETI_PREC_FP64)
+    RC(dalloc(h, &h->d_kbb_val, (int64_t)M.kbb_band.size()));
+  else
+    RC(dalloc(h, &h->d_kbb_val32, (int64_t)M.kbb_band.size()));
   RC(upload(h, &h->d_g_first, M.g_first));
   RC(upload(h, &h->d_g_rp, M.g_rp));
   RC(upload(h, &h->d_g_copies, M.g_copies));
@@ -910,7 +956,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_f, M.n_torn));
   RC(dalloc(h, &h->d_delta, M.n_torn));
   double** mv[] = {&h->d_lam, &h->d_lam_im, &h->d_lam_ker, &h->d_r,        &h->d_w,  &h->d_z,      &h->d_y,
-                   &h->d_p,   &h->d_q,      &h->d_d,       &h->d_lam_prev, &h->d_dt, &h->d_lam_acc,
+                   &h->d_p,   &h->d_q,      &h->d_lam_prev, &h->d_dt, &h->d_lam_acc,
                    &h->d_cl[0], &h->d_cl[1], &h->d_cr[0],  &h->d_cr[1],   &h->d_lam_conv, &h->d_lam_learn,
                    &h->d_lam_first, &h->d_lam_first_prev, &h->d_lam_guess};
   for (double** v : mv) RC(dalloc(h, v, M.m));

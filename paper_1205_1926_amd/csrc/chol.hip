@@ -140,47 +140,76 @@ __global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __rest
       const int wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
       const int nblk = nbw * (nbw + 1) / 2;
       typedef double d4 __attribute__((ext_vector_type(4)));
-      constexpr int BT = 4;  // blocks per batch: their window loads are in flight together
-      for (int q0 = wave; q0 < nblk; q0 += 4 * BT) {
-        int ra[BT], rb[BT], row0[BT], col[BT];
-        bool ok[BT];
-        T c[BT][4];
+      // this wave's blocks are q = wave + 4 i; they are processed BT at a
+      // time, the window values of the next batch loaded while the current
+      // batch runs its (interleaved) matrix-core chains
+      constexpr int BT = 4;
+      const int nmine = nblk > wave ? (nblk - wave + 3) / 4 : 0;
+      auto block_of = [&](int i, int& RB, int& CB) -> bool {
+        const int q = wave + 4 * i;
+        if (i >= nmine) return false;
+        RB = (int)sqrtf(2.0f * (float)q);
+        while (RB * (RB + 1) / 2 > q) --RB;
+        while ((RB + 1) * (RB + 2) / 2 <= q) ++RB;
+        CB = q - RB * (RB + 1) / 2;
+        return RB * 16 - (CB * 16 + 15) <= b;  // inside the band
+      };
+      auto load_batch = [&](int i0, T (&c)[BT][4]) {
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
-          const int q = q0 + 4 * t;
-          int RB = (int)sqrtf(2.0f * (float)q);
-          while (RB * (RB + 1) / 2 > q) --RB;
-          while ((RB + 1) * (RB + 2) / 2 <= q) ++RB;
-          const int CB = q - RB * (RB + 1) / 2;
-          ok[t] = q < nblk && RB * 16 - (CB * 16 + 15) <= b;  // inside the band
+          int RB = 0, CB = 0;
+          const bool ok = block_of(i0 + t, RB, CB);
+          const int row0 = J + jb + RB * 16 + lk, col = J + jb + CB * 16 + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = row0 + 4 * r;
+            const bool in = ok && row < rend && col <= row && row - col <= b;
+            c[t][r] = in ? A[(int64_t)row * Wb + (col - row + b)] : T(0);
+          }
+        }
+      };
+      T cur[BT][4], nxt[BT][4];
+      if (nmine > 0) load_batch(0, cur);
+      for (int i0 = 0; i0 < nmine; i0 += BT) {
+        if (i0 + BT < nmine) load_batch(i0 + BT, nxt);
+        int ra[BT], rb[BT], row0[BT], col[BT];
+        bool ok[BT];
+#pragma unroll
+        for (int t = 0; t < BT; ++t) {
+          int RB = 0, CB = 0;
+          ok[t] = block_of(i0 + t, RB, CB);
           ra[t] = jb + RB * 16 + li;
           rb[t] = jb + CB * 16 + li;
           row0[t] = J + jb + RB * 16 + lk;
           col[t] = J + jb + CB * 16 + li;
+        }
+        d4 acc[BT];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = row0[t] + 4 * r;
-            const bool in = ok[t] && row < rend && col[t] <= row && row - col[t] <= b;
-            c[t][r] = in ? A[(int64_t)row * Wb + (col[t] - row + b)] : T(0);
+        for (int t = 0; t < BT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < jb; k0 += 4) {
+          const int k = k0 + lk;
+          double av[BT], bv[BT];
+#pragma unroll
+          for (int t = 0; t < BT; ++t) {
+            av[t] = (ok[t] && ra[t] < nr && k < jb) ? (double)Lp[ra[t] * LS + k] : 0.0;
+            bv[t] = (ok[t] && rb[t] < nr && k < jb) ? (double)Lp[rb[t] * LS + k] : 0.0;
           }
+#pragma unroll
+          for (int t = 0; t < BT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[t], 0, 0, 0);
         }
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
-          if (!ok[t]) continue;
-          d4 acc = {0.0, 0.0, 0.0, 0.0};
-          for (int k0 = 0; k0 < jb; k0 += 4) {
-            const int k = k0 + lk;
-            const double av = (ra[t] < nr && k < jb) ? (double)Lp[ra[t] * LS + k] : 0.0;
-            const double bv = (rb[t] < nr && k < jb) ? (double)Lp[rb[t] * LS + k] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-          }
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = row0[t] + 4 * r;
-            if (row < rend && col[t] <= row && row - col[t] <= b)
-              A[(int64_t)row * Wb + (col[t] - row + b)] = c[t][r] - (T)acc[r];
+            if (ok[t] && row < rend && col[t] <= row && row - col[t] <= b)
+              A[(int64_t)row * Wb + (col[t] - row + b)] = cur[t][r] - (T)acc[t][r];
           }
         }
+#pragma unroll
+        for (int t = 0; t < BT; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cur[t][r] = nxt[t][r];
       }
     } else {
       const int rbeg = J + jb;

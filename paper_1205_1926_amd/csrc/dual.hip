@@ -1,6 +1,7 @@
 // Dual-space kernels of the PCGP (Algorithm 3), all FP64: the B gather,
 // G w = R^T B^T w, G^T a = B R a, the dense coarse solve with (G G^T)^{-1},
-// the lumped preconditioner B K B^T (Section 4.2), deterministic two-stage
+// the lumped preconditioner B K B^T (Section 4.2; K_bb values in FP64, or in
+// FP32 in the mixed-precision mode), deterministic two-stage
 // reductions and the scalar updates of the iteration.  Every kernel of the
 // iteration returns at once when the device "done" flag is set, so a fixed
 // number of iterations can be enqueued (or replayed from a graph) and the
@@ -110,24 +111,26 @@ void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t 
 // ---------------------------------------------------------------- coarse solve
 // a = scale * Ginv c: one wave per row, lanes stride the columns, wave
 // reduction by shuffles (fixed order).
-__global__ __launch_bounds__(256) void coarse_gemv_kernel(int64_t l, const double* __restrict__ G,
+template <typename TG>
+__global__ __launch_bounds__(256) void coarse_gemv_kernel(int64_t l, const TG* __restrict__ G,
                                                           const double* __restrict__ c, double* __restrict__ a,
                                                           double scale, const int32_t* __restrict__ done) {
   if (done && *done) return;
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= l) return;
-  const double* g = G + row * l;
+  const TG* g = G + row * l;
   double acc = 0.0;
-  for (int64_t j = lane; j < l; j += 64) acc += g[j] * c[j];
+  for (int64_t j = lane; j < l; j += 64) acc += (double)g[j] * c[j];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) a[row] = scale * acc;
 }
 
 void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double scale, const int32_t* done,
                         hipStream_t st) {
-  coarse_gemv_kernel<<<dim3((unsigned)((M.l + 3) / 4)), dim3(256), 0, st>>>(M.l, M.Ginv, c, a, scale, done);
+  coarse_gemv_kernel<double><<<dim3((unsigned)((M.l + 3) / 4)), dim3(256), 0, st>>>(M.l, M.Ginv, c, a, scale, done);
 }
+
 
 // ---------------------------------------------------------------- x - G^T a
 __global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* __restrict__ x,
@@ -163,8 +166,9 @@ void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double
 }
 
 // ---------------------------------------------------------------- lumped preconditioner
+template <typename TV>
 __global__ __launch_bounds__(RB) void lumped_kernel(DualMaps M, const double* __restrict__ w,
-                                                    const double* __restrict__ kv, double* __restrict__ out,
+                                                    const TV* __restrict__ kv, double* __restrict__ out,
                                                     const int32_t* __restrict__ done) {
   extern __shared__ double vloc[];
   if (done && *done) return;
@@ -186,18 +190,23 @@ __global__ __launch_bounds__(RB) void lumped_kernel(DualMaps M, const double* __
     const int64_t it = ioff + t;
     const int q0 = M.kbb_rp[it], q1 = M.kbb_rp[it + 1];
     double y = 0.0;
-    for (int q = q0 + lane; q < q1; q += G) y += kv[q] * vloc[M.kbb_col[q] - ioff];
+    for (int q = q0 + lane; q < q1; q += G) y += (double)kv[q] * vloc[M.kbb_col[q]];
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) y += __shfl_down(y, off, G);
     if (lane == 0) out[it] = y;
   }
 }
 
-void launch_lumped(const DualMaps& M, const double* w, const double* kbb_val, double* iface_out,
-                   const int32_t* done, hipStream_t st) {
+template <typename TV>
+void launch_lumped(const DualMaps& M, const double* w, const TV* kbb_val, double* iface_out, const int32_t* done,
+                   hipStream_t st) {
   size_t shm = (size_t)(M.max_iface > 0 ? M.max_iface : 1) * sizeof(double);
-  lumped_kernel<<<dim3((unsigned)M.nsub), dim3(RB), shm, st>>>(M, w, kbb_val, iface_out, done);
+  lumped_kernel<TV><<<dim3((unsigned)M.nsub), dim3(RB), shm, st>>>(M, w, kbb_val, iface_out, done);
 }
+template void launch_lumped<double>(const DualMaps&, const double*, const double*, double*, const int32_t*,
+                                    hipStream_t);
+template void launch_lumped<float>(const DualMaps&, const double*, const float*, double*, const int32_t*,
+                                   hipStream_t);
 
 // ---------------------------------------------------------------- reductions
 __global__ __launch_bounds__(RB) void dot_kernel(const double* __restrict__ x, const double* __restrict__ y,

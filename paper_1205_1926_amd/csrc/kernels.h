@@ -32,7 +32,8 @@ void launch_return_map(const tfeti_material& mat, int64_t npts, const double* si
                        const double* de, double* ds, double* dk, double* Dt, uint8_t* pl, hipStream_t st);
 void launch_assemble(const AssembleArgs& args, hipStream_t st);
 void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStream_t st);
-void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, double* out, hipStream_t st);
+template <typename T>
+void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, T* out, hipStream_t st);
 // list: subdomain indices (count of them), or NULL for subdomains 0 .. count-1
 void launch_regularize(const SubDev* subs, int64_t count, const int32_t* list, const double* QQt, double* band,
                        hipStream_t st);
@@ -100,7 +101,7 @@ struct DualMaps {
   const double* R_iface;
   const double* R_full;
   const int32_t* kbb_rp;
-  const int32_t* kbb_col;
+  const uint16_t* kbb_col;    // column, local to the subdomain's touched DOFs
   const double* Ginv;
   int32_t max_iface;          // largest per-subdomain touched-DOF count (LDS of the preconditioner)
 };
@@ -119,7 +120,8 @@ void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double sc
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
                      double* partials, const int32_t* done, hipStream_t st);
 // iface_out = K_bb (B^T w) per subdomain
-void launch_lumped(const DualMaps& M, const double* w, const double* kbb_val, double* iface_out,
+template <typename TV>
+void launch_lumped(const DualMaps& M, const double* w, const TV* kbb_val, double* iface_out,
                    const int32_t* done, hipStream_t st);
 
 int reduction_blocks(int64_t n);

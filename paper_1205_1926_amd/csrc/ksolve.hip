@@ -17,6 +17,9 @@
 // triangular.  Lanes skip the loads of chunks that lie entirely in those zero
 // parts (the backward pass with the interior envelope, a bound that is
 // monotone in the row), so the bytes read approach the envelope (skyline).
+// Panel loads are non-temporal (each factor entry is read once per apply)
+// and issued four chunks at a time per lane (a sweep of 2..16 on MI355X put
+// the optimum at 4 for both precisions).
 #include "kernels.h"
 
 namespace tfeti {
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
   constexpr int V = Vec<T>::V;
   constexpr int NT = 256;
   constexpr int RPT = NT / TS;           // threads per tile row
-  constexpr int UNR = 8;                 // panel chunks loaded back to back per lane
+  constexpr int UNR = 4;                 // panel chunks loaded back to back per lane
   extern __shared__ __align__(16) unsigned char smem[];
   T* xs = reinterpret_cast<T*>(smem);
   T* part = xs + A.part_off;             // after the largest subdomain vector
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
       for (; cc + (UNR - 1) * RPT < nco; cc += UNR * RPT) {
         VT L[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) L[u] = *reinterpret_cast<const VT*>(P + off + ((int64_t)(cc + u * RPT) * TS + r) * V);
+        for (int u = 0; u < UNR; ++u) L[u] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(P + off + ((int64_t)(cc + u * RPT) * TS + r) * V));
 #pragma unroll
         for (int u = 0; u < UNR; ++u) acc += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs + c0 + (cc + u * RPT) * V));
       }
@@ -191,7 +194,8 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
         VT L[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-          L[u] = *reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr + u * RPT) * TS + c) * V);
+          L[u] = __builtin_nontemporal_load(
+              reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr + u * RPT) * TS + c) * V));
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
           acc += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs + rbase + (rr + u * RPT) * V));

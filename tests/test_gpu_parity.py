@@ -217,9 +217,10 @@ def test_graph_replay_matches_eager(dev):
     result, solve after solve (several replays, eager work in between)."""
     from paper_1205_1926_amd import GpuSolver
     w = W.small_cube(S=(2, 2, 2), n=(3, 3, 3), amp=500.0, shear=100.0)
-    ge = GpuSolver(w, use_graph=0)
-    gg = GpuSolver(w, use_graph=1)
-    gt = GpuSolver(w, use_graph=1)          # split replay with timed solve kernels
+    # one fixed tile: the autotuner could pick different kernels per handle
+    ge = GpuSolver(w, use_graph=0, tile=32)
+    gg = GpuSolver(w, use_graph=1, tile=32)
+    gt = GpuSolver(w, use_graph=1, tile=32)  # split replay with timed solve kernels
     gt.set_timing(True)
     du = torch.zeros(ge.sizes["n_torn"], dtype=torch.float64, device=dev)
     for g in (ge, gg, gt):
