@@ -70,6 +70,25 @@ def cpu_baseline(seconds: float = 12.0):
                       f"BLAS limited to 1 thread"}
 
 
+def measured_traffic(precision: str, tile: int):
+    """HBM bytes per launch of the F-apply solve kernel from the committed
+    FETCH_SIZE/WRITE_SIZE summary, or None if that summary was taken on
+    another kernel source or tile."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ksolve_traffic_cube10x10x10_sub8.md")
+    src = os.path.join(ROOT, "paper_1205_1926_amd", "csrc", "ksolve.hip")
+    try:
+        line = [l for l in open(path) if l.startswith("traffic: ")][0]
+        rec = json.loads(line[len("traffic: "):])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    ent = rec.get(precision, {}).get(str(tile))
+    if rec.get("ksolve_sha256") != sha or not ent:
+        return None
+    return ent["traffic_bytes"]
+
+
 def counter_probe(g, reps: int) -> int:
     """Kernels of known traffic for FETCH_SIZE / WRITE_SIZE runs: the F-apply
     on the factors of the first Newton iteration, then a plain device copy of
@@ -201,6 +220,7 @@ def main() -> int:
     log(f"timed: {fapplies} F-applies in {elapsed:.3f} s; solve kernel mean {mean_kernel_s * 1e3:.3f} ms "
         f"over {k_cnt}; isolated F-apply {iso * 1e3:.3f} ms (kernel {iso_kernel_s * 1e3:.3f} ms)")
 
+    traffic = measured_traffic(args.precision, sz["tile"])
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -240,7 +260,9 @@ def main() -> int:
                             "applies_per_s": 1.0 / iso,
                             "GB_s_algorithmic": alg_bytes / iso_kernel_s / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_GBs": (traffic / mean_kernel_s / 1e9) if traffic else None,
                      "kernel": "ksolve_kernel (fused B^T scatter + forward/backward substitution)",
                      "bytes_per_launch": alg_bytes, "mean_kernel_ms": mean_kernel_s * 1e3,
                      "kernels_timed": k_cnt},

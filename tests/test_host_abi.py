@@ -41,7 +41,8 @@ def test_library_exports_every_declared_symbol():
     assert set(_capi.SIGNATURES) == set(declared_functions())
 
 
-@pytest.mark.parametrize("w", [W.config(0), W.config(1), W.small_cube(S=(3, 2, 2), n=(2, 3, 2)),
+@pytest.mark.parametrize("w", [W.config(0), W.config(1), W.config(2), W.config(4),
+                               W.small_cube(S=(3, 2, 2), n=(2, 3, 2)),
                                W.patch_test(S=(2, 2, 3), n=(2, 1, 2)),
                                W.Workload("uneven", (2, 3, 2), [3, 5], [2, 4, 3], [6, 2],
                                           dirichlet=[[1, 0, 0], [0, 0, 0], [0, 1, 0], [0, 0, 0], [1, 1, 1], [0, 0, 0]])])
