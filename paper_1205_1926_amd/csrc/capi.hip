@@ -59,7 +59,7 @@ struct tfeti_handle {
   int32_t* d_colour[8] = {};
   int64_t n_colour[8] = {};
   int32_t* d_elem_sub = nullptr;
-  double *d_QQt = nullptr, *d_dN = nullptr, *d_Ginv = nullptr;
+  double *d_QQt = nullptr, *d_dN = nullptr, *d_Ginv = nullptr, *d_Gpk = nullptr, *d_Gpart = nullptr;
   // matrices
   double* d_band = nullptr;     // K_reg (FP64 row-band)
   void* d_work = nullptr;       // factor work (row-band, factor precision)
@@ -983,6 +983,8 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   h->subpl.assign(M.n_sub, 0);
   h->flist.reserve(M.n_sub);
   RC(dalloc(h, &h->d_Ginv, (int64_t)M.lc * M.lc));
+  RC(dalloc(h, &h->d_Gpk, coarse_tiles(M.lc) * 64 * 64));
+  RC(dalloc(h, &h->d_Gpart, ((int64_t)M.lc + 63) / 64 * M.lc_pad));
   HIPCHK(hipMemsetAsync(h->d_sigma, 0, 6 * M.n_gp * sizeof(double), h->st));
   HIPCHK(hipMemsetAsync(h->d_kappa, 0, M.n_gp * sizeof(double), h->st));
   HIPCHK(hipMemsetAsync(h->d_dsigma, 0, 6 * M.n_gp * sizeof(double), h->st));
@@ -1011,6 +1013,8 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   dm.kbb_rp = h->d_kbb_rp;
   dm.kbb_col = h->d_kbb_col;
   dm.Ginv = h->d_Ginv;
+  dm.Gpk = h->d_Gpk;
+  dm.Gpart = h->d_Gpart;
   dm.max_iface = h->max_iface;
   // ---- coarse problem: banded Cholesky of G G^T, then the dense inverse ----
   {
@@ -1028,6 +1032,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
     launch_band_cholesky<double>(d_cs, 1, nullptr, d_cb, h->d_fail, M.bc, 0, h->st);
     launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st);
+    launch_coarse_pack(M.lc, h->d_Ginv, h->d_Gpk, h->st);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));

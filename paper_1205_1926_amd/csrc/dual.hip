@@ -109,28 +109,97 @@ void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t 
 }
 
 // ---------------------------------------------------------------- coarse solve
-// a = scale * Ginv c: one wave per row, lanes stride the columns, wave
-// reduction by shuffles (fixed order).
-template <typename TG>
-__global__ __launch_bounds__(256) void coarse_gemv_kernel(int64_t l, const TG* __restrict__ G,
-                                                          const double* __restrict__ c, double* __restrict__ a,
-                                                          double scale, const int32_t* __restrict__ done) {
+// a = scale * Ginv c with the symmetric (G G^T)^{-1} stored as its lower
+// CT x CT tiles (I >= J, tile t = I (I+1)/2 + J, row-major, zero-padded past
+// l): each tile is read once and contributes A_IJ c_J to block I and, off the
+// diagonal, A_IJ^T c_I to block J.  Every output block gets exactly one
+// partial per tile column index, summed in a fixed order by the second kernel.
+namespace {
+constexpr int CT = 64;
+__device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
+  I = (int)sqrtf(2.0f * (float)t);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  J = t - I * (I + 1) / 2;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void coarse_pack_kernel(int64_t l, const double* __restrict__ G,
+                                                          double* __restrict__ P) {
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  double* out = P + (int64_t)blockIdx.x * CT * CT;
+  for (int q = threadIdx.x; q < CT * CT; q += 256) {
+    const int64_t gi = (int64_t)I * CT + q / CT, gj = (int64_t)J * CT + q % CT;
+    out[q] = (gi < l && gj < l) ? G[gi * l + gj] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void coarse_symv_kernel(int64_t l, int64_t lp, const double* __restrict__ P,
+                                                          const double* __restrict__ c, double* __restrict__ part,
+                                                          const int32_t* __restrict__ done) {
+  __shared__ double A[CT][CT + 1];
+  __shared__ double xI[CT], xJ[CT];
   if (done && *done) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= l) return;
-  const TG* g = G + row * l;
-  double acc = 0.0;
-  for (int64_t j = lane; j < l; j += 64) acc += (double)g[j] * c[j];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) a[row] = scale * acc;
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  const double* tile = P + (int64_t)blockIdx.x * CT * CT;
+  const int tid = threadIdx.x;
+  double v[CT * CT / 256];
+#pragma unroll
+  for (int u = 0; u < CT * CT / 256; ++u) v[u] = __builtin_nontemporal_load(tile + u * 256 + tid);
+  if (tid < CT) {
+    const int64_t gj = (int64_t)J * CT + tid, gi = (int64_t)I * CT + tid;
+    xJ[tid] = gj < l ? c[gj] : 0.0;
+    xI[tid] = gi < l ? c[gi] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < CT * CT / 256; ++u) {
+    const int q = u * 256 + tid;
+    A[q / CT][q % CT] = v[u];
+  }
+  __syncthreads();
+  if (tid < CT) {
+    double sr = 0.0;
+    for (int j = 0; j < CT; ++j) sr += A[tid][j] * xJ[j];
+    part[(int64_t)J * lp + (int64_t)I * CT + tid] = sr;
+  } else if (tid < 2 * CT && I != J) {
+    const int j = tid - CT;
+    double sc = 0.0;
+    for (int i = 0; i < CT; ++i) sc += A[i][j] * xI[i];
+    part[(int64_t)I * lp + (int64_t)J * CT + j] = sc;
+  }
+}
+
+__global__ __launch_bounds__(256) void coarse_reduce_kernel(int64_t l, int64_t lp, int nT,
+                                                            const double* __restrict__ part, double* __restrict__ a,
+                                                            double scale, const int32_t* __restrict__ done) {
+  if (done && *done) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= l) return;
+  double s = 0.0;
+  for (int k = 0; k < nT; ++k) s += part[(int64_t)k * lp + i];
+  a[i] = scale * s;
+}
+
+int64_t coarse_tiles(int64_t l) {
+  const int64_t nT = (l + CT - 1) / CT;
+  return nT * (nT + 1) / 2;
+}
+
+void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream_t st) {
+  const int64_t nt = coarse_tiles(l);
+  if (nt > 0) coarse_pack_kernel<<<dim3((unsigned)nt), dim3(256), 0, st>>>(l, Ginv, packed);
 }
 
 void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double scale, const int32_t* done,
                         hipStream_t st) {
-  coarse_gemv_kernel<double><<<dim3((unsigned)((M.l + 3) / 4)), dim3(256), 0, st>>>(M.l, M.Ginv, c, a, scale, done);
+  const int nT = (int)((M.l + CT - 1) / CT);
+  const int64_t lp = (int64_t)nT * CT;
+  coarse_symv_kernel<<<dim3((unsigned)coarse_tiles(M.l)), dim3(256), 0, st>>>(M.l, lp, M.Gpk, c, M.Gpart, done);
+  coarse_reduce_kernel<<<dim3((unsigned)((M.l + 255) / 256)), dim3(256), 0, st>>>(M.l, lp, nT, M.Gpart, a, scale,
+                                                                                  done);
 }
-
 
 // ---------------------------------------------------------------- x - G^T a
 __global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* __restrict__ x,

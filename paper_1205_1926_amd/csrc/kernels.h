@@ -102,7 +102,9 @@ struct DualMaps {
   const double* R_full;
   const int32_t* kbb_rp;
   const uint16_t* kbb_col;    // column, local to the subdomain's touched DOFs
-  const double* Ginv;
+  const double* Ginv;          // dense (G G^T)^{-1}, l x l (setup only)
+  const double* Gpk;           // its lower 64 x 64 tiles, packed (coarse solves)
+  double* Gpart;               // per-tile partial products, ceil(l/64) x roundup(l, 64)
   int32_t max_iface;          // largest per-subdomain touched-DOF count (LDS of the preconditioner)
 };
 
@@ -116,6 +118,9 @@ void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t 
 // a = scale * Ginv c
 void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double scale, const int32_t* done,
                         hipStream_t st);
+// tiles of the packed lower triangle of an l x l symmetric matrix (64 x 64)
+int64_t coarse_tiles(int64_t l);
+void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream_t st);
 // out = (x ? x : 0) - sign * G^T a; optional partial sums of out.out
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
                      double* partials, const int32_t* done, hipStream_t st);
