@@ -8,9 +8,9 @@
 //
 // One workgroup (256 threads) per band matrix, right-looking by block
 // columns of NB: the panel (the NB block columns of every row the band
-// reaches, at most NB + b rows) is staged in LDS; wave 0 factors the
-// diagonal tile in registers (lane = row, lane broadcasts); the rows below
-// are solved against it in LDS; the panel is written back and the trailing
+// reaches, at most NB + b rows) is staged in LDS and factored column by
+// column with each row in a thread's registers (one barrier per column);
+// the panel is written back and the trailing
 // band window is updated from the LDS panel in 16 x 16 blocks on the FP64
 // matrix cores (FP32: 64 x 64 tiles, 4 x 4 outputs per thread), so global
 // traffic is one read-modify-write of the window per block column.
@@ -39,7 +39,7 @@ constexpr int TT = 64;  // trailing-update tile edge
 }  // namespace
 
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t count,
+__global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                             const int32_t* __restrict__ list,
                                                             T* __restrict__ W, int32_t* __restrict__ fail) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -74,41 +74,63 @@ __global__ __launch_bounds__(256) void band_cholesky_kernel(const SubDev* __rest
       }
     }
     __syncthreads();
-    // ---- diagonal tile: wave 0, lane = row, in registers ----
-    if (tid < 64) {
-      const int i = tid;
-      T a[NB];
+    // ---- panel factorization, column by column: thread r < blockDim.x
+    //      keeps row r of the panel in registers; at column j every row
+    //      below j takes L[r][j] = (x_r[j] - x_r[0:j] . L[j][0:j]) / L[j][j]
+    //      with row j read from LDS (one address for all lanes), and row j+1
+    //      completes its diagonal entry and publishes itself for the next
+    //      column; one barrier per column ----
+    {
+      const int r = tid;
+      const bool have = r < nr;
+      T x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) a[j] = (i < jb) ? Lp[i * LS + j] : T(0);
+      for (int j = 0; j < NB; ++j) x[j] = have ? Lp[r * LS + j] : T(0);
       bool bad = false;
+      if (r == 0 && jb > 0) {
+        T d = x[0];
+        if (!(d > T(0))) {
+          bad = true;
+          d = T(1);
+        }
+        x[0] = sqrt(d);
+        Lp[0] = x[0];
+      }
+      __syncthreads();
 #pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        if (k < jb) {
-          T dkk = bcast_lane(a[k], k);
-          if (!(dkk > T(0))) {
-            bad = true;
-            dkk = T(1);
-          }
-          const T lkk = sqrt(dkk);
-          if (i == k) a[k] = lkk;
-          if (i > k) a[k] = a[k] / lkk;
+      for (int j = 0; j < NB; ++j) {
+        if (j < jb) {
+          if (have && r > j) {
+            T v = x[j];
 #pragma unroll
-          for (int j = k + 1; j < NB; ++j) {
-            const T ljk = bcast_lane(a[k], j);
-            if (i >= j && j < jb) a[j] -= a[k] * ljk;
+            for (int k = 0; k < j; ++k) v -= x[k] * Lp[j * LS + k];
+            x[j] = v / Lp[j * LS + j];
+            if (r == j + 1 && j + 1 < jb) {
+              T d = x[j + 1];
+#pragma unroll
+              for (int k = 0; k <= j; ++k) d -= x[k] * x[k];
+              if (!(d > T(0))) {
+                bad = true;
+                d = T(1);
+              }
+              x[j + 1] = sqrt(d);
+#pragma unroll
+              for (int k = 0; k <= j + 1; ++k) Lp[r * LS + k] = x[k];
+            }
           }
+          __syncthreads();
         }
       }
-      if (bad && i == 0) s_fail = 1;
-      if (i < jb) {
+      if (bad) s_fail = 1;
+      if (have) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) Lp[i * LS + j] = a[j];
+        for (int j = 0; j < NB; ++j) Lp[r * LS + j] = x[j];
       }
     }
     __syncthreads();
-    // ---- rows below: x := x L_JJ^{-T}, the row in registers, the tile
-    //      entries read by every lane at the same LDS address ----
-    for (int r = jb + tid; r < nr; r += blockDim.x) {
+    // ---- rows past the first blockDim.x: solved against the finished
+    //      diagonal tile, independently ----
+    for (int r = (int)blockDim.x + tid; r < nr; r += blockDim.x) {
       T x[NB];
 #pragma unroll
       for (int j = 0; j < NB; ++j) x[j] = Lp[r * LS + j];
