@@ -208,16 +208,42 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
         d4 acc[BT];
 #pragma unroll
         for (int t = 0; t < BT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < jb; k0 += 4) {
-          const int k = k0 + lk;
-          double av[BT], bv[BT];
+        // operand rows past the panel (and blocks outside the band) read
+        // row 0 instead: their products only reach outputs that are not
+        // written back, so they need no zeroing, only an address in bounds
+        const T* pa[BT];
+        const T* pb[BT];
 #pragma unroll
-          for (int t = 0; t < BT; ++t) {
-            av[t] = (ok[t] && ra[t] < nr && k < jb) ? (double)Lp[ra[t] * LS + k] : 0.0;
-            bv[t] = (ok[t] && rb[t] < nr && k < jb) ? (double)Lp[rb[t] * LS + k] : 0.0;
+        for (int t = 0; t < BT; ++t) {
+          pa[t] = Lp + (ok[t] && ra[t] < nr ? ra[t] : 0) * LS + lk;
+          pb[t] = Lp + (ok[t] && rb[t] < nr ? rb[t] : 0) * LS + lk;
+        }
+        if (jb == NB) {
+#pragma unroll
+          for (int k0 = 0; k0 < NB; k0 += 4) {
+            double av[BT], bv[BT];
+#pragma unroll
+            for (int t = 0; t < BT; ++t) {
+              av[t] = (double)pa[t][k0];
+              bv[t] = (double)pb[t][k0];
+            }
+#pragma unroll
+            for (int t = 0; t < BT; ++t)
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[t], 0, 0, 0);
           }
+        } else {
+          for (int k0 = 0; k0 < jb; k0 += 4) {
+            const bool kin = k0 + lk < jb;
+            double av[BT], bv[BT];
 #pragma unroll
-          for (int t = 0; t < BT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[t], 0, 0, 0);
+            for (int t = 0; t < BT; ++t) {
+              av[t] = kin ? (double)pa[t][k0] : 0.0;
+              bv[t] = kin ? (double)pb[t][k0] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < BT; ++t)
+              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[t], 0, 0, 0);
+          }
         }
 #pragma unroll
         for (int t = 0; t < BT; ++t) {
