@@ -70,11 +70,23 @@ def cpu_baseline(seconds: float = 12.0):
                       f"BLAS limited to 1 thread"}
 
 
-def measured_traffic(precision: str, tile: int):
+def describe(w, sz) -> str:
+    """The workload in words: mesh, decomposition, sizes and load."""
+    sub = ("8^3" if set(w.nx) | set(w.ny) | set(w.nz) == {8}
+           else f"{min(w.nx + w.ny + w.nz)}..{max(w.nx + w.ny + w.nz)} elements per axis")
+    top = w.traction[5]
+    load = " + ".join(t for t, v in (("x shear", top[0]), ("y shear", top[1]), ("z traction", top[2])) if v)
+    return (f"{w.name}: unit cube of Q1 hexahedra, {sz['n_sub']} box subdomains of {sub}, {sz['n_torn']} torn DOF, "
+            f"{sz['m']} multipliers, clamped bottom, top face {load}, load ramp over {w.steps} steps")
+
+
+def measured_traffic(workload: str, precision: str, tile: int):
     """HBM bytes per launch of the F-apply solve kernel from the committed
     FETCH_SIZE/WRITE_SIZE summary, or None if that summary was taken on
-    another kernel source or tile."""
+    another workload, kernel source or tile."""
     import hashlib
+    if workload != "cube10x10x10_sub8":
+        return None
     path = os.path.join(ROOT, "profiles", "ksolve_traffic_cube10x10x10_sub8.md")
     src = os.path.join(ROOT, "paper_1205_1926_amd", "csrc", "ksolve.hip")
     try:
@@ -220,7 +232,7 @@ def main() -> int:
     log(f"timed: {fapplies} F-applies in {elapsed:.3f} s; solve kernel mean {mean_kernel_s * 1e3:.3f} ms "
         f"over {k_cnt}; isolated F-apply {iso * 1e3:.3f} ms (kernel {iso_kernel_s * 1e3:.3f} ms)")
 
-    traffic = measured_traffic(args.precision, sz["tile"])
+    traffic = measured_traffic(w.name, args.precision, sz["tile"])
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -240,11 +252,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-factors/f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: unit cube, {sz['n_sub']} box subdomains of 8^3 Q1 hexahedra, "
-                               f"{sz['n_torn']} torn DOF, {sz['m']} multipliers, clamped bottom, top traction "
-                               f"(compression + shear), load ramp over {w.steps} steps",
+        "config": {"workload": describe(w, sz),
                    "precision": args.precision, "tile": sz["tile"], "schedule": sz["schedule"],
-                   "autotuned": sz["autotuned"], "preconditioner": "lumped",
+                   "threads_per_subdomain": sz["threads"], "autotuned": sz["autotuned"], "preconditioner": "lumped",
                    "graph": bool(args.graph), "graph_active": graph_state,
                    "eps_pcg": w.eps_pcg, "eps_newton": w.eps_newton},
         "newton_step_ms": elapsed / max(len(reps), 1) * 1e3,

@@ -98,7 +98,8 @@ typedef struct {
   int32_t use_graph;            /* replay the PCGP iteration as a HIP graph     */
   int32_t tile;                 /* factor tile rows 16/32/64; 0 = autotuned: at
                                    the first factorization, every tile 16/32/64
-                                   with either subdomain order is timed (median
+                                   with either subdomain order and 256, 512 or
+                                   1024 threads per subdomain is timed (median
                                    of 20 F-applies x 40 + one panel packing) and
                                    the cheapest is kept;
                                    the choice is cached in the file named by the
@@ -154,6 +155,11 @@ typedef struct {
                                    first, 1 natural                              */
   int32_t autotuned;            /* 0 tile fixed by the options, 1 searched by the
                                    autotuner, 2 taken from its cache             */
+  int32_t threads;              /* threads per workgroup of the subdomain solves
+                                   (256; 512 or 1024 when the autotuner finds
+                                   them faster: few or uneven subdomains per
+                                   compute unit)                                 */
+  int32_t pad;
 } tfeti_sizes;
 
 typedef struct tfeti_handle tfeti_handle;

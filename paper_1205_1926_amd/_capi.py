@@ -56,7 +56,7 @@ class Sizes(C.Structure):
                 ("m_U", C.c_int64), ("l", C.c_int64), ("n_elem", C.c_int64), ("n_gp", C.c_int64),
                 ("n_gdof", C.c_int64), ("skyline_entries", C.c_int64), ("factor_entries", C.c_int64),
                 ("factor_bytes", C.c_int64), ("tile", C.c_int32), ("precision", C.c_int32),
-                ("schedule", C.c_int32), ("autotuned", C.c_int32)]
+                ("schedule", C.c_int32), ("autotuned", C.c_int32), ("threads", C.c_int32), ("pad", C.c_int32)]
 
 
 class Mlp(C.Structure):

@@ -1,5 +1,5 @@
 // Autotuner cache: one JSON object per line,
-//   {"key": "...", "tile": 32, "natural": 0, "ms": 1.768}
+//   {"key": "...", "tile": 32, "natural": 0, "threads": 256, "ms": 1.768}
 // Lines that do not parse are kept as they are and ignored.
 #include "autotune.h"
 
@@ -41,18 +41,21 @@ bool field(const std::string& line, const std::string& name, std::string* out) {
 }
 
 bool parse(const std::string& line, std::string* key, TuneChoice* c) {
-  std::string k, t, n, m;
-  if (!field(line, "key", &k) || !field(line, "tile", &t) || !field(line, "natural", &n) || !field(line, "ms", &m))
+  std::string k, t, n, m, w;
+  if (!field(line, "key", &k) || !field(line, "tile", &t) || !field(line, "natural", &n) || !field(line, "ms", &m) ||
+      !field(line, "threads", &w))
     return false;
   try {
     c->tile = std::stoi(t);
     c->natural = std::stoi(n);
+    c->threads = std::stoi(w);
     c->ms = std::stod(m);
   } catch (...) {
     return false;
   }
   if (c->tile != 16 && c->tile != 32 && c->tile != 64) return false;
   if (c->natural != 0 && c->natural != 1) return false;
+  if (c->threads != 256 && c->threads != 512 && c->threads != 1024) return false;
   *key = k;
   return true;
 }
@@ -99,8 +102,8 @@ bool tune_cache_store(const std::string& path, const std::string& key, const Tun
     }
   }
   char buf[512];
-  std::snprintf(buf, sizeof(buf), "{\"key\": \"%s\", \"tile\": %d, \"natural\": %d, \"ms\": %.6f}", key.c_str(), c.tile,
-                c.natural, c.ms);
+  std::snprintf(buf, sizeof(buf), "{\"key\": \"%s\", \"tile\": %d, \"natural\": %d, \"threads\": %d, \"ms\": %.6f}",
+                key.c_str(), c.tile, c.natural, c.threads, c.ms);
   keep.push_back(buf);
   const std::string tmp = path + ".tmp";
   {

@@ -12,6 +12,7 @@ namespace tfeti {
 struct TuneChoice {
   int tile = 32;      // rows per factor tile: 16, 32 or 64
   int natural = 0;    // subdomain schedule: 0 longest first, 1 natural order
+  int threads = 256;  // threads per workgroup of the subdomain solves: 256, 512 or 1024
   double ms = 0.0;    // median F-apply time measured for this choice
 };
 

@@ -25,6 +25,7 @@ struct tfeti_handle {
   hipStream_t st = nullptr;
   int TS = 32;
   int natural = 0;              // subdomain schedule: 0 longest first, 1 natural order
+  int nt = 256;                 // threads per workgroup of the subdomain solves
   int tuned = 0;                // 0 fixed tile, 1 searched, 2 from the autotuner cache
   bool tune_pending = false;
   double tune_ms = 0.0;
@@ -189,7 +190,7 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.if_row = h->d_if_row;
     a.if_coef = h->d_if_coef;
     a.done = done;
-    launch_ksolve<double>(a, h->TS, h->npad_max, h->st);
+    launch_ksolve<double>(a, h->TS, h->nt, h->npad_max, h->st);
   } else {
     KsolveArgs<float> a{};
     a.subs = h->d_subs;
@@ -210,7 +211,7 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.if_row = h->d_if_row;
     a.if_coef = h->d_if_coef;
     a.done = done;
-    launch_ksolve<float>(a, h->TS, h->npad_max, h->st);
+    launch_ksolve<float>(a, h->TS, h->nt, h->npad_max, h->st);
   }
 }
 
@@ -652,7 +653,7 @@ std::vector<int32_t> schedule(const HostModel& M, int natural) {
 }
 
 // Re-pack the current factor for tile TS and the given schedule.
-int retile(tfeti_handle* h, int TS, int natural) {
+int retile(tfeti_handle* h, int TS, int natural, int threads) {
   HostModel& M = h->M;
   const int64_t pe = assign_panels(M, TS);
   if (pe > h->panel_alloc) return fail(h, TFETI_E_INVALID, "internal: panel storage too small for the tile");
@@ -660,6 +661,7 @@ int retile(tfeti_handle* h, int TS, int natural) {
   h->panel_entries = pe;
   h->TS = TS;
   h->natural = natural;
+  h->nt = threads;
   const std::vector<int32_t> order = schedule(M, natural);
   HIPCHK(hipMemcpyAsync(h->d_subs, M.subs.data(), M.subs.size() * sizeof(SubDev), hipMemcpyHostToDevice, h->st));
   HIPCHK(hipMemcpyAsync(h->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
@@ -727,7 +729,7 @@ int autotune(tfeti_handle* h) {
   const std::string path = env ? env : "";
   TuneChoice c;
   if (!path.empty() && tune_cache_lookup(path, key, &c)) {
-    RC(retile(h, c.tile, c.natural));
+    RC(retile(h, c.tile, c.natural, c.threads));
     h->tuned = 2;
     h->tune_ms = c.ms;
     return 0;
@@ -737,18 +739,24 @@ int autotune(tfeti_handle* h) {
   best.ms = -1.0;
   for (int TS : {32, 64, 16})
     for (int nat : {0, 1}) {
-      RC(retile(h, TS, nat));
+      RC(retile(h, TS, nat, 256));
       const double tp = time_pack(h);
-      const double tf = time_fapply(h, 20);
-      const double ms = (tp >= 0 && tf > 0) ? kAppliesPerFactor * tf + tp : -1.0;
-      if (ms > 0 && (best.ms < 0 || ms < best.ms)) {
-        best.tile = TS;
-        best.natural = nat;
-        best.ms = ms;
+      for (int nt : {256, 512, 1024}) {
+        if (nt == 1024 && TS > 32) continue;
+        h->nt = nt;
+        drop_graphs(h);
+        const double tf = time_fapply(h, 20);
+        const double ms = (tp >= 0 && tf > 0) ? kAppliesPerFactor * tf + tp : -1.0;
+        if (ms > 0 && (best.ms < 0 || ms < best.ms)) {
+          best.tile = TS;
+          best.natural = nat;
+          best.threads = nt;
+          best.ms = ms;
+        }
       }
     }
   if (best.ms < 0) return fail(h, TFETI_E_HIP, "autotuner: no F-apply could be timed");
-  RC(retile(h, best.tile, best.natural));
+  RC(retile(h, best.tile, best.natural, best.threads));
   h->tuned = 1;
   h->tune_ms = best.ms;
   if (!path.empty()) (void)tune_cache_store(path, key, best);
@@ -1080,6 +1088,7 @@ int tfeti_get_sizes(const tfeti_handle* h, tfeti_sizes* o) {
   o->precision = h->prec;
   o->schedule = h->natural;
   o->autotuned = h->tuned;
+  o->threads = h->nt;
   return TFETI_OK;
 }
 
@@ -1436,6 +1445,7 @@ extern "C" int tfeti_model_host(const tfeti_problem* prob, int32_t tile, tfeti_s
   sizes->precision = -1;
   sizes->schedule = 0;
   sizes->autotuned = 0;
+  sizes->threads = 256;
   if (nnz) *nnz = (int64_t)M.b_col.size();
   if (rowptr) std::memcpy(rowptr, M.b_rowptr.data(), M.b_rowptr.size() * sizeof(int64_t));
   if (col) std::memcpy(col, M.b_col.data(), M.b_col.size() * sizeof(int64_t));

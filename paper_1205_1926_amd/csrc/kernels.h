@@ -85,7 +85,7 @@ struct KsolveArgs {
   int32_t part_off;           // LDS offset (entries of T) of the partial sums; set by the launcher
 };
 template <typename T>
-void launch_ksolve(const KsolveArgs<T>& a, int TS, int npad_max, hipStream_t st);
+void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st);
 
 // ---- dual-space kernels (FP64) ---------------------------------------------
 struct DualMaps {

@@ -3,9 +3,9 @@
 // subdomain) fused with the B^T scatter and the interface write of the dual
 // operator F = B K^+ B^T (Section 4.2).
 //
-// One workgroup per subdomain, in a schedule order chosen by the host
-// (longest subdomain first); the whole subdomain vector lives in LDS.  Each
-// triangular solve walks the block rows (TS rows each): all four waves
+// One workgroup (256, 512 or 1024 threads) per subdomain, in a schedule order
+// chosen by the host; the whole subdomain vector lives in LDS.  Each
+// triangular solve walks the block rows (TS rows each): all waves
 // stream the off-diagonal panel chunks (16-byte loads, one output row per
 // lane, coalesced) and accumulate partial dot products; wave 0 reduces them
 // and applies the inverted diagonal tile with lane broadcasts.
@@ -63,11 +63,10 @@ __device__ __forceinline__ auto vdot(const VT& a, const VT& b) -> decltype(a[0] 
 
 }  // namespace
 
-template <typename T, int TS>
-__global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
+template <typename T, int TS, int NT>
+__global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   using VT = typename Vec<T>::type;
   constexpr int V = Vec<T>::V;
-  constexpr int NT = 256;
   constexpr int RPT = NT / TS;           // threads per tile row
   constexpr int UNR = 4;                 // panel chunks loaded back to back per lane
   extern __shared__ __align__(16) unsigned char smem[];
@@ -252,22 +251,36 @@ __global__ __launch_bounds__(256) void ksolve_kernel(KsolveArgs<T> A) {
   }
 }
 
+template <typename T, int NT>
+static void launch_ts(const KsolveArgs<T>& b, int TS, size_t shm, hipStream_t st) {
+  dim3 grid((unsigned)b.nsub), block(NT);
+  if (TS == 16)
+    ksolve_kernel<T, 16, NT><<<grid, block, shm, st>>>(b);
+  else if (TS == 32)
+    ksolve_kernel<T, 32, NT><<<grid, block, shm, st>>>(b);
+  else if constexpr (NT <= 512)
+    ksolve_kernel<T, 64, NT><<<grid, block, shm, st>>>(b);
+}
+
 template <typename T>
-void launch_ksolve(const KsolveArgs<T>& a, int TS, int npad_max, hipStream_t st) {
-  // shared memory: the vector (npad_max entries, rounded to 16 bytes) + 256 partials
+void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st) {
+  // shared memory: the vector (npad_max entries, rounded to 16 bytes) + one
+  // partial sum per thread
+  // 1024 threads only with tiles of 16 or 32 rows (the 64-row kernel needs
+  // more registers than 16 waves per compute unit leave)
+  const int NT = (threads == 1024 && TS <= 32) ? 1024 : (threads == 512 ? 512 : 256);
   size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
-  size_t shm = vec + 256 * sizeof(T);
+  size_t shm = vec + (size_t)NT * sizeof(T);
   KsolveArgs<T> b = a;
   b.part_off = (int32_t)(vec / sizeof(T));
-  dim3 grid((unsigned)a.nsub), block(256);
-  if (TS == 16)
-    ksolve_kernel<T, 16><<<grid, block, shm, st>>>(b);
-  else if (TS == 32)
-    ksolve_kernel<T, 32><<<grid, block, shm, st>>>(b);
+  if (NT == 1024)
+    launch_ts<T, 1024>(b, TS, shm, st);
+  else if (NT == 512)
+    launch_ts<T, 512>(b, TS, shm, st);
   else
-    ksolve_kernel<T, 64><<<grid, block, shm, st>>>(b);
+    launch_ts<T, 256>(b, TS, shm, st);
 }
-template void launch_ksolve<double>(const KsolveArgs<double>&, int, int, hipStream_t);
-template void launch_ksolve<float>(const KsolveArgs<float>&, int, int, hipStream_t);
+template void launch_ksolve<double>(const KsolveArgs<double>&, int, int, int, hipStream_t);
+template void launch_ksolve<float>(const KsolveArgs<float>&, int, int, int, hipStream_t);
 
 }  // namespace tfeti

@@ -4,6 +4,8 @@ replay on):
 
 * the 4x4x4-subdomain cube (139 968 torn DOFs): the first load steps against
   the FP64 oracle, displacement bar 1e-6;
+* the uneven 8x8x8-subdomain mesh (512 subdomains of 6..10 elements per
+  axis): a dual solve's properties and the FP32/FP64 agreement;
 * the 10x10x10-subdomain cube (2 187 000 torn DOFs): K^+ on sampled
   subdomains against the oracle's factor of the same 8^3 subdomain (outputs
   the oracle can compute one by one), and properties that hold at any size
@@ -46,6 +48,7 @@ def rel(a, b):
 
 
 SOLVED = {}
+UNEVEN = {}
 
 
 @pytest.fixture(scope="module")
@@ -132,3 +135,30 @@ def test_cube10_dual_solve_properties(precision, dev, mesh4):
     SOLVED[precision] = u
     if "fp64" in SOLVED and "fp32" in SOLVED:
         assert rel(SOLVED["fp32"], SOLVED["fp64"]) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uneven8_dual_solve_properties(precision, dev):
+    from paper_1205_1926_amd import GpuSolver
+    w = W.config(2)
+    mesh = UNEVEN.setdefault("mesh", Mesh(w))
+    g = GpuSolver(w, use_graph=1, precision=precision)
+    n = g.sizes["n_torn"]
+    g.begin_load_step()
+    g.assemble(g.zeros(n))
+    g.factorize()
+    f = mesh.torn_load(w.load_factor(1))
+    lam, u, rep, rc = g.dual_pcg(T(f, dev))
+    assert rep["converged"] == 1
+    lam, u = lam.cpu().numpy(), u.cpu().numpy()
+    assert np.linalg.norm(mesh.B @ u) <= 1e-7 * np.linalg.norm(u)
+    r = f - mesh.B.T @ lam
+    worst = 0.0
+    for s in mesh.subs:
+        sl = slice(s.off, s.off + s.n_dofs)
+        worst = max(worst, np.abs(rigid_modes(s).T @ r[sl]).max() / max(np.abs(f[sl]).max(), np.abs(r[sl]).max()))
+    assert worst <= 1e-9
+    g.close()
+    UNEVEN[precision] = u
+    if "fp64" in UNEVEN and "fp32" in UNEVEN:
+        assert rel(UNEVEN["fp32"], UNEVEN["fp64"]) <= 1e-6
