@@ -80,10 +80,10 @@ def describe(w, sz) -> str:
             f"{sz['m']} multipliers, clamped bottom, top face {load}, load ramp over {w.steps} steps")
 
 
-def measured_traffic(workload: str, precision: str, tile: int):
+def measured_traffic(workload: str, precision: str, tile: int, threads: int):
     """HBM bytes per launch of the F-apply solve kernel from the committed
     FETCH_SIZE/WRITE_SIZE summary, or None if that summary was taken on
-    another workload, kernel source or tile."""
+    another workload, kernel source, tile or workgroup size."""
     import hashlib
     if workload != "cube10x10x10_sub8":
         return None
@@ -95,7 +95,7 @@ def measured_traffic(workload: str, precision: str, tile: int):
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, IndexError, ValueError):
         return None
-    ent = rec.get(precision, {}).get(str(tile))
+    ent = rec.get(precision, {}).get(f"{tile}/{threads}")
     if rec.get("ksolve_sha256") != sha or not ent:
         return None
     return ent["traffic_bytes"]
@@ -232,7 +232,7 @@ def main() -> int:
     log(f"timed: {fapplies} F-applies in {elapsed:.3f} s; solve kernel mean {mean_kernel_s * 1e3:.3f} ms "
         f"over {k_cnt}; isolated F-apply {iso * 1e3:.3f} ms (kernel {iso_kernel_s * 1e3:.3f} ms)")
 
-    traffic = measured_traffic(w.name, args.precision, sz["tile"])
+    traffic = measured_traffic(w.name, args.precision, sz["tile"], sz["threads"])
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
