@@ -62,9 +62,27 @@ void launch_gather(const DualMaps& M, const double* iface, double* out, const do
 }
 
 // ---------------------------------------------------------------- G w
+// six sums of a workgroup at once: wave shuffles, then the waves' results
+// in order (fixed order, deterministic)
+__device__ __forceinline__ void block_sum6(double (&acc)[6], double (*sh)[6]) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+    for (int off = 32; off > 0; off >>= 1) acc[j] += __shfl_down(acc[j], off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sh[w][j] = acc[j];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double s = 0.0;
+    for (int k = 0; k < RB / 64; ++k) s += sh[k][threadIdx.x];
+    acc[0] = s;  // thread j < 6 holds sum j
+  }
+}
+
 __global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* __restrict__ w,
                                                      double* __restrict__ c, const int32_t* __restrict__ done) {
-  __shared__ double sh[RB];
+  __shared__ double sh[RB / 64][6];
   if (done && *done) return;
   const int64_t p = blockIdx.x;
   const SubDev s = M.subs[p];
@@ -76,10 +94,8 @@ __global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* _
     const double* R = M.R_iface + 6 * it;
     for (int j = 0; j < 6; ++j) acc[j] += R[j] * v;
   }
-  for (int j = 0; j < 6; ++j) {
-    double s6 = block_sum(acc[j], sh);
-    if (threadIdx.x == 0) c[6 * p + j] = s6;
-  }
+  block_sum6(acc, sh);
+  if (threadIdx.x < 6) c[6 * p + threadIdx.x] = acc[0];
 }
 
 void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st) {
@@ -89,7 +105,7 @@ void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t
 // ---------------------------------------------------------------- R^T f
 __global__ __launch_bounds__(RB) void rt_apply_kernel(DualMaps M, const double* __restrict__ f,
                                                       double* __restrict__ c) {
-  __shared__ double sh[RB];
+  __shared__ double sh[RB / 64][6];
   const int64_t p = blockIdx.x;
   const SubDev s = M.subs[p];
   double acc[6] = {0, 0, 0, 0, 0, 0};
@@ -98,10 +114,8 @@ __global__ __launch_bounds__(RB) void rt_apply_kernel(DualMaps M, const double* 
     const double* R = M.R_full + 6 * (s.dof_off + ld);
     for (int j = 0; j < 6; ++j) acc[j] += R[j] * v;
   }
-  for (int j = 0; j < 6; ++j) {
-    double s6 = block_sum(acc[j], sh);
-    if (threadIdx.x == 0) c[6 * p + j] = s6;
-  }
+  block_sum6(acc, sh);
+  if (threadIdx.x < 6) c[6 * p + threadIdx.x] = acc[0];
 }
 
 void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t st) {
@@ -171,15 +185,31 @@ __global__ __launch_bounds__(256) void coarse_symv_kernel(int64_t l, int64_t lp,
   }
 }
 
+// 64 outputs per workgroup; the four waves sum interleaved quarters of the
+// partials (4 loads in flight each), then wave 0 adds the quarters in order
 __global__ __launch_bounds__(256) void coarse_reduce_kernel(int64_t l, int64_t lp, int nT,
                                                             const double* __restrict__ part, double* __restrict__ a,
                                                             double scale, const int32_t* __restrict__ done) {
+  __shared__ double q4[4][64];
   if (done && *done) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= l) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int k = 0; k < nT; ++k) s += part[(int64_t)k * lp + i];
-  a[i] = scale * s;
+  if (i < l) {
+    int k = w;
+    for (; k + 12 < nT; k += 16) {
+      const double v0 = part[(int64_t)k * lp + i], v1 = part[(int64_t)(k + 4) * lp + i];
+      const double v2 = part[(int64_t)(k + 8) * lp + i], v3 = part[(int64_t)(k + 12) * lp + i];
+      s += v0;
+      s += v1;
+      s += v2;
+      s += v3;
+    }
+    for (; k < nT; k += 4) s += part[(int64_t)k * lp + i];
+  }
+  q4[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < l) a[i] = scale * (((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane]);
 }
 
 int64_t coarse_tiles(int64_t l) {
@@ -197,8 +227,8 @@ void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double sc
   const int nT = (int)((M.l + CT - 1) / CT);
   const int64_t lp = (int64_t)nT * CT;
   coarse_symv_kernel<<<dim3((unsigned)coarse_tiles(M.l)), dim3(256), 0, st>>>(M.l, lp, M.Gpk, c, M.Gpart, done);
-  coarse_reduce_kernel<<<dim3((unsigned)((M.l + 255) / 256)), dim3(256), 0, st>>>(M.l, lp, nT, M.Gpart, a, scale,
-                                                                                  done);
+  coarse_reduce_kernel<<<dim3((unsigned)((M.l + 63) / 64)), dim3(256), 0, st>>>(M.l, lp, nT, M.Gpart, a, scale,
+                                                                                done);
 }
 
 // ---------------------------------------------------------------- x - G^T a
