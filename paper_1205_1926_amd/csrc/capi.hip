@@ -74,6 +74,7 @@ struct tfeti_handle {
   double *d_u = nullptr, *d_du = nullptr, *d_f1 = nullptr, *d_df = nullptr, *d_fint = nullptr, *d_f = nullptr,
          *d_delta = nullptr;
   // PCGP work
+  double* d_zfull = nullptr;     // FP32 mode: K^+ (f - B^T lambda) of the last outer residual
   double *d_lam = nullptr, *d_lam_im = nullptr, *d_lam_ker = nullptr, *d_r = nullptr, *d_w = nullptr,
          *d_z = nullptr, *d_y = nullptr, *d_p = nullptr, *d_q = nullptr, *d_lam_prev = nullptr,
          *d_dt = nullptr, *d_lam_acc = nullptr;
@@ -509,6 +510,7 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
   }
   PcgScalars Sh{};
   int total_iters = 0, outer = 0;
+  bool z_valid = false;  // d_zfull = K^+ (f - B^T lambda) for the final lambda
   bool converged = false;
   double r_final = r_ref;
   if (!mixed) {
@@ -523,14 +525,20 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
     r_final = Sh.rr;
   } else {
     const double eps_floor = h->opt.refine_eps > 0 ? h->opt.refine_eps : 1e-5;
+    z_valid = false;
     const int max_outer = 50;
     for (;;) {
-      // outer residual r = d~ - F64 lambda_acc (FP64), rho = P r (already in
-      // d_r before the first sweep)
+      // outer residual r = d - F64 lambda = B z with z = K^+ (f - B^T lambda),
+      // lambda = lambda_Im + lambda_acc, in one FP64 pass that also keeps z
+      // for the displacement recovery; rho = P r (the candidate's residual is
+      // already in d_r before the first sweep)
+      z_valid = false;
       if (outer > 0) {
-        launch_copy(m, h->d_dt, h->d_r, h->st);
-        fapply(h, lam_acc, h->d_q, nullptr, nullptr, nullptr, false, true);
-        launch_axpby(m, -1.0, h->d_q, 1.0, h->d_r, h->st);
+        launch_copy(m, h->d_lam_im, h->d_lam, h->st);
+        launch_axpby(m, 1.0, lam_acc, 1.0, h->d_lam, h->st);
+        ksolve(h, f, h->d_lam, -1.0, h->d_iface, h->d_zfull, nullptr, nullptr, true);
+        launch_gather(h->dm, h->d_iface, h->d_r, nullptr, nullptr, nullptr, h->st);
+        z_valid = true;
         fapplies++;
         fapplies64++;
       }
@@ -546,6 +554,7 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
         status = TFETI_W_PCG_MAXIT;
         break;
       }
+      z_valid = false;
       // inner PCGP on P F32 delta = rho from delta = 0
       launch_axpby(m, 0.0, nullptr, 0.0, h->d_lam_ker, h->st);
       // inner tolerance: the reduction still needed (with a factor 2 of
@@ -567,8 +576,14 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
   // in FP32 mode; the recursively updated PCGP residual in FP64 mode)
   launch_g_apply(h->dm, h->d_r, h->d_c, nullptr, h->st);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, -1.0, nullptr, h->st);
-  // u = K^+ (f - B^T lambda) + R alpha (FP64 operator)
-  if (u_out) ksolve(h, f, h->d_lam, -1.0, nullptr, u_out, h->d_a, nullptr, true);
+  // u = K^+ (f - B^T lambda) + R alpha (FP64 operator; the last outer
+  // residual's subdomain solve when it was made with the final lambda)
+  if (u_out) {
+    if (z_valid)
+      launch_add_rigid(h->dm, h->d_zfull, h->d_a, u_out, h->st);
+    else
+      ksolve(h, f, h->d_lam, -1.0, nullptr, u_out, h->d_a, nullptr, true);
+  }
   HIPCHK(hipStreamSynchronize(h->st));
   HIPCHK(hipGetLastError());
   h->last_f64 = fapplies64;
@@ -963,6 +978,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_fint, M.n_torn));
   RC(dalloc(h, &h->d_f, M.n_torn));
   RC(dalloc(h, &h->d_delta, M.n_torn));
+  if (h->prec == TFETI_PREC_FP32) RC(dalloc(h, &h->d_zfull, M.n_torn));
   double** mv[] = {&h->d_lam, &h->d_lam_im, &h->d_lam_ker, &h->d_r,        &h->d_w,  &h->d_z,      &h->d_y,
                    &h->d_p,   &h->d_q,      &h->d_lam_prev, &h->d_dt, &h->d_lam_acc,
                    &h->d_cl[0], &h->d_cl[1], &h->d_cr[0],  &h->d_cr[1],   &h->d_lam_conv, &h->d_lam_learn,

@@ -122,6 +122,24 @@ void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t 
   rt_apply_kernel<<<dim3((unsigned)M.nsub), dim3(RB), 0, st>>>(M, f, c);
 }
 
+// ---------------------------------------------------------------- u = z + R alpha
+__global__ __launch_bounds__(RB) void add_rigid_kernel(DualMaps M, const double* __restrict__ z,
+                                                       const double* __restrict__ alpha, double* __restrict__ u) {
+  const int64_t p = blockIdx.x;
+  const SubDev s = M.subs[p];
+  const double* al = alpha + 6 * p;
+  const double a0 = al[0], a1 = al[1], a2 = al[2], a3 = al[3], a4 = al[4], a5 = al[5];
+  for (int ld = threadIdx.x; ld < s.ndof; ld += RB) {
+    const int64_t d = s.dof_off + ld;
+    const double* R = M.R_full + 6 * d;
+    u[d] = z[d] + R[0] * a0 + R[1] * a1 + R[2] * a2 + R[3] * a3 + R[4] * a4 + R[5] * a5;
+  }
+}
+
+void launch_add_rigid(const DualMaps& M, const double* z, const double* alpha, double* u, hipStream_t st) {
+  add_rigid_kernel<<<dim3((unsigned)M.nsub), dim3(RB), 0, st>>>(M, z, alpha, u);
+}
+
 // ---------------------------------------------------------------- coarse solve
 // a = scale * Ginv c with the symmetric (G G^T)^{-1} stored as its lower
 // CT x CT tiles (I >= J, tile t = I (I+1)/2 + J, row-major, zero-padded past

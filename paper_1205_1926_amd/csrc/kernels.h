@@ -115,6 +115,8 @@ void launch_gather(const DualMaps& M, const double* iface, double* out, const do
 void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st);
 // c[6p+j] = sum_ld R_full[ld][j] f[ld]       (R^T f)
 void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t st);
+// u = z + R alpha per subdomain (torn vectors; alpha 6 per subdomain)
+void launch_add_rigid(const DualMaps& M, const double* z, const double* alpha, double* u, hipStream_t st);
 // a = scale * Ginv c
 void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double scale, const int32_t* done,
                         hipStream_t st);
