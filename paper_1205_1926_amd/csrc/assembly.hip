@@ -239,19 +239,53 @@ void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStre
 }
 
 // K_bb values for the lumped preconditioner (before regularization)
+// K_bb values of the lumped preconditioner, read from the assembled band:
+// one thread per lane slot of a group walks its neighbour mask in bit order
+// and writes the three entries (components 0, 1, 2) coupling its touched
+// DOF to each masked node, zeros past its own count; the band position of
+// entry (f, f2) is row max(f, f2), column min(f, f2).
 template <typename T>
-__global__ void gather_kbb_kernel(const int64_t* __restrict__ pos, int64_t n, const double* __restrict__ band,
-                                  T* __restrict__ out) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) out[q] = (T)band[pos[q]];
+__global__ __launch_bounds__(256) void gather_kbb_kernel(DualMaps M, const double* __restrict__ band,
+                                                         T* __restrict__ out) {
+  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = slot / 64;
+  if (g >= M.kbb_groups) return;
+  const int lane = (int)(slot % 64);
+  const int nb = M.kbb_gnb[g];
+  T* o = out + M.kbb_goff[g] + lane;
+  const int32_t it = M.kbb_row[slot];
+  uint32_t mask = M.kbb_mask[slot];
+  int b = 0;
+  if (it >= 0) {
+    const SubDev s = M.subs[M.kbb_gsub[g]];
+    const int32_t ld = M.if_ldof[it], a = ld / 3;
+    const int32_t f = factor_index(s, ld);
+    const double* A = band + s.band_off;
+    for (; mask; ++b) {
+      const int k = __ffs(mask) - 1;
+      mask &= mask - 1;
+      const int32_t a2 = a + (k % 3 - 1) + s.N[0] * ((k / 3) % 3 - 1 + s.N[1] * (k / 9 - 1));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int32_t f2 = factor_index(s, 3 * a2 + c);
+        const int32_t r = f > f2 ? f : f2, cc = f > f2 ? f2 : f;
+        o[(int64_t)(3 * b + c) * 64] = (T)A[(int64_t)r * s.Wb + (cc - r + s.b)];
+      }
+    }
+  }
+  for (; b < nb; ++b)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[(int64_t)(3 * b + c) * 64] = T(0);
 }
 
 template <typename T>
-void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, T* out, hipStream_t st) {
-  if (n > 0) gather_kbb_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(pos, n, band, out);
+void launch_gather_kbb(const DualMaps& M, const double* band, T* out, hipStream_t st) {
+  const int64_t slots = 64 * M.kbb_groups;
+  if (slots > 0)
+    gather_kbb_kernel<T><<<dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st>>>(M, band, out);
 }
-template void launch_gather_kbb<double>(const int64_t*, int64_t, const double*, double*, hipStream_t);
-template void launch_gather_kbb<float>(const int64_t*, int64_t, const double*, float*, hipStream_t);
+template void launch_gather_kbb<double>(const DualMaps&, const double*, double*, hipStream_t);
+template void launch_gather_kbb<float>(const DualMaps&, const double*, float*, hipStream_t);
 
 // K_reg = K + rho Q Q^T at the fixing DOFs, rho = max_j K[j, j] (Remark 1)
 __global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restrict__ subs, int64_t count,

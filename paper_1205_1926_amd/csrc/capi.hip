@@ -36,21 +36,23 @@ struct tfeti_handle {
   int32_t *d_subpl = nullptr, *d_flist = nullptr;
   int64_t last_refactored = 0;
   int prec = 0;
-  int npad_max = 0, max_iface = 0, bmax = 0, chol_nb = 0;
+  int npad_max = 0, max_iface = 0, max_ndof = 0, bmax = 0, chol_nb = 0;
   int64_t panel_entries = 0;
   std::vector<void*> allocs;
   // maps
   SubDev* d_subs = nullptr;
   int32_t* d_order = nullptr;
-  int32_t *d_if_fidx = nullptr, *d_if_ldof = nullptr, *d_if_rp = nullptr, *d_if_row = nullptr, *d_if_sub = nullptr;
+  int32_t *d_if_fidx = nullptr, *d_if_ldof = nullptr, *d_if_rp = nullptr, *d_if_row = nullptr, *d_b_sub = nullptr;
+  uint32_t *d_b_pk = nullptr, *d_if_pk = nullptr;
+  double* d_rscale = nullptr;
   double* d_if_coef = nullptr;
   int64_t* d_b_rowptr = nullptr;
   int32_t* d_b_iface = nullptr;
   double* d_b_val = nullptr;
-  double *d_R_full = nullptr, *d_R_iface = nullptr;
-  int32_t* d_kbb_rp = nullptr;
-  uint16_t* d_kbb_col = nullptr;  // local to the subdomain's touched DOFs
-  int64_t* d_kbb_band = nullptr;
+  double* d_R_full = nullptr;
+  int32_t *d_kbb_row = nullptr, *d_kbb_gnb = nullptr, *d_kbb_gsub = nullptr, *d_kbb_g0 = nullptr;
+  uint32_t* d_kbb_mask = nullptr;
+  int64_t* d_kbb_goff = nullptr;
   double* d_kbb_val = nullptr;    // FP64 mode
   float* d_kbb_val32 = nullptr;   // FP32 mode
   int64_t* d_g_first = nullptr;
@@ -633,9 +635,9 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   launch_pad_identity(h->d_subs, M.n_sub, h->d_band, h->st);
   // the lumped preconditioner uses the unregularized tangent
   if (h->prec == TFETI_PREC_FP64)
-    launch_gather_kbb<double>(h->d_kbb_band, (int64_t)M.kbb_band.size(), h->d_band, h->d_kbb_val, h->st);
+    launch_gather_kbb<double>(h->dm, h->d_band, h->d_kbb_val, h->st);
   else
-    launch_gather_kbb<float>(h->d_kbb_band, (int64_t)M.kbb_band.size(), h->d_band, h->d_kbb_val32, h->st);
+    launch_gather_kbb<float>(h->dm, h->d_band, h->d_kbb_val32, h->st);
   unsigned long long cnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
@@ -881,14 +883,18 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   for (const SubDev& s : M.subs) {
     h->npad_max = std::max(h->npad_max, s.npad);
     h->max_iface = std::max(h->max_iface, s.n_iface);
+    h->max_ndof = std::max(h->max_ndof, s.ndof);
     h->bmax = std::max(h->bmax, s.b);
+  }
+  {
+    int dev = 0, lds = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if ((int64_t)h->max_ndof * (int64_t)sizeof(double) > (int64_t)lds)
+      return fail(h, TFETI_E_INVALID, "a subdomain has too many DOFs for the preconditioner's LDS vector");
   }
   // schedule: longest subdomain first (stable)
   const std::vector<int32_t> order = schedule(M, 0);
-  // if_sub map
-  std::vector<int32_t> if_sub(M.n_iface);
-  for (int64_t p = 0; p < M.n_sub; ++p)
-    for (int32_t t = 0; t < M.subs[p].n_iface; ++t) if_sub[M.subs[p].iface_off + t] = (int32_t)p;
   // dN table [gp][node][axis] from B_g
   std::vector<double> dN(8 * 8 * 3);
   for (int g = 0; g < 8; ++g)
@@ -905,32 +911,24 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(upload(h, &h->d_if_rp, M.if_rp));
   RC(upload(h, &h->d_if_row, M.if_row));
   RC(upload(h, &h->d_if_coef, M.if_coef));
-  RC(upload(h, &h->d_if_sub, if_sub));
+  RC(upload(h, &h->d_if_pk, M.if_pk));
+  RC(upload(h, &h->d_b_sub, M.b_sub));
+  RC(upload(h, &h->d_b_pk, M.b_pk));
+  RC(upload(h, &h->d_rscale, M.rscale));
   RC(upload(h, &h->d_b_rowptr, M.b_rowptr));
   RC(upload(h, &h->d_b_iface, M.b_iface));
   RC(upload(h, &h->d_b_val, M.b_val));
   RC(upload(h, &h->d_R_full, M.R_full));
-  RC(upload(h, &h->d_R_iface, M.R_iface));
-  RC(upload(h, &h->d_kbb_rp, M.kbb_rp));
-  {
-    // K_bb columns as indices local to the subdomain's touched DOFs (16 bits)
-    std::vector<uint16_t> col16(M.kbb_col.size());
-    for (int64_t p = 0; p < M.n_sub; ++p) {
-      const SubDev& sd = M.subs[p];
-      if (sd.n_iface > 65535) return fail(h, TFETI_E_INVALID, "a subdomain has more than 65535 touched DOFs");
-      for (int32_t t = 0; t < sd.n_iface; ++t) {
-        const int64_t it = sd.iface_off + t;
-        for (int32_t q = M.kbb_rp[it]; q < M.kbb_rp[it + 1]; ++q)
-          col16[q] = (uint16_t)(M.kbb_col[q] - sd.iface_off);
-      }
-    }
-    RC(upload(h, &h->d_kbb_col, col16));
-  }
-  RC(upload(h, &h->d_kbb_band, M.kbb_band));
+  RC(upload(h, &h->d_kbb_row, M.kbb_row));
+  RC(upload(h, &h->d_kbb_mask, M.kbb_mask));
+  RC(upload(h, &h->d_kbb_goff, M.kbb_goff));
+  RC(upload(h, &h->d_kbb_gnb, M.kbb_gnb));
+  RC(upload(h, &h->d_kbb_gsub, M.kbb_gsub));
+  RC(upload(h, &h->d_kbb_g0, M.kbb_g0));
   if (h->prec == TFETI_PREC_FP64)
-    RC(dalloc(h, &h->d_kbb_val, (int64_t)M.kbb_band.size()));
+    RC(dalloc(h, &h->d_kbb_val, M.kbb_goff.back()));
   else
-    RC(dalloc(h, &h->d_kbb_val32, (int64_t)M.kbb_band.size()));
+    RC(dalloc(h, &h->d_kbb_val32, M.kbb_goff.back()));
   RC(upload(h, &h->d_g_first, M.g_first));
   RC(upload(h, &h->d_g_rp, M.g_rp));
   RC(upload(h, &h->d_g_copies, M.g_copies));
@@ -996,7 +994,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_iface, M.n_iface));
   RC(dalloc(h, &h->d_c, M.lc_pad));
   RC(dalloc(h, &h->d_a, M.lc_pad));
-  RC(dalloc(h, &h->d_partials, 1024));
+  RC(dalloc(h, &h->d_partials, 4096));
   RC(dalloc(h, &h->d_scal, 16));
   RC(dalloc(h, &h->d_S, 1));
   RC(dalloc(h, &h->d_fail, 1));
@@ -1031,15 +1029,24 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   dm.if_rp = h->d_if_rp;
   dm.if_row = h->d_if_row;
   dm.if_coef = h->d_if_coef;
-  dm.if_sub = h->d_if_sub;
-  dm.R_iface = h->d_R_iface;
+  dm.if_pk = h->d_if_pk;
+  dm.b_sub = h->d_b_sub;
+  dm.b_pk = h->d_b_pk;
+  dm.rscale = h->d_rscale;
+  for (int a = 0; a < 3; ++a) dm.hh[a] = 0.5 * M.h[a];
   dm.R_full = h->d_R_full;
-  dm.kbb_rp = h->d_kbb_rp;
-  dm.kbb_col = h->d_kbb_col;
+  dm.if_ldof = h->d_if_ldof;
+  dm.kbb_row = h->d_kbb_row;
+  dm.kbb_mask = h->d_kbb_mask;
+  dm.kbb_goff = h->d_kbb_goff;
+  dm.kbb_gnb = h->d_kbb_gnb;
+  dm.kbb_gsub = h->d_kbb_gsub;
+  dm.kbb_g0 = h->d_kbb_g0;
+  dm.kbb_groups = (int64_t)M.kbb_gnb.size();
   dm.Ginv = h->d_Ginv;
   dm.Gpk = h->d_Gpk;
   dm.Gpart = h->d_Gpart;
-  dm.max_iface = h->max_iface;
+  dm.max_ndof = h->max_ndof;
   // ---- coarse problem: banded Cholesky of G G^T, then the dense inverse ----
   {
     double* d_cb = nullptr;

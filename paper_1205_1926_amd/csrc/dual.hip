@@ -12,7 +12,7 @@ namespace tfeti {
 
 namespace {
 constexpr int RB = 256;            // threads of reduction blocks
-constexpr int kMaxRedBlocks = 1024;
+constexpr int kMaxRedBlocks = 4096;
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
@@ -44,8 +44,19 @@ __global__ __launch_bounds__(RB) void gather_kernel(int64_t m, const int64_t* __
   if (done && *done) return;
   double acc = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < m; r += (int64_t)gridDim.x * RB) {
-    double q = 0.0;
-    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) q += val[e] * iface[ent[e]];
+    // the first two entries' loads are issued together (most rows have two)
+    // every row has an entry; the second one's index is clamped so that all
+    // loads are unconditional and in flight together
+    const int64_t e0 = rp[r], e1 = rp[r + 1];
+    const bool h1 = e0 + 1 < e1;
+    const int64_t f1 = h1 ? e0 + 1 : e0;
+    const int32_t i0 = ent[e0], i1 = ent[f1];
+    const double v0 = val[e0], v1 = val[f1];
+    const double x0 = iface[i0], x1 = iface[i1];
+    double q = v0 * x0;
+    const double q2 = q + v1 * x1;
+    q = h1 ? q2 : q;
+    for (int64_t e = e0 + 2; e < e1; ++e) q += val[e] * iface[ent[e]];
     out[r] = q;
     if (dotv) acc += q * dotv[r];
   }
@@ -80,22 +91,51 @@ __device__ __forceinline__ void block_sum6(double (&acc)[6], double (*sh)[6]) {
   }
 }
 
+// One workgroup per subdomain streams the subdomain's B^T entries (U per
+// thread in flight): v = coef * w[row] lands on the raw modes of the entry's
+// node (translation of its component; rotations by its centred coordinates);
+// the six sums are scaled to the orthonormal modes at the end.
 __global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* __restrict__ w,
                                                      double* __restrict__ c, const int32_t* __restrict__ done) {
   __shared__ double sh[RB / 64][6];
   if (done && *done) return;
   const int64_t p = blockIdx.x;
-  const SubDev s = M.subs[p];
+  const int64_t t0 = M.subs[p].iface_off;
+  const int32_t e0 = M.if_rp[t0], e1 = M.if_rp[t0 + M.subs[p].n_iface];
+  const double hh[3] = {M.hh[0], M.hh[1], M.hh[2]};
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int t = threadIdx.x; t < s.n_iface; t += RB) {
-    const int64_t it = s.iface_off + t;
-    double v = 0.0;
-    for (int e = M.if_rp[it]; e < M.if_rp[it + 1]; ++e) v += M.if_coef[e] * w[M.if_row[e]];
-    const double* R = M.R_iface + 6 * it;
-    for (int j = 0; j < 6; ++j) acc[j] += R[j] * v;
+  constexpr int U = 4;
+  for (int32_t eb = e0 + (int32_t)threadIdx.x; eb < e1; eb += U * RB) {
+    int32_t row[U];
+    uint32_t pk[U];
+    double cf[U], wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t e = eb + u * RB < e1 ? eb + u * RB : eb;  // clamped: loads stay unconditional
+      row[u] = M.if_row[e];
+      pk[u] = M.if_pk[e];
+      cf[u] = eb + u * RB < e1 ? M.if_coef[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) wv[u] = w[row[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double v = cf[u] * wv[u];
+      double x, y, z;
+      const int32_t cc = rigid_unpack(pk[u], hh, x, y, z);
+      acc[0] += cc == 0 ? v : 0.0;
+      acc[1] += cc == 1 ? v : 0.0;
+      acc[2] += cc == 2 ? v : 0.0;
+      acc[3] += (cc == 0 ? -y : (cc == 1 ? x : 0.0)) * v;
+      acc[4] += (cc == 1 ? -z : (cc == 2 ? y : 0.0)) * v;
+      acc[5] += (cc == 0 ? z : (cc == 2 ? -x : 0.0)) * v;
+    }
   }
   block_sum6(acc, sh);
-  if (threadIdx.x < 6) c[6 * p + threadIdx.x] = acc[0];
+  if (threadIdx.x < 6) {
+    const double* sc = M.rscale + 4 * p;
+    c[6 * p + threadIdx.x] = acc[0] * sc[threadIdx.x < 3 ? 0 : threadIdx.x - 2];
+  }
 }
 
 void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st) {
@@ -203,31 +243,36 @@ __global__ __launch_bounds__(256) void coarse_symv_kernel(int64_t l, int64_t lp,
   }
 }
 
-// 64 outputs per workgroup; the four waves sum interleaved quarters of the
-// partials (4 loads in flight each), then wave 0 adds the quarters in order
+// 16 outputs per workgroup, 16 slices of the partials per output (up to 8
+// loads in flight per thread), then the slices added in a fixed order
 __global__ __launch_bounds__(256) void coarse_reduce_kernel(int64_t l, int64_t lp, int nT,
                                                             const double* __restrict__ part, double* __restrict__ a,
                                                             double scale, const int32_t* __restrict__ done) {
-  __shared__ double q4[4][64];
+  __shared__ double q[16][17];
   if (done && *done) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int o = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + o;
   double s = 0.0;
   if (i < l) {
-    int k = w;
-    for (; k + 12 < nT; k += 16) {
-      const double v0 = part[(int64_t)k * lp + i], v1 = part[(int64_t)(k + 4) * lp + i];
-      const double v2 = part[(int64_t)(k + 8) * lp + i], v3 = part[(int64_t)(k + 12) * lp + i];
-      s += v0;
-      s += v1;
-      s += v2;
-      s += v3;
+    for (int k0 = sl; k0 < nT; k0 += 8 * 16) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + 16 * u;
+        v[u] = k < nT ? part[(int64_t)k * lp + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
     }
-    for (; k < nT; k += 4) s += part[(int64_t)k * lp + i];
   }
-  q4[w][lane] = s;
+  q[sl][o] = s;
   __syncthreads();
-  if (w == 0 && i < l) a[i] = scale * (((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane]);
+  if (sl == 0 && i < l) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += q[k][o];
+    a[i] = scale * t;
+  }
 }
 
 int64_t coarse_tiles(int64_t l) {
@@ -245,29 +290,58 @@ void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double sc
   const int nT = (int)((M.l + CT - 1) / CT);
   const int64_t lp = (int64_t)nT * CT;
   coarse_symv_kernel<<<dim3((unsigned)coarse_tiles(M.l)), dim3(256), 0, st>>>(M.l, lp, M.Gpk, c, M.Gpart, done);
-  coarse_reduce_kernel<<<dim3((unsigned)((M.l + 63) / 64)), dim3(256), 0, st>>>(M.l, lp, nT, M.Gpart, a, scale,
+  coarse_reduce_kernel<<<dim3((unsigned)((M.l + 15) / 16)), dim3(256), 0, st>>>(M.l, lp, nT, M.Gpart, a, scale,
                                                                                 done);
 }
 
 // ---------------------------------------------------------------- x - G^T a
+// One multiplier row per thread: (G^T a)_r = sum_e b_val[e] R(node_e) . a_p(e),
+// the mode values of the entry's node formed from its packed coordinates.
 __global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* __restrict__ x,
                                                       const double* __restrict__ a, double sign,
                                                       double* __restrict__ out, double* __restrict__ partials,
                                                       const int32_t* __restrict__ done) {
   __shared__ double sh[RB];
   if (done && *done) return;
+  const double hh[3] = {M.hh[0], M.hh[1], M.hh[2]};
   double acc = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < M.m; r += (int64_t)gridDim.x * RB) {
+    const int64_t e0 = M.b_rowptr[r], e1 = M.b_rowptr[r + 1];
+    const double xr = x ? x[r] : 0.0;
     double g = 0.0;
-    for (int64_t e = M.b_rowptr[r]; e < M.b_rowptr[r + 1]; ++e) {
-      const int32_t t = M.b_iface[e];
-      const double* R = M.R_iface + 6 * (int64_t)t;
-      const double* ap = a + 6 * (int64_t)M.if_sub[t];
-      double v = 0.0;
-      for (int j = 0; j < 6; ++j) v += R[j] * ap[j];
-      g += M.b_val[e] * v;
+    // entries two at a time, the second one's index clamped so that every
+    // load is unconditional and in flight together
+    for (int64_t e = e0; e < e1; e += 2) {
+      const bool h1 = e + 1 < e1;
+      const int64_t f1 = h1 ? e + 1 : e;
+      const int32_t p0 = M.b_sub[e], p1 = M.b_sub[f1];
+      const uint32_t k0 = M.b_pk[e], k1 = M.b_pk[f1];
+      const double bv0 = M.b_val[e], bv1 = M.b_val[f1];
+      double s0[4], s1[4], a0[6], a1[6];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s0[j] = M.rscale[4 * (int64_t)p0 + j];
+        s1[j] = M.rscale[4 * (int64_t)p1 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        a0[j] = a[6 * (int64_t)p0 + j];
+        a1[j] = a[6 * (int64_t)p1 + j];
+      }
+      double x0, y0, z0, x1, y1, z1, R0[6], R1[6];
+      rigid_row(rigid_unpack(k0, hh, x0, y0, z0), x0, y0, z0, s0, R0);
+      rigid_row(rigid_unpack(k1, hh, x1, y1, z1), x1, y1, z1, s1, R1);
+      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        v0 += R0[j] * a0[j];
+        v1 += R1[j] * a1[j];
+      }
+      g += bv0 * v0;
+      const double g2 = g + bv1 * v1;
+      g = h1 ? g2 : g;
     }
-    double o = (x ? x[r] : 0.0) - sign * g;
+    double o = xr - sign * g;
     out[r] = o;
     acc += o * o;
   }
@@ -283,42 +357,81 @@ void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double
 }
 
 // ---------------------------------------------------------------- lumped preconditioner
+// One workgroup per subdomain.  B^T w is scattered into an LDS copy of the
+// whole subdomain vector (zero off the touched DOFs).  Then each wavefront
+// takes groups of 64 touched DOFs (one per lane; the group's values are
+// stored slot-major, so every load is 64 consecutive values) and walks the
+// lanes' neighbour masks LU nodes at a time, summing values x neighbour
+// components in bit order (fixed order, deterministic); lanes with fewer
+// nodes than the group read zero values against their own node.
+namespace {
+constexpr int LT = 512;  // threads of the preconditioner workgroups
+constexpr int LU = 4;    // neighbour nodes per step
+}  // namespace
+
 template <typename TV>
-__global__ __launch_bounds__(RB) void lumped_kernel(DualMaps M, const double* __restrict__ w,
+__global__ __launch_bounds__(LT) void lumped_kernel(DualMaps M, const double* __restrict__ w,
                                                     const TV* __restrict__ kv, double* __restrict__ out,
                                                     const int32_t* __restrict__ done) {
   extern __shared__ double vloc[];
   if (done && *done) return;
   const int64_t p = blockIdx.x;
-  const int32_t nif = M.subs[p].n_iface;
+  const int32_t nif = M.subs[p].n_iface, ndof = M.subs[p].ndof, N0 = M.subs[p].N[0], N1 = M.subs[p].N[1];
   const int64_t ioff = M.subs[p].iface_off;
-  for (int t = threadIdx.x; t < nif; t += RB) {
+  for (int q = threadIdx.x; q < ndof; q += LT) vloc[q] = 0.0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < nif; t += LT) {
+    // every touched DOF has an entry: the first one's loads are unconditional
     const int64_t it = ioff + t;
-    double v = 0.0;
-    for (int e = M.if_rp[it]; e < M.if_rp[it + 1]; ++e) v += M.if_coef[e] * w[M.if_row[e]];
-    vloc[t] = v;
+    const int32_t e0 = M.if_rp[it], e1 = M.if_rp[it + 1], ld = M.if_ldof[it];
+    double v = M.if_coef[e0] * w[M.if_row[e0]];
+    for (int e = e0 + 1; e < e1; ++e) v += M.if_coef[e] * w[M.if_row[e]];
+    vloc[ld] = v;
   }
   __syncthreads();
-  // K_bb rows: a group of 16 lanes per row streams the row's entries
-  // (coalesced), then reduces by shuffles in a fixed order
-  constexpr int G = 16;
-  const int lane = threadIdx.x % G;
-  for (int t = threadIdx.x / G; t < nif; t += RB / G) {
-    const int64_t it = ioff + t;
-    const int q0 = M.kbb_rp[it], q1 = M.kbb_rp[it + 1];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int32_t g1 = M.kbb_g0[p + 1];
+  for (int32_t g = M.kbb_g0[p] + wave; g < g1; g += LT / 64) {
+    const int64_t slot = 64 * (int64_t)g + lane;
+    const int32_t it = M.kbb_row[slot];
+    uint32_t mask = M.kbb_mask[slot];
+    const int nb = M.kbb_gnb[g];
+    const TV* v = kv + M.kbb_goff[g] + lane;
+    const int32_t a = it >= 0 ? M.if_ldof[it] / 3 : 0;
     double y = 0.0;
-    for (int q = q0 + lane; q < q1; q += G) y += (double)kv[q] * vloc[M.kbb_col[q]];
+    for (int b0 = 0; b0 < nb; b0 += LU) {
+      int a2[LU];
+      TV x[3 * LU];
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) y += __shfl_down(y, off, G);
-    if (lane == 0) out[it] = y;
+      for (int u = 0; u < LU; ++u) {
+        const int k = mask ? __ffs(mask) - 1 : 13;  // 13: the node itself
+        mask &= mask - 1;
+        a2[u] = a + (k % 3 - 1) + N0 * ((k / 3) % 3 - 1 + N1 * (k / 9 - 1));
+        // past the group's count: the last block is read again and zeroed
+        const bool in = b0 + u < nb;
+        const int bb = in ? b0 + u : nb - 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const TV t = v[(int64_t)(3 * bb + c) * 64];
+          x[3 * u + c] = in ? t : TV(0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < LU; ++u)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) y += (double)x[3 * u + c] * vloc[3 * a2[u] + c];
+    }
+    if (it >= 0) out[it] = y;
   }
 }
 
 template <typename TV>
 void launch_lumped(const DualMaps& M, const double* w, const TV* kbb_val, double* iface_out, const int32_t* done,
                    hipStream_t st) {
-  size_t shm = (size_t)(M.max_iface > 0 ? M.max_iface : 1) * sizeof(double);
-  lumped_kernel<TV><<<dim3((unsigned)M.nsub), dim3(RB), shm, st>>>(M, w, kbb_val, iface_out, done);
+  size_t shm = (size_t)(M.max_ndof > 0 ? M.max_ndof : 1) * sizeof(double);
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void*)lumped_kernel<TV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  lumped_kernel<TV><<<dim3((unsigned)M.nsub), dim3(LT), shm, st>>>(M, w, kbb_val, iface_out, done);
 }
 template void launch_lumped<double>(const DualMaps&, const double*, const double*, double*, const int32_t*,
                                     hipStream_t);

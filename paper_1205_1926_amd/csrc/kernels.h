@@ -32,8 +32,6 @@ void launch_return_map(const tfeti_material& mat, int64_t npts, const double* si
                        const double* de, double* ds, double* dk, double* Dt, uint8_t* pl, hipStream_t st);
 void launch_assemble(const AssembleArgs& args, hipStream_t st);
 void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStream_t st);
-template <typename T>
-void launch_gather_kbb(const int64_t* pos, int64_t n, const double* band, T* out, hipStream_t st);
 // list: subdomain indices (count of them), or NULL for subdomains 0 .. count-1
 void launch_regularize(const SubDev* subs, int64_t count, const int32_t* list, const double* QQt, double* band,
                        hipStream_t st);
@@ -97,15 +95,25 @@ struct DualMaps {
   const int32_t* if_rp;
   const int32_t* if_row;
   const double* if_coef;
-  const int32_t* if_sub;
-  const double* R_iface;
+  const uint32_t* if_pk;       // packed centred node coordinates per B^T entry
+  const int32_t* b_sub;        // subdomain per B entry
+  const uint32_t* b_pk;        // packed centred node coordinates per B entry
+  const double* rscale;        // 4 per subdomain: inverse norms of the raw rigid modes
+  double hh[3];                // half element edge lengths
   const double* R_full;
-  const int32_t* kbb_rp;
-  const uint16_t* kbb_col;    // column, local to the subdomain's touched DOFs
+  const int32_t* if_ldof;      // local natural DOF of each touched DOF
+  // K_bb in wavefront groups of 64 touched DOFs (lane slot = 64 group + lane)
+  const int32_t* kbb_row;      // touched DOF of each lane slot, -1 past the end
+  const uint32_t* kbb_mask;    // its touched nodes among the 27 around its node
+  const int64_t* kbb_goff;     // value offset of each group
+  const int32_t* kbb_gnb;      // neighbour blocks of each group (values 3 x 64 per block)
+  const int32_t* kbb_gsub;     // subdomain of each group
+  const int32_t* kbb_g0;       // first group of each subdomain (nsub + 1)
+  int64_t kbb_groups;
   const double* Ginv;          // dense (G G^T)^{-1}, l x l (setup only)
   const double* Gpk;           // its lower 64 x 64 tiles, packed (coarse solves)
   double* Gpart;               // per-tile partial products, ceil(l/64) x roundup(l, 64)
-  int32_t max_iface;          // largest per-subdomain touched-DOF count (LDS of the preconditioner)
+  int32_t max_ndof;           // largest subdomain DOF count (LDS of the preconditioner)
 };
 
 // out[r] = sum_e b_val[e] * iface[b_iface[e]]; if dotv: partial sums of out.dotv
@@ -127,6 +135,9 @@ void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
                      double* partials, const int32_t* done, hipStream_t st);
 // iface_out = K_bb (B^T w) per subdomain
+// K_bb values of every subdomain from the assembled (unregularized) band
+template <typename T>
+void launch_gather_kbb(const DualMaps& M, const double* band, T* out, hipStream_t st);
 template <typename TV>
 void launch_lumped(const DualMaps& M, const double* w, const TV* kbb_val, double* iface_out,
                    const int32_t* done, hipStream_t st);

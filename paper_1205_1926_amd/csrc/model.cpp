@@ -302,40 +302,37 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
       }
   }
 
-  // ---- rigid body modes (translations, rotations about the centroid) ----
+  // ---- rigid body modes: closed form on the centred box grid ----
   M.R_full.assign(6 * M.n_torn, 0.0);
+  M.rscale.assign(4 * M.n_sub, 0.0);
   M.QQt.assign(81 * M.n_sub, 0.0);
+  const double hh[3] = {0.5 * M.h[0], 0.5 * M.h[1], 0.5 * M.h[2]};
+  auto node_pack = [&](const SubDev& s, int32_t ldof) {
+    int32_t a = ldof / 3, c = ldof - 3 * a;
+    int32_t i = a % s.N[0], j = (a / s.N[0]) % s.N[1], k = a / (s.N[0] * s.N[1]);
+    return rigid_pack(2 * i - (s.N[0] - 1), 2 * j - (s.N[1] - 1), 2 * k - (s.N[2] - 1), c);
+  };
   for (int64_t p = 0; p < M.n_sub; ++p) {
     const SubDev& s = M.subs[p];
+    if (s.N[0] > 512 || s.N[1] > 512 || s.N[2] > 512) return "a subdomain has more than 512 nodes on an axis";
     int64_t nn = s.ndof / 3;
-    double cx = 0, cy = 0, cz = 0;
-    std::vector<double> X(3 * nn);
-    for (int32_t k = 0; k < s.N[2]; ++k)
-      for (int32_t j = 0; j < s.N[1]; ++j)
-        for (int32_t i = 0; i < s.N[0]; ++i) {
-          int32_t a = i + s.N[0] * (j + s.N[1] * k);
-          X[3 * a + 0] = (M.sub_e0[3 * p] + i) * M.h[0];
-          X[3 * a + 1] = (M.sub_e0[3 * p + 1] + j) * M.h[1];
-          X[3 * a + 2] = (M.sub_e0[3 * p + 2] + k) * M.h[2];
-          cx += X[3 * a];
-          cy += X[3 * a + 1];
-          cz += X[3 * a + 2];
-        }
-    cx /= nn;
-    cy /= nn;
-    cz /= nn;
-    double* R = &M.R_full[6 * s.dof_off];
-    for (int64_t a = 0; a < nn; ++a) {
-      double x = X[3 * a] - cx, y = X[3 * a + 1] - cy, z = X[3 * a + 2] - cz;
-      double* r0 = R + 6 * (3 * a + 0);
-      double* r1 = R + 6 * (3 * a + 1);
-      double* r2 = R + 6 * (3 * a + 2);
-      r0[0] = 1.0; r1[1] = 1.0; r2[2] = 1.0;
-      r0[3] = -y; r1[3] = x;
-      r1[4] = -z; r2[4] = y;
-      r0[5] = z;  r2[5] = -x;
+    double sxy = 0.0, syz = 0.0, sxz = 0.0;
+    for (int32_t a = 0; a < nn; ++a) {
+      double x, y, z;
+      rigid_unpack(node_pack(s, 3 * a), hh, x, y, z);
+      sxy += x * x + y * y;
+      syz += y * y + z * z;
+      sxz += x * x + z * z;
     }
-    mgs(R, s.ndof, 6);
+    const double sc[4] = {1.0 / std::sqrt((double)nn), 1.0 / std::sqrt(sxy), 1.0 / std::sqrt(syz),
+                          1.0 / std::sqrt(sxz)};
+    for (int q = 0; q < 4; ++q) M.rscale[4 * p + q] = sc[q];
+    double* R = &M.R_full[6 * s.dof_off];
+    for (int32_t ld = 0; ld < s.ndof; ++ld) {
+      double x, y, z;
+      const int32_t c = rigid_unpack(node_pack(s, ld), hh, x, y, z);
+      rigid_row(c, x, y, z, sc, R + 6 * ld);
+    }
     // Q: orthonormal basis of the rows of R at the fixing DOFs
     double Rs[9 * 6];
     for (int q = 0; q < 9; ++q) {
@@ -358,40 +355,81 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
         Q[9 * i + j] = v;
       }
   }
-  M.R_iface.resize(6 * M.n_iface);
+  // packed node coordinates of every B entry and of every B^T entry
+  M.b_sub.resize(nnz);
+  M.b_pk.resize(nnz);
+  for (int64_t e = 0; e < nnz; ++e) {
+    M.b_sub[e] = e_sub[e];
+    M.b_pk[e] = node_pack(M.subs[e_sub[e]], e_ldof[e]);
+  }
+  M.if_pk.resize(nnz);
   for (int64_t p = 0; p < M.n_sub; ++p) {
     const SubDev& s = M.subs[p];
     for (int32_t t = 0; t < s.n_iface; ++t) {
-      int32_t ld = M.if_ldof[s.iface_off + t];
-      for (int j = 0; j < 6; ++j) M.R_iface[6 * (s.iface_off + t) + j] = M.R_full[6 * (s.dof_off + ld) + j];
+      const int64_t it = s.iface_off + t;
+      const uint32_t pk = node_pack(s, M.if_ldof[it]);
+      for (int32_t e = M.if_rp[it]; e < M.if_rp[it + 1]; ++e) M.if_pk[e] = pk;
     }
   }
 
-  // ---- K_bb pattern: touched DOF pairs whose nodes share an element ----
-  M.kbb_rp.assign(M.n_iface + 1, 0);
-  for (int64_t p = 0; p < M.n_sub; ++p) {
-    const SubDev& s = M.subs[p];
-    for (int32_t t = 0; t < s.n_iface; ++t) {
-      int32_t ld = M.if_ldof[s.iface_off + t];
-      int32_t a = ld / 3;
-      int32_t i = a % s.N[0], j = (a / s.N[0]) % s.N[1], k = a / (s.N[0] * s.N[1]);
-      int32_t f = M.if_fidx[s.iface_off + t];
-      for (int dk = -1; dk <= 1; ++dk)
-        for (int dj = -1; dj <= 1; ++dj)
-          for (int di = -1; di <= 1; ++di) {
-            int32_t ii = i + di, jj = j + dj, kk = k + dk;
-            if (ii < 0 || jj < 0 || kk < 0 || ii >= s.N[0] || jj >= s.N[1] || kk >= s.N[2]) continue;
-            int32_t a2 = ii + s.N[0] * (jj + s.N[1] * kk);
-            for (int c2 = 0; c2 < 3; ++c2) {
-              int32_t t2 = tidx[s.dof_off + 3 * a2 + c2];
-              if (t2 < 0) continue;
-              int32_t f2 = M.if_fidx[t2];
-              int32_t r = std::max(f, f2), cc = std::min(f, f2);
-              M.kbb_col.push_back(t2);
-              M.kbb_band.push_back(s.band_off + (int64_t)r * s.Wb + (cc - r + s.b));
+  // ---- K_bb (lumped preconditioner): per touched DOF, the touched nodes
+  //      among the 27 nodes around its own (bit 9 (dk+1) + 3 (dj+1) + di+1)
+  //      and three values (the three components) per such node.  The touched
+  //      DOFs of a subdomain are sorted by their node count (stable) and cut
+  //      into groups of 64, one wavefront each; a group stores its values
+  //      slot-major, value (3 b + c) of lane l at off + (3 b + c) 64 + l,
+  //      padded with zeros to the group's largest count. ----
+  {
+    std::vector<uint8_t> node_touched(M.n_torn / 3, 0);
+    for (int64_t e = 0; e < nnz; ++e) node_touched[M.b_col[e] / 3] = 1;
+    M.kbb_g0.assign(M.n_sub + 1, 0);
+    M.kbb_row.clear();
+    M.kbb_mask.clear();
+    M.kbb_goff.assign(1, 0);
+    M.kbb_gnb.clear();
+    M.kbb_gsub.clear();
+    for (int64_t p = 0; p < M.n_sub; ++p) {
+      const SubDev& s = M.subs[p];
+      std::vector<uint32_t> mask(s.n_iface);
+      std::vector<int32_t> ord(s.n_iface);
+      for (int32_t t = 0; t < s.n_iface; ++t) {
+        const int64_t it = s.iface_off + t;
+        int32_t a = M.if_ldof[it] / 3;
+        int32_t i = a % s.N[0], j = (a / s.N[0]) % s.N[1], k = a / (s.N[0] * s.N[1]);
+        uint32_t mk = 0;
+        for (int dk = -1; dk <= 1; ++dk)
+          for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+              int32_t ii = i + di, jj = j + dj, kk = k + dk;
+              if (ii < 0 || jj < 0 || kk < 0 || ii >= s.N[0] || jj >= s.N[1] || kk >= s.N[2]) continue;
+              int32_t a2 = ii + s.N[0] * (jj + s.N[1] * kk);
+              if (node_touched[s.dof_off / 3 + a2]) mk |= 1u << (9 * (dk + 1) + 3 * (dj + 1) + (di + 1));
             }
+        mask[t] = mk;
+        ord[t] = t;
+      }
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+        return __builtin_popcount(mask[x]) > __builtin_popcount(mask[y]);
+      });
+      const int32_t ng = (s.n_iface + 63) / 64;
+      for (int32_t g = 0; g < ng; ++g) {
+        int32_t nb = 0;
+        for (int32_t l = 0; l < 64; ++l) {
+          const int32_t q = 64 * g + l;
+          if (q < s.n_iface) {
+            M.kbb_row.push_back((int32_t)(s.iface_off + ord[q]));
+            M.kbb_mask.push_back(mask[ord[q]]);
+            nb = std::max(nb, __builtin_popcount(mask[ord[q]]));
+          } else {
+            M.kbb_row.push_back(-1);
+            M.kbb_mask.push_back(0u);
           }
-      M.kbb_rp[s.iface_off + t + 1] = (int32_t)M.kbb_col.size();
+        }
+        M.kbb_gnb.push_back(nb);
+        M.kbb_gsub.push_back((int32_t)p);
+        M.kbb_goff.push_back(M.kbb_goff.back() + (int64_t)3 * nb * 64);
+      }
+      M.kbb_g0[p + 1] = M.kbb_g0[p] + ng;
     }
   }
 
@@ -563,8 +601,6 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
     for (int q = 0; q < 9; ++q)
       if (s.fix[q] < 0 || s.fix[q] >= s.ndof) return "internal: fixing DOF out of range";
   }
-  for (size_t q = 0; q < M.kbb_band.size(); ++q)
-    if (M.kbb_band[q] < 0 || M.kbb_band[q] >= M.band_entries) return "internal: K_bb map out of range";
   for (size_t q = 0; q < M.wn_rows.size(); ++q)
     if (M.wn_rows[q] < -1 || M.wn_rows[q] >= M.m) return "internal: warm-start row map out of range";
   for (size_t q = 0; q < M.wn_elems.size(); ++q)

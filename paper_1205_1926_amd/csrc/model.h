@@ -41,11 +41,20 @@ struct HostModel {
   std::vector<double> if_coef;
   // rigid modes
   std::vector<double> R_full;           // n_torn * 6 (torn order)
-  std::vector<double> R_iface;          // n_iface * 6
-  // K_bb pattern (lumped preconditioner): CSR over touched DOFs
-  std::vector<int32_t> kbb_rp;          // n_iface + 1
-  std::vector<int32_t> kbb_col;         // global touched index
-  std::vector<int64_t> kbb_band;        // entry offset in the row-band storage
+  std::vector<double> rscale;           // 4 per subdomain: inverse norms of the raw modes
+  std::vector<int32_t> b_sub;           // subdomain of each B entry
+  std::vector<uint32_t> b_pk;           // packed centred node coordinates of each B entry
+  std::vector<uint32_t> if_pk;          // the same for each B^T entry (if_row order)
+  // K_bb (lumped preconditioner) in wavefront groups of 64 touched DOFs
+  // sorted by neighbour count: per lane slot the touched DOF (-1 past the
+  // end) and its 27-neighbour mask of touched nodes; per group the value
+  // offset, the block count and the subdomain; per subdomain its first group
+  std::vector<int32_t> kbb_row;         // 64 per group
+  std::vector<uint32_t> kbb_mask;       // 64 per group
+  std::vector<int64_t> kbb_goff;        // groups + 1
+  std::vector<int32_t> kbb_gnb;         // groups
+  std::vector<int32_t> kbb_gsub;        // groups
+  std::vector<int32_t> kbb_g0;          // n_sub + 1
   // untorn maps
   std::vector<int64_t> g_first;         // n_gdof: torn index of the lowest-p copy
   std::vector<int32_t> g_rp;            // n_gdof + 1

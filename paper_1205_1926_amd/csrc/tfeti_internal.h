@@ -49,6 +49,44 @@ __host__ __device__ inline int32_t factor_index(const SubDev& s, int32_t ldof) {
   return 3 * (i * s.fs[0] + j * s.fs[1] + k * s.fs[2]) + c;
 }
 
+// Rigid body modes of a box subdomain in closed form (the kernel of the
+// floating subdomain's stiffness, Section 2): with node (i, j, k) at the
+// coordinates (x, y, z) relative to the box centre, the three translations
+// and the rotations (-y, x, 0), (0, -z, y), (z, 0, -x) are mutually
+// orthogonal on a centred tensor grid, so scaling each by the inverse of its
+// norm gives an orthonormal basis.  A touched DOF carries its doubled
+// centred node coordinates 2 i - (N - 1) (signed 10-bit fields, so at most
+// 512 nodes per axis) and its component in one packed word; the host's
+// R values and the kernels use the same two roundings, x = (2 i - (N - 1))
+// (h / 2) and then x * s.
+__host__ __device__ inline uint32_t rigid_pack(int32_t xi, int32_t yi, int32_t zi, int32_t c) {
+  return ((uint32_t)xi & 1023u) | (((uint32_t)yi & 1023u) << 10) | (((uint32_t)zi & 1023u) << 20) |
+         ((uint32_t)c << 30);
+}
+// centred coordinates and component of a packed word; hh = half the element
+// edge lengths
+__host__ __device__ inline int32_t rigid_unpack(uint32_t pk, const double* hh, double& x, double& y, double& z) {
+  x = (double)((int32_t)(pk << 22) >> 22) * hh[0];
+  y = (double)((int32_t)(pk << 12) >> 22) * hh[1];
+  z = (double)((int32_t)(pk << 2) >> 22) * hh[2];
+  return (int32_t)(pk >> 30);
+}
+// the six mode values of one DOF; sc = (s_t, s_3, s_4, s_5), the inverse
+// norms of the translations and of the three rotations (selects only, so
+// device code keeps everything in registers)
+__host__ __device__ inline void rigid_row(int32_t c, double x, double y, double z, const double (&sc)[4],
+                                          double* R) {
+  R[0] = c == 0 ? sc[0] : 0.0;
+  R[1] = c == 1 ? sc[0] : 0.0;
+  R[2] = c == 2 ? sc[0] : 0.0;
+  const double r3a = -(y * sc[1]), r3b = x * sc[1];
+  const double r4a = -(z * sc[2]), r4b = y * sc[2];
+  const double r5a = z * sc[3], r5b = -(x * sc[3]);
+  R[3] = c == 0 ? r3a : (c == 1 ? r3b : 0.0);
+  R[4] = c == 1 ? r4a : (c == 2 ? r4b : 0.0);
+  R[5] = c == 0 ? r5a : (c == 2 ? r5b : 0.0);
+}
+
 // Panel geometry: entries of one layout for tile TS, vector width V.
 __host__ __device__ inline int64_t panel_entries(int32_t npad, int32_t bo, int32_t TS) {
   int64_t tot = 0;
