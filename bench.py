@@ -263,7 +263,7 @@ def main() -> int:
         "pcg_iters_per_s": pcg_iters / elapsed,
         "fapplies_total": fapplies,
         "learned_warm_start": args.learned,
-        "steps_detail": [{k: r[k] for k in ("iteration", "pcg_iters", "fapplies", "refactored", "warm_choice",
+        "steps_detail": [{k: r[k] for k in ("iteration", "pcg_iters", "fapplies", "refactored", "restored", "warm_choice",
                                              "plastic_gp", "ms_assembly", "ms_factor", "ms_pcg", "ms_total")}
                          for r in reps],
         "fapply_isolated": {"ms": iso * 1e3, "kernel_ms": iso_kernel_s * 1e3,

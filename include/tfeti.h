@@ -142,6 +142,12 @@ typedef struct {
   int32_t refactored;           /* subdomains factorized in this iteration (the
                                    others kept the factor of their unchanged
                                    elastic tangent)                              */
+  int32_t restored;             /* subdomains elastic again whose elastic factor
+                                   was copied back instead of factorized (the
+                                   library keeps every subdomain's elastic
+                                   factor once all were elastic at one
+                                   factorization; not with refactor_all)         */
+  int32_t pad;
 } tfeti_newton_report;
 
 typedef struct {

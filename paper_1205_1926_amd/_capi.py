@@ -48,7 +48,7 @@ class NewtonReport(C.Structure):
                 ("plastic_gp", C.c_int32), ("plastic_elements", C.c_int32), ("relres", C.c_double),
                 ("crit", C.c_double), ("ms_assembly", C.c_double), ("ms_factor", C.c_double),
                 ("ms_pcg", C.c_double), ("ms_total", C.c_double), ("warm_choice", C.c_int32),
-                ("refactored", C.c_int32)]
+                ("refactored", C.c_int32), ("restored", C.c_int32), ("pad", C.c_int32)]
 
 
 class Sizes(C.Structure):

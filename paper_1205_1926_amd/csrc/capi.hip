@@ -33,7 +33,12 @@ struct tfeti_handle {
   // factor reuse: subdomains whose current factor is of the elastic tangent
   std::vector<uint8_t> fact_elastic;
   std::vector<int32_t> subpl, flist;
-  int32_t *d_subpl = nullptr, *d_flist = nullptr;
+  int32_t *d_subpl = nullptr, *d_flist = nullptr, *d_rlist = nullptr;
+  // band factors of the elastic stiffness of every subdomain, kept from the
+  // first factorization in which every subdomain was elastic
+  double* d_eband = nullptr;
+  bool e_valid = false;
+  int64_t last_restored = 0;
   int64_t last_refactored = 0;
   int prec = 0;
   int npad_max = 0, max_iface = 0, max_ndof = 0, bmax = 0, chol_nb = 0;
@@ -789,14 +794,29 @@ int factorize(tfeti_handle* h) {
   const HostModel& M = h->M;
   std::vector<int32_t>& list = h->flist;
   list.clear();
+  std::vector<int32_t> restore;
   if (h->opt.refactor_all) {
     for (int64_t p = 0; p < M.n_sub; ++p) list.push_back((int32_t)p);
   } else {
     launch_sub_plastic(h->d_subs, M.n_sub, h->d_plastic, h->d_subpl, h->st);
     HIPCHK(hipMemcpyAsync(h->subpl.data(), h->d_subpl, M.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
-    for (int64_t p = 0; p < M.n_sub; ++p)
-      if (h->subpl[p] || !h->fact_elastic[p]) list.push_back((int32_t)p);
+    for (int64_t p = 0; p < M.n_sub; ++p) {
+      if (h->subpl[p])
+        list.push_back((int32_t)p);
+      else if (!h->fact_elastic[p])
+        (h->e_valid ? restore : list).push_back((int32_t)p);
+    }
+  }
+  // elastic again: the kept elastic factor is copied back and packed
+  h->last_restored = (int64_t)restore.size();
+  if (!restore.empty()) {
+    HIPCHK(hipMemcpyAsync(h->d_rlist, restore.data(), restore.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          h->st));
+    const int64_t cnt = (int64_t)restore.size();
+    launch_copy_band(h->d_subs, cnt, h->d_rlist, h->d_eband, (double*)h->d_work, h->st);
+    pack(h, cnt, h->d_rlist);
+    for (int32_t p : restore) h->fact_elastic[p] = 1;
   }
   h->last_refactored = (int64_t)list.size();
   if (!list.empty()) {
@@ -823,6 +843,13 @@ int factorize(tfeti_handle* h) {
   if (h->tune_pending) {
     h->tune_pending = false;
     RC(autotune(h));
+  }
+  // keep the elastic factors once every subdomain holds one
+  if (!h->opt.refactor_all && !h->e_valid && h->d_eband &&
+      std::all_of(h->fact_elastic.begin(), h->fact_elastic.end(), [](uint8_t v) { return v != 0; })) {
+    HIPCHK(hipMemcpyAsync(h->d_eband, h->d_work, (size_t)M.band_entries * sizeof(double), hipMemcpyDeviceToDevice,
+                          h->st));
+    h->e_valid = true;
   }
   return 0;
 }
@@ -955,6 +982,12 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     if (hipMalloc(&q, (size_t)M.band_entries * sizeof(double)) != hipSuccess) return fail(h, TFETI_E_OOM, "factor work");
     h->allocs.push_back(q);
     h->d_work = q;
+    if (!h->opt.refactor_all) {
+      if (hipMalloc(&q, (size_t)M.band_entries * sizeof(double)) != hipSuccess)
+        return fail(h, TFETI_E_OOM, "elastic factors");
+      h->allocs.push_back(q);
+      h->d_eband = (double*)q;
+    }
     if (hipMalloc(&q, (size_t)std::max<int64_t>(h->panel_alloc, 1) * fsz) != hipSuccess)
       return fail(h, TFETI_E_OOM, "forward panels");
     h->allocs.push_back(q);
@@ -1001,6 +1034,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_plcount, 1));
   RC(dalloc(h, &h->d_subpl, M.n_sub));
   RC(dalloc(h, &h->d_flist, M.n_sub));
+  RC(dalloc(h, &h->d_rlist, M.n_sub));
   h->fact_elastic.assign(M.n_sub, 0);
   h->subpl.assign(M.n_sub, 0);
   h->flist.reserve(M.n_sub);
@@ -1172,6 +1206,7 @@ int tfeti_newton_step(tfeti_handle* h, tfeti_newton_report* rep) {
   RC(factorize(h));
   r.ms_factor = ms_since(t1);
   r.refactored = (int32_t)h->last_refactored;
+  r.restored = (int32_t)h->last_restored;
   auto t2 = std::chrono::steady_clock::now();
   tfeti_pcg_report pr{};
   // warm-start candidates.  First Newton iteration: the tangent at a zero

@@ -284,8 +284,10 @@ def test_autotuner_choice_and_cache(tmp_path, monkeypatch, dev):
 
 
 def test_elastic_factor_reuse_is_exact(dev):
-    """Keeping the factor of subdomains whose tangent is and was elastic gives
-    bit-identical results to factorizing every subdomain each iteration."""
+    """Keeping the factor of subdomains whose tangent is and was elastic, and
+    copying back the kept elastic factor of subdomains that are elastic again,
+    gives bit-identical results to factorizing every subdomain each
+    iteration."""
     from paper_1205_1926_amd import GpuSolver
     w = W.small_cube(S=(3, 2, 2), n=(3, 3, 3), amp=650.0, shear=150.0, steps=3)
     runs = {}
@@ -300,6 +302,11 @@ def test_elastic_factor_reuse_is_exact(dev):
     assert counts[0] == n_sub
     assert min(counts) < n_sub          # elastic subdomains kept their factors
     assert all(r["refactored"] == n_sub for h in runs[1][0] for r in h)
+    # the first iteration of a later load step is elastic everywhere: the
+    # subdomains plastic at the end of the previous step get their kept
+    # elastic factor back instead of a factorization
+    assert sum(r["restored"] for h in runs[0][0] for r in h) > 0
+    assert all(r["restored"] == 0 for h in runs[1][0] for r in h)
     assert [len(h) for h in runs[0][0]] == [len(h) for h in runs[1][0]]
 
 
