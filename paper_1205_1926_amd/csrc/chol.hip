@@ -6,51 +6,61 @@
 // r-b+k, k = b the diagonal); rows are the subdomain DOFs in the factor
 // ordering, padded with identity rows to a multiple of 64.
 //
-// One workgroup (256 threads) per band matrix, right-looking by block
-// columns of NB: the panel (the NB block columns of every row the band
-// reaches, at most NB + b rows) is staged in LDS and factored column by
-// column with each row in a thread's registers (one barrier per column);
-// the panel is written back and the trailing
-// band window is updated from the LDS panel in 16 x 16 blocks on the FP64
-// matrix cores (FP32: 64 x 64 tiles, 4 x 4 outputs per thread), so global
-// traffic is one read-modify-write of the window per block column.
+// One workgroup (256 threads) per band matrix, left-looking by block columns
+// of NB.  Per block column J (the panel: the NB columns of every row the
+// band reaches, at most NB + b rows):
+//  U. the panel takes its updates from the finished columns in the band,
+//     A_panel - L_panel,k L_tile,k^T over k in [J - b, J), on the FP64
+//     matrix cores: the tile rows' L (negated) are staged in LDS, each
+//     wavefront keeps the accumulators of its row blocks in registers
+//     (initialized with the panel's entries) and streams its rows of L from
+//     memory 16 columns at a time, the next chunk's loads in flight;
+//  F. the accumulators become the LDS panel;
+//  D. the panel is factored column by column, each row in a thread's
+//     registers, one barrier per column;
+//  W. the panel is written back.
+// Finished columns are only read, so the band is written once per entry
+// and no store waits on the matrix-core chain.
 #include "kernels.h"
 
 namespace tfeti {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ T bcast_lane(T v, int l);
-template <>
-__device__ __forceinline__ float bcast_lane<float>(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-template <>
-__device__ __forceinline__ double bcast_lane<double>(double v, int l) {
-  long long x = __double_as_longlong(v);
-  int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), l);
-  int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int TT = 64;  // trailing-update tile edge
+// row stride (doubles) of the staged tile rows: whole 16-column chunks
+// covering b, plus 2 so that the 16 rows of a read start in distinct banks
+__host__ __device__ inline int tile_stride(int bmax) { return ((bmax + 15) / 16 * 16 + 29) / 32 * 32 + 2; }
 
 }  // namespace
 
-template <typename T, int NB>
+template <int NB, int G>
 __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                             const int32_t* __restrict__ list,
-                                                            T* __restrict__ W, int32_t* __restrict__ fail) {
+                                                            double* __restrict__ W, int32_t* __restrict__ fail,
+                                                            int LB) {
+  static_assert(NB % 16 == 0, "tile of whole 16 x 16 blocks");
   extern __shared__ __align__(16) unsigned char smem[];
-  T* Lp = reinterpret_cast<T*>(smem);          // panel rows x (NB + 1)
+  // phase U: the tile rows' negated L over the update columns (NB x LB);
+  // phases F..W: the panel (rows x LS), whose diagonal tile's rows hold L in
+  // slots 0..r and the transposed inverse, X[r'][r] at slot r' + 1 (r' >= r)
+  double* Bt = reinterpret_cast<double*>(smem);
+  double* P = reinterpret_cast<double*>(smem);
   constexpr int LS = NB + 1;
+  constexpr int KS = NB / 4;   // matrix-core steps over the panel columns
+  constexpr int NJ = NB / 16;  // column blocks of the panel
   __shared__ int s_fail;
+  __shared__ double s_rcp[NB];  // reciprocals of the tile's diagonal
   if ((int64_t)blockIdx.x >= count) return;
   const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
   const int b = subs[p].b, Wb = subs[p].Wb, n = subs[p].npad;
-  T* A = W + subs[p].band_off;
-  const int tid = threadIdx.x;
+  double* A = W + subs[p].band_off;
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
   if (tid == 0) s_fail = 0;
 
   for (int J = 0; J < n; J += NB) {
@@ -58,64 +68,196 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
     int rend = J + jb + b;
     if (rend > n) rend = n;
     const int nr = rend - J;                      // panel rows (>= jb)
-    // ---- stage the panel (8 loads in flight per thread) ----
-    for (int q0 = tid; q0 < nr * NB; q0 += 8 * 256) {
-      T v[8];
+    const int nbr = (nr + 15) / 16;               // panel row blocks
+    const int kbeg = J > b ? J - b : 0;           // first update column
+    const int nq = (J - kbeg + 15) / 16;          // 16-column update chunks
+    const bool multi = nbr > 4 * G;               // row blocks in several passes
+    // ---- U. updates from the finished columns ----
+    for (int q0 = tid; q0 < NB * 16 * nq; q0 += 8 * 256) {
+      double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = q0 + u * 256;
-        const int r = q / NB, j = q - (q / NB) * NB;
-        v[u] = (q < nr * NB && j < jb && j <= r && r - j <= b) ? A[(int64_t)(J + r) * Wb + (j - r + b)] : T(0);
+        const int c = q / (16 * nq), kk = q - c * (16 * nq);
+        const int row = J + c, k = kbeg + kk;
+        const int rc = row < rend ? row : rend - 1;
+        int kc = k > rc - b ? k : rc - b;
+        kc = kc < rc ? kc : rc;
+        v[u] = A[(int64_t)rc * Wb + (kc - rc + b)];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = q0 + u * 256;
-        if (q < nr * NB) Lp[(q / NB) * LS + (q - (q / NB) * NB)] = v[u];
+        const int c = q / (16 * nq), kk = q - c * (16 * nq);
+        const int row = J + c, k = kbeg + kk;
+        const bool in = c < jb && k < J && k >= row - b;
+        if (q < NB * 16 * nq) Bt[c * LB + kk] = in ? -v[u] : 0.0;
       }
     }
     __syncthreads();
-    // ---- panel factorization, column by column: thread r < blockDim.x
-    //      keeps row r of the panel in registers; at column j every row
-    //      below j takes L[r][j] = (x_r[j] - x_r[0:j] . L[j][0:j]) / L[j][j]
-    //      with row j read from LDS (one address for all lanes), and row j+1
-    //      completes its diagonal entry and publishes itself for the next
-    //      column; one barrier per column ----
+    // row blocks of this wavefront in pass `pass`: zigzag over groups of 4
+    auto row_block = [&](int pass, int g) { return 4 * G * pass + 4 * g + ((g & 1) ? 3 - wave : wave); };
+    d4 acc[G][NJ];
+    for (int pass = 0; pass * 4 * G < nbr; ++pass) {
+      // accumulators start from the panel's entries (zero outside the band)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int jc = 0; jc < NJ; ++jc)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int R = row_block(pass, g);
+            const int row = J + 16 * R + lk + 4 * r, col = J + 16 * jc + li;
+            const bool in = R < nbr && row < rend && col < J + jb && col <= row && row - col <= b;
+            const int rc = row < rend ? row : rend - 1;
+            int cc = col > rc - b ? col : rc - b;
+            cc = cc < rc ? cc : rc;
+            const double v = A[(int64_t)rc * Wb + (cc - rc + b)];
+            acc[g][jc][r] = in ? v : 0.0;
+          }
+      // one chunk: the next chunk's L rows are requested (clamped addresses,
+      // so unconditionally), this chunk's rows (copied from the previous
+      // request) meet the staged tile rows, and the request is copied over
+      // at the end, when the matrix-core chain has been issued
+      auto load_chunk = [&](int q, double (&a)[G][4]) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int R = row_block(pass, g);
+          const int row = J + 16 * R + li;
+          const int rc = row < rend ? row : rend - 1;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int k = kbeg + 16 * q + 4 * lk + s;
+            int kc = k > rc - b ? k : rc - b;
+            kc = kc < rc ? kc : rc;
+            a[g][s] = A[(int64_t)rc * Wb + (kc - rc + b)];
+          }
+        }
+      };
+      double a[G][4], an[G][4];
+      load_chunk(0, a);
+      for (int q = 0; q < nq; ++q) {
+        load_chunk(q + 1, an);
+        double bq[NJ][4];
+#pragma unroll
+        for (int jc = 0; jc < NJ; ++jc)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) bq[jc][s] = Bt[(16 * jc + li) * LB + 16 * q + 4 * lk + s];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int R = row_block(pass, g);
+          // rows of block R meet this chunk's columns inside the band?
+          if (R < nbr && kbeg + 16 * q + 15 >= J + 16 * R - b) {
+            const int row = J + 16 * R + li;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int k = kbeg + 16 * q + 4 * lk + s;
+              const double av = (row < rend && k < J && k >= row - b) ? a[g][s] : 0.0;
+#pragma unroll
+              for (int jc = 0; jc < NJ; ++jc) acc[g][jc] = mfma4(av, bq[jc][s], acc[g][jc]);
+            }
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[g][s] = an[g][s];
+      }
+      if (multi) {
+        // several passes: this pass's panel rows go back to memory and are
+        // staged with the others below
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int jc = 0; jc < NJ; ++jc)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int R = row_block(pass, g);
+              const int row = J + 16 * R + lk + 4 * r, col = J + 16 * jc + li;
+              if (R < nbr && row < rend && col < J + jb && col <= row && row - col <= b)
+                A[(int64_t)row * Wb + (col - row + b)] = acc[g][jc][r];
+            }
+      }
+    }
+    __syncthreads();
+    // ---- F. the LDS panel (zero outside the band and past jb) ----
+    if (!multi) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int jc = 0; jc < NJ; ++jc)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int R = row_block(0, g);
+            const int i = 16 * R + lk + 4 * r, j = 16 * jc + li;
+            if (R < nbr && i < nr) P[i * LS + j] = acc[g][jc][r];
+          }
+    } else {
+      for (int q = tid; q < nr * NB; q += 256) {
+        const int r = q / NB, j = q - (q / NB) * NB;
+        const bool in = j < jb && j <= r && r - j <= b;
+        const double x = A[in ? (int64_t)(J + r) * Wb + (j - r + b) : 0];
+        P[r * LS + j] = in ? x : 0.0;
+      }
+    }
+    __syncthreads();
+    // ---- D. panel factorization, column by column: thread r keeps row r
+    //      of the panel in registers (rows past the first 256 follow once
+    //      the tile is done); at column j every row below j takes
+    //      L[r][j] = (x_r[j] - x_r[0:j] . L[j][0:j]) / L[j][j] with row j
+    //      read from LDS (one address for all lanes) and 1 / L[j][j] from
+    //      the pivot, and row j+1 completes its diagonal entry and publishes
+    //      itself and the reciprocal for the next column; one barrier per
+    //      column.  Dot products run as two interleaved partial sums. ----
     {
       const int r = tid;
       const bool have = r < nr;
-      T x[NB];
+      double x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = have ? Lp[r * LS + j] : T(0);
+      for (int j = 0; j < NB; ++j) x[j] = have ? P[r * LS + j] : 0.0;
       bool bad = false;
       if (r == 0 && jb > 0) {
-        T d = x[0];
-        if (!(d > T(0))) {
+        double d = x[0];
+        if (!(d > 0.0)) {
           bad = true;
-          d = T(1);
+          d = 1.0;
         }
         x[0] = sqrt(d);
-        Lp[0] = x[0];
+        P[0] = x[0];
+        s_rcp[0] = 1.0 / x[0];
       }
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j < jb) {
           if (have && r > j) {
-            T v = x[j];
+            double v0 = x[j], v1 = 0.0;
 #pragma unroll
-            for (int k = 0; k < j; ++k) v -= x[k] * Lp[j * LS + k];
-            x[j] = v / Lp[j * LS + j];
+            for (int k = 0; k < j; ++k) {
+              if (k & 1)
+                v1 -= x[k] * P[j * LS + k];
+              else
+                v0 -= x[k] * P[j * LS + k];
+            }
+            x[j] = (v0 + v1) * s_rcp[j];
             if (r == j + 1 && j + 1 < jb) {
-              T d = x[j + 1];
+              double d0 = x[j + 1], d1 = 0.0;
 #pragma unroll
-              for (int k = 0; k <= j; ++k) d -= x[k] * x[k];
-              if (!(d > T(0))) {
+              for (int k = 0; k <= j; ++k) {
+                if (k & 1)
+                  d1 -= x[k] * x[k];
+                else
+                  d0 -= x[k] * x[k];
+              }
+              double d = d0 + d1;
+              if (!(d > 0.0)) {
                 bad = true;
-                d = T(1);
+                d = 1.0;
               }
               x[j + 1] = sqrt(d);
+              s_rcp[j + 1] = 1.0 / x[j + 1];
 #pragma unroll
-              for (int k = 0; k <= j + 1; ++k) Lp[r * LS + k] = x[k];
+              for (int k = 0; k <= j + 1; ++k) P[r * LS + k] = x[k];
             }
           }
           __syncthreads();
@@ -124,180 +266,38 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
       if (bad) s_fail = 1;
       if (have) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) Lp[r * LS + j] = x[j];
+        for (int j = 0; j < NB; ++j) P[r * LS + j] = x[j];
       }
     }
     __syncthreads();
-    // ---- rows past the first blockDim.x: solved against the finished
-    //      diagonal tile, independently ----
-    for (int r = (int)blockDim.x + tid; r < nr; r += blockDim.x) {
-      T x[NB];
+    // ---- rows past the first 256: solved against the finished diagonal
+    //      tile, independently ----
+    for (int r = 256 + tid; r < nr; r += 256) {
+      double x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = Lp[r * LS + j];
+      for (int j = 0; j < NB; ++j) x[j] = P[r * LS + j];
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j < jb) {
-          T v = x[j];
+          double v0 = x[j], v1 = 0.0;
 #pragma unroll
-          for (int k = 0; k < j; ++k) v -= x[k] * Lp[j * LS + k];
-          x[j] = v / Lp[j * LS + j];
+          for (int k = 0; k < j; ++k) {
+            if (k & 1)
+              v1 -= x[k] * P[j * LS + k];
+            else
+              v0 -= x[k] * P[j * LS + k];
+          }
+          x[j] = (v0 + v1) * s_rcp[j];
         }
       }
 #pragma unroll
-      for (int j = 0; j < NB; ++j) Lp[r * LS + j] = x[j];
+      for (int j = 0; j < NB; ++j) P[r * LS + j] = x[j];
     }
     __syncthreads();
-    // ---- write the panel back ----
+    // ---- W. write the panel back ----
     for (int q = tid; q < nr * NB; q += blockDim.x) {
       const int r = q / NB, j = q - (q / NB) * NB;
-      if (j < jb && j <= r && r - j <= b) A[(int64_t)(J + r) * Wb + (j - r + b)] = Lp[r * LS + j];
-    }
-    // ---- trailing update from the LDS panel (columns >= J + jb only) ----
-    if constexpr (sizeof(T) == 8) {
-      // 16 x 16 blocks of the lower band window on the FP64 matrix cores:
-      // block (RB, CB) accumulates P_R P_C^T over the panel columns, 4 at a
-      // time (lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; output r
-      // of lane l is D[l / 16 + 4 r][l % 16])
-      const int nwin = nr - jb, nbw = (nwin + 15) / 16;
-      const int wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
-      const int nblk = nbw * (nbw + 1) / 2;
-      typedef double d4 __attribute__((ext_vector_type(4)));
-      // this wave's blocks are q = wave + 4 i; they are processed BT at a
-      // time, the window values of the next batch loaded while the current
-      // batch runs its (interleaved) matrix-core chains
-      constexpr int BT = 4;
-      const int nmine = nblk > wave ? (nblk - wave + 3) / 4 : 0;
-      auto block_of = [&](int i, int& RB, int& CB) -> bool {
-        const int q = wave + 4 * i;
-        if (i >= nmine) return false;
-        RB = (int)sqrtf(2.0f * (float)q);
-        while (RB * (RB + 1) / 2 > q) --RB;
-        while ((RB + 1) * (RB + 2) / 2 <= q) ++RB;
-        CB = q - RB * (RB + 1) / 2;
-        return RB * 16 - (CB * 16 + 15) <= b;  // inside the band
-      };
-      auto load_batch = [&](int i0, T (&c)[BT][4]) {
-#pragma unroll
-        for (int t = 0; t < BT; ++t) {
-          int RB = 0, CB = 0;
-          const bool ok = block_of(i0 + t, RB, CB);
-          const int row0 = J + jb + RB * 16 + lk, col = J + jb + CB * 16 + li;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = row0 + 4 * r;
-            const bool in = ok && row < rend && col <= row && row - col <= b;
-            c[t][r] = in ? A[(int64_t)row * Wb + (col - row + b)] : T(0);
-          }
-        }
-      };
-      T cur[BT][4], nxt[BT][4];
-      if (nmine > 0) load_batch(0, cur);
-      for (int i0 = 0; i0 < nmine; i0 += BT) {
-        if (i0 + BT < nmine) load_batch(i0 + BT, nxt);
-        int ra[BT], rb[BT], row0[BT], col[BT];
-        bool ok[BT];
-#pragma unroll
-        for (int t = 0; t < BT; ++t) {
-          int RB = 0, CB = 0;
-          ok[t] = block_of(i0 + t, RB, CB);
-          ra[t] = jb + RB * 16 + li;
-          rb[t] = jb + CB * 16 + li;
-          row0[t] = J + jb + RB * 16 + lk;
-          col[t] = J + jb + CB * 16 + li;
-        }
-        d4 acc[BT];
-#pragma unroll
-        for (int t = 0; t < BT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-        // operand rows past the panel (and blocks outside the band) read
-        // row 0 instead: their products only reach outputs that are not
-        // written back, so they need no zeroing, only an address in bounds
-        const T* pa[BT];
-        const T* pb[BT];
-#pragma unroll
-        for (int t = 0; t < BT; ++t) {
-          pa[t] = Lp + (ok[t] && ra[t] < nr ? ra[t] : 0) * LS + lk;
-          pb[t] = Lp + (ok[t] && rb[t] < nr ? rb[t] : 0) * LS + lk;
-        }
-        if (jb == NB) {
-#pragma unroll
-          for (int k0 = 0; k0 < NB; k0 += 4) {
-            double av[BT], bv[BT];
-#pragma unroll
-            for (int t = 0; t < BT; ++t) {
-              av[t] = (double)pa[t][k0];
-              bv[t] = (double)pb[t][k0];
-            }
-#pragma unroll
-            for (int t = 0; t < BT; ++t)
-              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[t], 0, 0, 0);
-          }
-        } else {
-          for (int k0 = 0; k0 < jb; k0 += 4) {
-            const bool kin = k0 + lk < jb;
-            double av[BT], bv[BT];
-#pragma unroll
-            for (int t = 0; t < BT; ++t) {
-              av[t] = kin ? (double)pa[t][k0] : 0.0;
-              bv[t] = kin ? (double)pb[t][k0] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < BT; ++t)
-              acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc[t], 0, 0, 0);
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < BT; ++t) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = row0[t] + 4 * r;
-            if (ok[t] && row < rend && col[t] <= row && row - col[t] <= b)
-              A[(int64_t)row * Wb + (col[t] - row + b)] = cur[t][r] - (T)acc[t][r];
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < BT; ++t)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) cur[t][r] = nxt[t][r];
-      }
-    } else {
-      const int rbeg = J + jb;
-      const int ty = tid / 16, tx = tid % 16;
-      for (int RT = rbeg; RT < rend; RT += TT) {
-        for (int CT = rbeg; CT <= RT; CT += TT) {
-          if (RT - (CT + TT - 1) > b) continue;
-          int ri[4], ci[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            int r = RT + ty * 4 + u - J;
-            ri[u] = (r < nr ? r : nr - 1) * LS;
-            int c = CT + tx + 16 * u - J;
-            ci[u] = (c < nr ? c : nr - 1) * LS;
-          }
-          T acc[4][4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[u][v] = T(0);
-          for (int k = 0; k < jb; ++k) {
-            T ra[4], cb[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) ra[u] = Lp[ri[u] + k];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) cb[v] = Lp[ci[v] + k];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc[u][v] += ra[u] * cb[v];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int r = RT + ty * 4 + u, c = CT + tx + 16 * v;
-              if (r < rend && c <= r && r - c <= b) A[(int64_t)r * Wb + (c - r + b)] -= acc[u][v];
-            }
-        }
-      }
+      if (j < jb && j <= r && r - j <= b) A[(int64_t)(J + r) * Wb + (j - r + b)] = P[r * LS + j];
     }
     __syncthreads();
   }
@@ -306,9 +306,15 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
 
 namespace {
 int g_smem_limit = 0;
+
+size_t chol_lds(int nb, int bmax) {
+  const size_t tile = (size_t)nb * tile_stride(bmax), panel = (size_t)(nb + bmax) * (nb + 1);
+  return (tile > panel ? tile : panel) * sizeof(double);
 }
+}  // namespace
 
 int band_cholesky_nb(int bmax, size_t elem) {
+  (void)elem;
   if (g_smem_limit == 0) {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
@@ -316,40 +322,39 @@ int band_cholesky_nb(int bmax, size_t elem) {
       v = 65536;
     g_smem_limit = v;
   }
-  for (int nb : {32, 16, 8})
-    if ((size_t)(nb + bmax) * (nb + 1) * elem <= (size_t)g_smem_limit) return nb;
+  for (int nb : {32, 16})
+    if (chol_lds(nb, bmax) <= (size_t)g_smem_limit) return nb;
   return 0;
 }
 
-template <typename T, int NB>
-static int launch_nb(const SubDev* subs, int64_t nsub, const int32_t* list, T* band, int32_t* fail, int bmax,
+template <int NB, int G>
+static int launch_nb(const SubDev* subs, int64_t nsub, const int32_t* list, double* band, int32_t* fail, int bmax,
                      hipStream_t st) {
-  size_t shm = (size_t)(NB + bmax) * (NB + 1) * sizeof(T);
+  const size_t shm = chol_lds(NB, bmax);
   if (shm > 65536)
-    (void)hipFuncSetAttribute((const void*)band_cholesky_kernel<T, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)band_cholesky_kernel<NB, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shm);
-  if (nsub > 0) band_cholesky_kernel<T, NB><<<dim3((unsigned)nsub), dim3(256), shm, st>>>(subs, nsub, list, band, fail);
+  if (nsub > 0)
+    band_cholesky_kernel<NB, G><<<dim3((unsigned)nsub), dim3(256), shm, st>>>(subs, nsub, list, band, fail,
+                                                                             tile_stride(bmax));
   return 0;
 }
 
 template <typename T>
 int launch_band_cholesky(const SubDev* subs, int64_t nsub, const int32_t* list, T* band, int32_t* fail, int bmax,
                          int nb, hipStream_t st) {
+  static_assert(sizeof(T) == 8, "FP64 factors");
   if (nb <= 0) nb = band_cholesky_nb(bmax, sizeof(T));
   switch (nb) {
     case 32:
-      return launch_nb<T, 32>(subs, nsub, list, band, fail, bmax, st);
+      return launch_nb<32, 5>(subs, nsub, list, band, fail, bmax, st);
     case 16:
-      return launch_nb<T, 16>(subs, nsub, list, band, fail, bmax, st);
-    case 8:
-      return launch_nb<T, 8>(subs, nsub, list, band, fail, bmax, st);
+      return launch_nb<16, 5>(subs, nsub, list, band, fail, bmax, st);
     default:
       return -1;
   }
 }
 template int launch_band_cholesky<double>(const SubDev*, int64_t, const int32_t*, double*, int32_t*, int, int,
                                           hipStream_t);
-template int launch_band_cholesky<float>(const SubDev*, int64_t, const int32_t*, float*, int32_t*, int, int,
-                                         hipStream_t);
 
 }  // namespace tfeti
