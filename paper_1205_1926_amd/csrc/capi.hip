@@ -32,6 +32,7 @@ struct tfeti_handle {
   int64_t panel_alloc = 0;      // panel storage (entries per layout) allocated
   // factor reuse: subdomains whose current factor is of the elastic tangent
   std::vector<uint8_t> fact_elastic;
+  std::vector<uint8_t> band_factored;  // d_band holds the subdomain's factor (since the last assembly)
   std::vector<int32_t> subpl, flist;
   int32_t *d_subpl = nullptr, *d_flist = nullptr, *d_rlist = nullptr;
   // band factors of the elastic stiffness of every subdomain, kept from the
@@ -70,7 +71,6 @@ struct tfeti_handle {
   double *d_QQt = nullptr, *d_dN = nullptr, *d_Ginv = nullptr, *d_Gpk = nullptr, *d_Gpart = nullptr;
   // matrices
   double* d_band = nullptr;     // K_reg (FP64 row-band)
-  void* d_work = nullptr;       // factor work (row-band, factor precision)
   void* d_F = nullptr;          // forward panels (factor precision)
   void* d_B = nullptr;          // backward panels (factor precision)
   double* d_F64 = nullptr;      // FP32 mode: FP64 panels of the same factor (outer refinement)
@@ -121,7 +121,7 @@ struct tfeti_handle {
   hipEvent_t sync_ev = nullptr;
   hipGraphExec_t gexec = nullptr;                          // `batch` whole iterations
   hipGraphExec_t gexec_a = nullptr, gexec_b = nullptr;     // split iteration (timed solves)
-  bool graph_failed = false, graph_split = false;
+  bool graph_failed = false, graph_split = false, graph_timed = false;
   int graph_batch = 0;
 };
 
@@ -326,6 +326,16 @@ bool capture_one(tfeti_handle* h, hipGraphExec_t* exec, int batch, int part) {
   if (ok) {
     const int32_t* done = &h->d_S->done;
     for (int k = 0; k < batch; ++k) {
+      if (part == 3) {
+        // whole iteration with the solve kernel bracketed by event nodes
+        // (events 2k, 2k+1; read after each replay)
+        enqueue_iteration_a(h, done);
+        ok = ok && hipEventRecordWithFlags(h->ev[2 * k], h->gs, hipEventRecordExternal) == hipSuccess;
+        ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done);
+        ok = ok && hipEventRecordWithFlags(h->ev[2 * k + 1], h->gs, hipEventRecordExternal) == hipSuccess;
+        enqueue_iteration_b(h, done);
+        continue;
+      }
       if (part == 0 || part == 1) enqueue_iteration_a(h, done);
       if (part == 0) enqueue_iteration_solve(h, done, false);
       if (part == 0 || part == 2) enqueue_iteration_b(h, done);
@@ -356,9 +366,19 @@ void drop_graphs(tfeti_handle* h) {
 bool capture_graph(tfeti_handle* h, int batch) {
   drop_graphs(h);
   bool ok;
+  h->graph_timed = false;
   if (h->timing) {
-    ok = capture_one(h, &h->gexec_a, 1, 1) && capture_one(h, &h->gexec_b, 1, 2);
-    h->graph_split = true;
+    // preferred: the whole batch with event nodes around the solve kernels;
+    // else part A and part B graphs around an eager, event-bracketed launch
+    h->graph_split = false;
+    ok = 2 * batch <= (int)h->ev.size() && capture_one(h, &h->gexec, batch, 3);
+    if (ok) {
+      h->graph_timed = true;
+    } else {
+      drop_graphs(h);
+      ok = capture_one(h, &h->gexec_a, 1, 1) && capture_one(h, &h->gexec_b, 1, 2);
+      h->graph_split = true;
+    }
   } else {
     ok = capture_one(h, &h->gexec, batch, 0);
     h->graph_split = false;
@@ -392,8 +412,9 @@ int pcg_loop(tfeti_handle* h, double eps, int maxit, PcgScalars* out) {
   const int batch = h->opt.check_every > 0 ? h->opt.check_every : 8;
   bool graph = h->opt.use_graph && !h->graph_failed;
   if (graph) {
-    const bool have = h->timing ? (h->gexec_a && h->gexec_b && h->graph_split)
-                                : (h->gexec && !h->graph_split && h->graph_batch == batch);
+    const bool have = h->timing ? ((h->gexec && h->graph_timed && h->graph_batch == batch) ||
+                                   (h->gexec_a && h->gexec_b && h->graph_split))
+                                : (h->gexec && !h->graph_split && !h->graph_timed && h->graph_batch == batch);
     if (!have) graph = capture_graph(h, batch);
   }
   if (graph) {
@@ -407,6 +428,7 @@ int pcg_loop(tfeti_handle* h, double eps, int maxit, PcgScalars* out) {
   for (;;) {
     if (graph && !h->graph_split) {
       HIPCHK(hipGraphLaunch(h->gexec, h->gs));
+      if (h->graph_timed) h->ev_used = batch;
     } else if (graph) {
       hipStream_t saved = h->st;
       h->st = h->gs;
@@ -612,6 +634,7 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
 int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   const HostModel& M = h->M;
   HIPCHK(hipMemsetAsync(h->d_band, 0, M.band_entries * sizeof(double), h->st));
+  std::fill(h->band_factored.begin(), h->band_factored.end(), 0);
   HIPCHK(hipMemsetAsync(fint, 0, M.n_torn * sizeof(double), h->st));
   HIPCHK(hipMemsetAsync(h->d_plcount, 0, sizeof(unsigned long long), h->st));
   AssembleArgs a{};
@@ -653,14 +676,14 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
 
 // Pack the FP64 band factors of the listed subdomains (all if list is
 // NULL) into the solve panels of the current tile.
-void pack(tfeti_handle* h, int64_t count, const int32_t* list) {
+void pack(tfeti_handle* h, int64_t count, const int32_t* list, const double* band = nullptr) {
+  if (!band) band = h->d_band;
   if (h->prec == TFETI_PREC_FP64) {
-    launch_pack_panels<double, double>(h->d_subs, count, list, (const double*)h->d_work, (double*)h->d_F,
-                                       (double*)h->d_B, h->TS, h->st);
+    launch_pack_panels<double, double>(h->d_subs, count, list, band, (double*)h->d_F, (double*)h->d_B, h->TS, h->st);
   } else {
     // FP64 panels (outer refinement) and FP32 panels (inner iterations) in one pass
-    launch_pack_panels<double, double>(h->d_subs, count, list, (const double*)h->d_work, h->d_F64, h->d_B64, h->TS,
-                                       h->st, (float*)h->d_F, (float*)h->d_B);
+    launch_pack_panels<double, double>(h->d_subs, count, list, band, h->d_F64, h->d_B64, h->TS, h->st,
+                                       (float*)h->d_F, (float*)h->d_B);
   }
 }
 
@@ -679,6 +702,8 @@ int retile(tfeti_handle* h, int TS, int natural, int threads) {
   HostModel& M = h->M;
   const int64_t pe = assign_panels(M, TS);
   if (pe > h->panel_alloc) return fail(h, TFETI_E_INVALID, "internal: panel storage too small for the tile");
+  if (!std::all_of(h->band_factored.begin(), h->band_factored.end(), [](uint8_t x) { return x != 0; }))
+    return fail(h, TFETI_E_INVALID, "internal: retiling needs every subdomain's factor in the band");
   drop_graphs(h);
   h->panel_entries = pe;
   h->TS = TS;
@@ -808,25 +833,33 @@ int factorize(tfeti_handle* h) {
         (h->e_valid ? restore : list).push_back((int32_t)p);
     }
   }
-  // elastic again: the kept elastic factor is copied back and packed
+  // elastic again: the kept elastic factor is packed again
   h->last_restored = (int64_t)restore.size();
   if (!restore.empty()) {
     HIPCHK(hipMemcpyAsync(h->d_rlist, restore.data(), restore.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           h->st));
-    const int64_t cnt = (int64_t)restore.size();
-    launch_copy_band(h->d_subs, cnt, h->d_rlist, h->d_eband, (double*)h->d_work, h->st);
-    pack(h, cnt, h->d_rlist);
+    pack(h, (int64_t)restore.size(), h->d_rlist, h->d_eband);
     for (int32_t p : restore) h->fact_elastic[p] = 1;
   }
   h->last_refactored = (int64_t)list.size();
   if (!list.empty()) {
+    // the band is factorized in place; a subdomain whose band already holds
+    // its factor (factorized again without an assembly in between) is only
+    // packed again
+    std::vector<int32_t> fresh;
+    for (int32_t p : list)
+      if (!h->band_factored[p]) fresh.push_back(p);
+    HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
+    if (!fresh.empty()) {
+      HIPCHK(hipMemcpyAsync(h->d_flist, fresh.data(), fresh.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                            h->st));
+      const int64_t nf = (int64_t)fresh.size();
+      launch_regularize(h->d_subs, nf, h->d_flist, h->d_QQt, h->d_band, h->st);
+      launch_band_cholesky<double>(h->d_subs, nf, h->d_flist, h->d_band, h->d_fail, h->bmax, h->chol_nb, h->st);
+      for (int32_t p : fresh) h->band_factored[p] = 1;
+    }
     HIPCHK(hipMemcpyAsync(h->d_flist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
     const int64_t cnt = (int64_t)list.size();
-    launch_regularize(h->d_subs, cnt, h->d_flist, h->d_QQt, h->d_band, h->st);
-    HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
-    launch_copy_band(h->d_subs, cnt, h->d_flist, h->d_band, (double*)h->d_work, h->st);
-    launch_band_cholesky<double>(h->d_subs, cnt, h->d_flist, (double*)h->d_work, h->d_fail, h->bmax, h->chol_nb,
-                                 h->st);
     pack(h, cnt, h->d_flist);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
@@ -844,10 +877,12 @@ int factorize(tfeti_handle* h) {
     h->tune_pending = false;
     RC(autotune(h));
   }
-  // keep the elastic factors once every subdomain holds one
-  if (!h->opt.refactor_all && !h->e_valid && h->d_eband &&
-      std::all_of(h->fact_elastic.begin(), h->fact_elastic.end(), [](uint8_t v) { return v != 0; })) {
-    HIPCHK(hipMemcpyAsync(h->d_eband, h->d_work, (size_t)M.band_entries * sizeof(double), hipMemcpyDeviceToDevice,
+  // keep the elastic factors once the band holds every subdomain's one
+  auto all_set = [](const std::vector<uint8_t>& v) {
+    return std::all_of(v.begin(), v.end(), [](uint8_t x) { return x != 0; });
+  };
+  if (!h->opt.refactor_all && !h->e_valid && h->d_eband && all_set(h->fact_elastic) && all_set(h->band_factored)) {
+    HIPCHK(hipMemcpyAsync(h->d_eband, h->d_band, (size_t)M.band_entries * sizeof(double), hipMemcpyDeviceToDevice,
                           h->st));
     h->e_valid = true;
   }
@@ -979,9 +1014,6 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   }
   {
     void* q = nullptr;
-    if (hipMalloc(&q, (size_t)M.band_entries * sizeof(double)) != hipSuccess) return fail(h, TFETI_E_OOM, "factor work");
-    h->allocs.push_back(q);
-    h->d_work = q;
     if (!h->opt.refactor_all) {
       if (hipMalloc(&q, (size_t)M.band_entries * sizeof(double)) != hipSuccess)
         return fail(h, TFETI_E_OOM, "elastic factors");
@@ -1036,6 +1068,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_flist, M.n_sub));
   RC(dalloc(h, &h->d_rlist, M.n_sub));
   h->fact_elastic.assign(M.n_sub, 0);
+  h->band_factored.assign(M.n_sub, 0);
   h->subpl.assign(M.n_sub, 0);
   h->flist.reserve(M.n_sub);
   RC(dalloc(h, &h->d_Ginv, (int64_t)M.lc * M.lc));
