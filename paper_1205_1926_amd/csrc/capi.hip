@@ -88,6 +88,7 @@ struct tfeti_handle {
   double* d_iface = nullptr;
   double *d_c = nullptr, *d_a = nullptr;
   double* d_partials = nullptr;
+  double* d_iface2 = nullptr;   // second right-hand side of a two-vector subdomain solve
   double* d_scal = nullptr;
   PcgScalars* d_S = nullptr;
   int32_t* d_fail = nullptr;
@@ -177,7 +178,8 @@ double read_scalar(tfeti_handle* h, const double* d) {
 
 // ------------------------------------------------------------------ operators
 void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double lam_sign, double* out_iface,
-            double* out_full, const double* alpha, const int32_t* done, bool use64 = false) {
+            double* out_full, const double* alpha, const int32_t* done, bool use64 = false,
+            const double* lam2 = nullptr, double* out_iface2 = nullptr) {
   if (h->prec == TFETI_PREC_FP64 || use64) {
     KsolveArgs<double> a{};
     a.subs = h->d_subs;
@@ -198,6 +200,8 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.if_row = h->d_if_row;
     a.if_coef = h->d_if_coef;
     a.done = done;
+    a.lam2 = lam2;
+    a.out_iface2 = out_iface2;
     launch_ksolve<double>(a, h->TS, h->nt, h->npad_max, h->st);
   } else {
     KsolveArgs<float> a{};
@@ -219,6 +223,8 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.if_row = h->d_if_row;
     a.if_coef = h->d_if_coef;
     a.done = done;
+    a.lam2 = lam2;
+    a.out_iface2 = out_iface2;
     launch_ksolve<float>(a, h->TS, h->nt, h->npad_max, h->st);
   }
 }
@@ -484,10 +490,41 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
   launch_rt_apply(h->dm, f, h->d_c, h->st);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, nullptr, h->st);
   launch_gt_apply(h->dm, nullptr, h->d_a, -1.0, h->d_lam_im, nullptr, nullptr, h->st);
+  // the first warm-start candidate, if finite, is projected now: its
+  // residual d~ - F P g = B K^+ (f - B^T (lambda_Im + P g)) comes from the
+  // same pass over the factors as d~
+  bool rejected = false;
+  const double* cands[2] = {guess, guess2};
+  bool merged = false;
+  auto finite = [&](const double* g) -> int {
+    int zero = 0;
+    if (hipMemcpyAsync(&h->d_S->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice, h->st) != hipSuccess) return -1;
+    launch_check_finite(m, g, h->d_S, h->st);
+    PcgScalars Sc;
+    if (hipMemcpyAsync(&Sc, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st) != hipSuccess ||
+        hipStreamSynchronize(h->st) != hipSuccess)
+      return -1;
+    return Sc.nonfinite ? 0 : 1;
+  };
+  if (cands[0]) {
+    const int fin = finite(cands[0]);
+    if (fin < 0) return fail(h, TFETI_E_HIP, "HIP error in the warm-start check");
+    if (fin == 0) {
+      rejected = true;
+      cands[0] = nullptr;
+    } else {
+      project(h, cands[0], h->d_cl[0], nullptr, nullptr);
+      launch_copy(m, h->d_lam_im, h->d_lam, h->st);
+      launch_axpby(m, 1.0, h->d_cl[0], 1.0, h->d_lam, h->st);
+      merged = true;
+    }
+  }
   // d~ = d - F lambda_Im = B K^+ (f - B^T lambda_Im) in one pass over the
   // factors (FP64 operator)
-  ksolve(h, f, h->d_lam_im, -1.0, h->d_iface, nullptr, nullptr, nullptr, true);
+  ksolve(h, f, h->d_lam_im, -1.0, h->d_iface, nullptr, nullptr, nullptr, true, merged ? h->d_lam : nullptr,
+         merged ? h->d_iface2 : nullptr);
   launch_gather(h->dm, h->d_iface, h->d_dt, nullptr, nullptr, nullptr, h->st);
+  if (merged) launch_gather(h->dm, h->d_iface2, h->d_cr[0], nullptr, nullptr, nullptr, h->st);
   int fapplies = 1, fapplies64 = 1;
   // r_ref = ||P d~||
   {
@@ -498,29 +535,23 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
   const double r_ref = read_rref(h);
   // warm start (safeguarded): each finite candidate g gives lambda_Ker = P g
   // and r = d~ - F lambda_Ker; the candidate with the smaller ||P r|| wins
-  bool rejected = false;
-  const double* cands[2] = {guess, guess2};
   double best = -1.0;
   int choice = 0;
   double* lam_acc = mixed ? h->d_lam_acc : h->d_lam_ker;
   for (int c = 0; c < 2; ++c) {
     if (!cands[c]) continue;
-    {
-      int zero = 0;
-      HIPCHK(hipMemcpyAsync(&h->d_S->nonfinite, &zero, sizeof(int), hipMemcpyHostToDevice, h->st));
+    if (!(c == 0 && merged)) {
+      const int fin = finite(cands[c]);
+      if (fin < 0) return fail(h, TFETI_E_HIP, "HIP error in the warm-start check");
+      if (fin == 0) {
+        rejected = true;
+        continue;
+      }
+      project(h, cands[c], h->d_cl[c], nullptr, nullptr);
+      fapply(h, h->d_cl[c], h->d_q, nullptr, nullptr, nullptr, false, true);
+      launch_copy(m, h->d_dt, h->d_cr[c], h->st);
+      launch_axpby(m, -1.0, h->d_q, 1.0, h->d_cr[c], h->st);
     }
-    launch_check_finite(m, cands[c], h->d_S, h->st);
-    PcgScalars Sc;
-    HIPCHK(hipMemcpyAsync(&Sc, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    if (Sc.nonfinite) {
-      rejected = true;
-      continue;
-    }
-    project(h, cands[c], h->d_cl[c], nullptr, nullptr);
-    fapply(h, h->d_cl[c], h->d_q, nullptr, nullptr, nullptr, false, true);
-    launch_copy(m, h->d_dt, h->d_cr[c], h->st);
-    launch_axpby(m, -1.0, h->d_q, 1.0, h->d_cr[c], h->st);
     fapplies++;
     fapplies64++;
     set_rref(h, h->d_cr[c], h->d_w);
@@ -1057,6 +1088,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   h->wm.erp = h->d_wn_erp;
   h->wm.elems = h->d_wn_elems;
   RC(dalloc(h, &h->d_iface, M.n_iface));
+  RC(dalloc(h, &h->d_iface2, M.n_iface));
   RC(dalloc(h, &h->d_c, M.lc_pad));
   RC(dalloc(h, &h->d_a, M.lc_pad));
   RC(dalloc(h, &h->d_partials, 4096));

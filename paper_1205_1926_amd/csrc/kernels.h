@@ -80,7 +80,9 @@ struct KsolveArgs {
   const int32_t* if_row;
   const double* if_coef;
   const int32_t* done;        // skip when *done != 0 (nullptr: never)
-  int32_t part_off;           // LDS offset (entries of T) of the partial sums; set by the launcher
+  const double* lam2;         // a second right-hand side in_full + lam_sign B^T lam2, or nullptr
+  double* out_iface2;         // its z at the touched DOFs (with lam2)
+  int32_t vec_stride;         // LDS entries per right-hand side; set by the launcher
 };
 template <typename T>
 void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st);

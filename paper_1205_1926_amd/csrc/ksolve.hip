@@ -63,15 +63,18 @@ __device__ __forceinline__ auto vdot(const VT& a, const VT& b) -> decltype(a[0] 
 
 }  // namespace
 
-template <typename T, int TS, int NT>
+template <typename T, int TS, int NT, int NR>
 __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   using VT = typename Vec<T>::type;
   constexpr int V = Vec<T>::V;
   constexpr int RPT = NT / TS;           // threads per tile row
   constexpr int UNR = 4;                 // panel chunks loaded back to back per lane
   extern __shared__ __align__(16) unsigned char smem[];
-  T* xs = reinterpret_cast<T*>(smem);
-  T* part = xs + A.part_off;             // after the largest subdomain vector
+  // NR right-hand sides, each a vector of vec_stride entries in LDS, then
+  // one partial sum per thread and right-hand side
+  T* xs0 = reinterpret_cast<T*>(smem);
+  T* part0 = xs0 + NR * A.vec_stride;
+  const int VS = A.vec_stride;
 
   if (A.done && *A.done) return;
   const int tid = threadIdx.x;
@@ -84,20 +87,31 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   const int N0 = pa == 0 ? s.N[0] : (pa == 1 ? s.N[1] : s.N[2]);
   const int N1 = pb == 0 ? s.N[0] : (pb == 1 ? s.N[1] : s.N[2]);
 
-  // ---- input: x = in_full (factor order) + lam_sign B^T lam ----
-  for (int i = tid; i < n; i += NT) xs[i] = T(0);
+  // ---- input: x_k = in_full (factor order) + lam_sign B^T lam_k ----
+  for (int i = tid; i < n; i += NT)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) xs0[k * VS + i] = T(0);
   __syncthreads();
   if (A.in_full) {
-    for (int ld = tid; ld < s.ndof; ld += NT) xs[factor_index(s, ld)] = (T)A.in_full[s.dof_off + ld];
+    for (int ld = tid; ld < s.ndof; ld += NT) {
+      const T f = (T)A.in_full[s.dof_off + ld];
+      const int fi = factor_index(s, ld);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) xs0[k * VS + fi] = f;
+    }
     __syncthreads();
   }
   if (A.lam) {
     for (int t = tid; t < s.n_iface; t += NT) {
       const int64_t it = s.iface_off + t;
       double v = A.in_full ? A.in_full[s.dof_off + A.if_ldof[it]] : 0.0;
-      double bt = 0.0;
-      for (int e = A.if_rp[it]; e < A.if_rp[it + 1]; ++e) bt += A.if_coef[e] * A.lam[A.if_row[e]];
-      xs[A.if_fidx[it]] = (T)(v + A.lam_sign * bt);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const double* lam = k == 0 ? A.lam : A.lam2;
+        double bt = 0.0;
+        for (int e = A.if_rp[it]; e < A.if_rp[it + 1]; ++e) bt += A.if_coef[e] * lam[A.if_row[e]];
+        xs0[k * VS + A.if_fidx[it]] = (T)(v + A.lam_sign * bt);
+      }
     }
   }
   __syncthreads();
@@ -111,7 +125,9 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
       const int w = I * TS < s.bo ? I * TS : s.bo;
       const int nco = w / V;
       const int c0 = I * TS - w;
-      T acc = T(0);
+      T acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = T(0);
       // first envelope column of the row (padding rows: the diagonal), and
       // the first chunk holding a column at or after it
       int fc = I * TS + r;
@@ -128,24 +144,35 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) L[u] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(P + off + ((int64_t)(cc + u * RPT) * TS + r) * V));
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) acc += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs + c0 + (cc + u * RPT) * V));
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + (cc + u * RPT) * V));
       }
       for (; cc < nco; cc += RPT) {
         VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)cc * TS + r) * V);
-        VT y = *reinterpret_cast<const VT*>(xs + c0 + cc * V);
-        acc += vdot<VT, V>(L, y);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          VT y = *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + cc * V);
+          acc[k] += vdot<VT, V>(L, y);
+        }
       }
-      part[tid] = acc;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) part0[k * NT + tid] = acc[k];
       __syncthreads();
       if (tid < 64) {
-        T a = T(0);
-        if (tid < TS) {
-          T sum = T(0);
+        T a[NR], y[NR];
 #pragma unroll
-          for (int k = 0; k < RPT; ++k) sum += part[k * TS + tid];
-          a = xs[I * TS + tid] - sum;
+        for (int k = 0; k < NR; ++k) {
+          a[k] = T(0);
+          y[k] = T(0);
+          if (tid < TS) {
+            T sum = T(0);
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) sum += part0[k * NT + j * TS + tid];
+            a[k] = xs0[k * VS + I * TS + tid] - sum;
+          }
         }
-        T y = T(0);
 #pragma unroll
         for (int cc = 0; cc < TS / V; ++cc) {
           VT L;
@@ -154,9 +181,13 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           else
             L = VT(T(0));
 #pragma unroll
-          for (int v = 0; v < V; ++v) y += L[v] * bcast<T>(a, cc * V + v);
+          for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) y[k] += L[v] * bcast<T>(a[k], cc * V + v);
         }
-        if (tid < TS) xs[I * TS + tid] = y;
+        if (tid < TS)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) xs0[k * VS + I * TS + tid] = y[k];
       }
       __syncthreads();
       off += (int64_t)TS * (w + TS);
@@ -174,7 +205,9 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
       off -= (int64_t)TS * (TS + w);
       const int nco = w / V;
       const int rbase = (I + 1) * TS;
-      T acc = T(0);
+      T acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = T(0);
       // rows below the block that can reach column I TS + c: no row of node
       // q starts before node q - 1 - N0 - N0 N1, so rows past the last DOF of
       // node col/3 + 1 + N0 + N0 N1 are zero in this column, and so are the
@@ -197,24 +230,34 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
               reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr + u * RPT) * TS + c) * V));
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-          acc += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs + rbase + (rr + u * RPT) * V));
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + (rr + u * RPT) * V));
       }
       for (; rr < rend; rr += RPT) {
         VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr) * TS + c) * V);
-        VT z = *reinterpret_cast<const VT*>(xs + rbase + rr * V);
-        acc += vdot<VT, V>(L, z);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          VT z = *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + rr * V);
+          acc[k] += vdot<VT, V>(L, z);
+        }
       }
-      part[tid] = acc;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) part0[k * NT + tid] = acc[k];
       __syncthreads();
       if (tid < 64) {
-        T a = T(0);
-        if (tid < TS) {
-          T sum = T(0);
+        T a[NR], z[NR];
 #pragma unroll
-          for (int k = 0; k < RPT; ++k) sum += part[k * TS + tid];
-          a = xs[I * TS + tid] - sum;
+        for (int k = 0; k < NR; ++k) {
+          a[k] = T(0);
+          z[k] = T(0);
+          if (tid < TS) {
+            T sum = T(0);
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) sum += part0[k * NT + j * TS + tid];
+            a[k] = xs0[k * VS + I * TS + tid] - sum;
+          }
         }
-        T z = T(0);
 #pragma unroll
         for (int rc = 0; rc < TS / V; ++rc) {
           VT L;
@@ -223,9 +266,13 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           else
             L = VT(T(0));
 #pragma unroll
-          for (int v = 0; v < V; ++v) z += L[v] * bcast<T>(a, rc * V + v);
+          for (int k = 0; k < NR; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) z[k] += L[v] * bcast<T>(a[k], rc * V + v);
         }
-        if (tid < TS) xs[I * TS + tid] = z;
+        if (tid < TS)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) xs0[k * VS + I * TS + tid] = z[k];
       }
       __syncthreads();
     }
@@ -235,12 +282,13 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   if (A.out_iface) {
     for (int t = tid; t < s.n_iface; t += NT) {
       const int64_t it = s.iface_off + t;
-      A.out_iface[it] = (double)xs[A.if_fidx[it]];
+      A.out_iface[it] = (double)xs0[A.if_fidx[it]];
+      if (NR > 1) A.out_iface2[it] = (double)xs0[VS + A.if_fidx[it]];
     }
   }
   if (A.out_full) {
     for (int ld = tid; ld < s.ndof; ld += NT) {
-      double v = (double)xs[factor_index(s, ld)];
+      double v = (double)xs0[factor_index(s, ld)];
       if (A.alpha) {
         const double* R = A.R_full + 6 * (s.dof_off + ld);
         const double* al = A.alpha + 6 * (int64_t)p;
@@ -251,34 +299,53 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int NR>
 static void launch_ts(const KsolveArgs<T>& b, int TS, size_t shm, hipStream_t st) {
   dim3 grid((unsigned)b.nsub), block(NT);
-  if (TS == 16)
-    ksolve_kernel<T, 16, NT><<<grid, block, shm, st>>>(b);
-  else if (TS == 32)
-    ksolve_kernel<T, 32, NT><<<grid, block, shm, st>>>(b);
-  else if constexpr (NT <= 512)
-    ksolve_kernel<T, 64, NT><<<grid, block, shm, st>>>(b);
+  if (TS == 16) {
+    if (shm > 65536)
+      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 16, NT, NR>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    ksolve_kernel<T, 16, NT, NR><<<grid, block, shm, st>>>(b);
+  } else if (TS == 32) {
+    if (shm > 65536)
+      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 32, NT, NR>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    ksolve_kernel<T, 32, NT, NR><<<grid, block, shm, st>>>(b);
+  } else if constexpr (NT <= 512) {
+    if (shm > 65536)
+      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 64, NT, NR>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    ksolve_kernel<T, 64, NT, NR><<<grid, block, shm, st>>>(b);
+  }
 }
 
 template <typename T>
 void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st) {
-  // shared memory: the vector (npad_max entries, rounded to 16 bytes) + one
-  // partial sum per thread
+  // shared memory: NR vectors (npad_max entries each, rounded to 16 bytes)
+  // + NR partial sums per thread; a second right-hand side when lam2 is set
   // 1024 threads only with tiles of 16 or 32 rows (the 64-row kernel needs
   // more registers than 16 waves per compute unit leave)
   const int NT = (threads == 1024 && TS <= 32) ? 1024 : (threads == 512 ? 512 : 256);
-  size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
-  size_t shm = vec + (size_t)NT * sizeof(T);
+  const int NR = a.lam2 ? 2 : 1;
+  const size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
+  const size_t shm = NR * (vec + (size_t)NT * sizeof(T));
   KsolveArgs<T> b = a;
-  b.part_off = (int32_t)(vec / sizeof(T));
-  if (NT == 1024)
-    launch_ts<T, 1024>(b, TS, shm, st);
-  else if (NT == 512)
-    launch_ts<T, 512>(b, TS, shm, st);
-  else
-    launch_ts<T, 256>(b, TS, shm, st);
+  b.vec_stride = (int32_t)(vec / sizeof(T));
+  if (NR == 2) {
+    if (NT == 1024)
+      launch_ts<T, 1024, 2>(b, TS, shm, st);
+    else if (NT == 512)
+      launch_ts<T, 512, 2>(b, TS, shm, st);
+    else
+      launch_ts<T, 256, 2>(b, TS, shm, st);
+  } else if (NT == 1024) {
+    launch_ts<T, 1024, 1>(b, TS, shm, st);
+  } else if (NT == 512) {
+    launch_ts<T, 512, 1>(b, TS, shm, st);
+  } else {
+    launch_ts<T, 256, 1>(b, TS, shm, st);
+  }
 }
 template void launch_ksolve<double>(const KsolveArgs<double>&, int, int, int, hipStream_t);
 template void launch_ksolve<float>(const KsolveArgs<float>&, int, int, int, hipStream_t);
