@@ -110,9 +110,13 @@ __constant__ int8_t c_axis[3][3] = {{0, 1, 2}, {1, 0, 2}, {2, 1, 0}};
 __constant__ int8_t c_noff[8][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 1, 0},
                                     {0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}};
 
+// MODE 1: return map, state increments and internal force of every
+// element; MODE 2: the tangent of the elements of the subdomains flagged in
+// A.need (the return map is evaluated again for its D).
+template <int MODE>
 __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs A) {
   __shared__ double s_dN[8][8][3];                       // [gp][node][axis]
-  __shared__ double s_D[kElemPerBlock][8][36];
+  __shared__ double s_D[MODE == 2 ? kElemPerBlock : 1][8][36];
   __shared__ double s_ds[kElemPerBlock][8][6];           // w * dsigma
   __shared__ double s_du[kElemPerBlock][24];
   __shared__ int32_t s_dof[kElemPerBlock][24];           // torn DOF
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs A) {
   if (tid < kElemPerBlock * 8) {
     int el = tid / 8, a = tid % 8;
     int64_t ci = first + el;
-    if (ci < A.n_colour) {
+    if (ci < A.n_colour && (MODE != 2 || A.need[A.elem_sub[A.elems[ci]]])) {
       int32_t e = A.elems[ci];
       const SubDev& s = A.subs[A.elem_sub[e]];
       int32_t le = (int32_t)(e - s.elem_off);
@@ -152,11 +156,16 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs A) {
     }
   }
   __syncthreads();
+  // an element of this block takes part (MODE 2: its subdomain is flagged)
+  auto active = [&](int el) {
+    const int64_t ci = first + el;
+    return ci < A.n_colour && (MODE != 2 || A.need[A.elem_sub[A.elems[ci]]]);
+  };
   // return map: one thread per (element, Gauss point)
   if (tid < kElemPerBlock * 8) {
     int el = tid / 8, g = tid % 8;
     int64_t ci = first + el;
-    if (ci < A.n_colour) {
+    if (active(el)) {
       int32_t e = A.elems[ci];
       int64_t gp = 8 * (int64_t)e + g;
       double de[6] = {0, 0, 0, 0, 0, 0};
@@ -168,20 +177,24 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs A) {
       double sg[6], ds[6], dk;
       for (int i = 0; i < 6; ++i) sg[i] = A.sigma[6 * gp + i];
       bool plastic;
-      return_map_point(A.M, sg, A.kappa[gp], de, ds, &dk, &s_D[el][g][0], &plastic);
-      for (int i = 0; i < 6; ++i) {
-        A.dsigma[6 * gp + i] = ds[i];
-        s_ds[el][g][i] = A.w * ds[i];
+      return_map_point(A.M, sg, A.kappa[gp], de, ds, &dk, MODE == 2 ? &s_D[el][g][0] : nullptr, &plastic);
+      if (MODE == 1) {
+        for (int i = 0; i < 6; ++i) {
+          A.dsigma[6 * gp + i] = ds[i];
+          s_ds[el][g][i] = A.w * ds[i];
+        }
+        A.dkappa[gp] = dk;
+        A.plastic[gp] = plastic ? 1 : 0;
+        if (plastic) atomicAdd(&s_cnt, 1);
       }
-      A.dkappa[gp] = dk;
-      A.plastic[gp] = plastic ? 1 : 0;
-      if (plastic) atomicAdd(&s_cnt, 1);
     }
   }
   __syncthreads();
-  if (tid == 0 && s_cnt) atomicAdd(A.plastic_count, (unsigned long long)s_cnt);
+  if (MODE == 1) {
+    if (tid == 0 && s_cnt) atomicAdd(A.plastic_count, (unsigned long long)s_cnt);
+  }
   // internal force: one thread per (element, element DOF)
-  for (int q = tid; q < kElemPerBlock * 24; q += blockDim.x) {
+  for (int q = tid; q < (MODE == 1 ? kElemPerBlock * 24 : 0); q += blockDim.x) {
     int el = q / 24, al = q % 24;
     if (first + el >= A.n_colour) continue;
     int a = al / 3, c = al % 3;
@@ -191,9 +204,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs A) {
     A.fint[s_dof[el][al]] += f;
   }
   // tangent: the 300 lower entries of each element matrix
-  for (int q = tid; q < kElemPerBlock * 300; q += blockDim.x) {
+  for (int q = tid; q < (MODE == 2 ? kElemPerBlock * 300 : 0); q += blockDim.x) {
     int el = q / 300, r = q % 300;
-    if (first + el >= A.n_colour) continue;
+    if (!active(el)) continue;
     // r -> (al, be) with al >= be, row-major lower triangle
     int al = (int)((sqrt(8.0 * r + 1.0) - 1.0) * 0.5);
     while ((al + 1) * (al + 2) / 2 <= r) ++al;
@@ -202,7 +215,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs A) {
     int a = al / 3, c = al % 3, bn = be / 3, d = be % 3;
     double kv = 0.0;
     for (int g = 0; g < 8; ++g) {
-      const double* D = &s_D[el][g][0];
+      const double* D = &s_D[MODE == 2 ? el : 0][g][0];
       for (int u = 0; u < 3; ++u) {
         double lu = s_dN[g][a][c_axis[c][u]];
         int ru = c_rows[c][u];
@@ -219,23 +232,28 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs A) {
   }
 }
 
-void launch_assemble(const AssembleArgs& args, hipStream_t st) {
+void launch_assemble(const AssembleArgs& args, int mode, hipStream_t st) {
   if (args.n_colour <= 0) return;
   int64_t blocks = (args.n_colour + kElemPerBlock - 1) / kElemPerBlock;
-  assemble_kernel<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(args);
+  if (mode == 1)
+    assemble_kernel<1><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(args);
+  else
+    assemble_kernel<2><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(args);
 }
 
-// identity rows for the padding of every subdomain factor
-__global__ void pad_identity_kernel(const SubDev* __restrict__ subs, int64_t nsub, double* __restrict__ band) {
-  int64_t p = blockIdx.x;
-  if (p >= nsub) return;
+// identity rows for the padding of the listed subdomain factors (all if
+// list is NULL)
+__global__ void pad_identity_kernel(const SubDev* __restrict__ subs, int64_t nsub, const int32_t* __restrict__ list,
+                                    double* __restrict__ band) {
+  if ((int64_t)blockIdx.x >= nsub) return;
+  const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
   const SubDev s = subs[p];
   for (int32_t r = s.ndof + threadIdx.x; r < s.npad; r += blockDim.x)
     band[s.band_off + (int64_t)r * s.Wb + s.b] = 1.0;
 }
 
-void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStream_t st) {
-  pad_identity_kernel<<<dim3((unsigned)nsub), dim3(64), 0, st>>>(subs, nsub, band);
+void launch_pad_identity(const SubDev* subs, int64_t nsub, const int32_t* list, double* band, hipStream_t st) {
+  if (nsub > 0) pad_identity_kernel<<<dim3((unsigned)nsub), dim3(64), 0, st>>>(subs, nsub, list, band);
 }
 
 // K_bb values for the lumped preconditioner (before regularization)
@@ -246,10 +264,11 @@ void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStre
 // entry (f, f2) is row max(f, f2), column min(f, f2).
 template <typename T>
 __global__ __launch_bounds__(256) void gather_kbb_kernel(DualMaps M, const double* __restrict__ band,
-                                                         T* __restrict__ out) {
+                                                         const uint8_t* __restrict__ need, T* __restrict__ out) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t g = slot / 64;
   if (g >= M.kbb_groups) return;
+  if (need && !need[M.kbb_gsub[g]]) return;
   const int lane = (int)(slot % 64);
   const int nb = M.kbb_gnb[g];
   T* o = out + M.kbb_goff[g] + lane;
@@ -279,13 +298,31 @@ __global__ __launch_bounds__(256) void gather_kbb_kernel(DualMaps M, const doubl
 }
 
 template <typename T>
-void launch_gather_kbb(const DualMaps& M, const double* band, T* out, hipStream_t st) {
+void launch_gather_kbb(const DualMaps& M, const double* band, const uint8_t* need, T* out, hipStream_t st) {
   const int64_t slots = 64 * M.kbb_groups;
   if (slots > 0)
-    gather_kbb_kernel<T><<<dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st>>>(M, band, out);
+    gather_kbb_kernel<T><<<dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st>>>(M, band, need, out);
 }
-template void launch_gather_kbb<double>(const DualMaps&, const double*, double*, hipStream_t);
-template void launch_gather_kbb<float>(const DualMaps&, const double*, float*, hipStream_t);
+template void launch_gather_kbb<double>(const DualMaps&, const double*, const uint8_t*, double*, hipStream_t);
+template void launch_gather_kbb<float>(const DualMaps&, const double*, const uint8_t*, float*, hipStream_t);
+
+// K_bb values of the listed subdomains copied from src (whole groups)
+template <typename T>
+__global__ __launch_bounds__(256) void copy_kbb_kernel(DualMaps M, int64_t count, const int32_t* __restrict__ list,
+                                                       const T* __restrict__ src, T* __restrict__ dst) {
+  if ((int64_t)blockIdx.y >= count) return;
+  const int32_t p = list[blockIdx.y];
+  const int64_t v0 = M.kbb_goff[M.kbb_g0[p]], v1 = M.kbb_goff[M.kbb_g0[p + 1]];
+  for (int64_t i = v0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < v1; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+template <typename T>
+void launch_copy_kbb(const DualMaps& M, int64_t count, const int32_t* list, const T* src, T* dst, hipStream_t st) {
+  if (count > 0) copy_kbb_kernel<T><<<dim3(16, (unsigned)count), dim3(256), 0, st>>>(M, count, list, src, dst);
+}
+template void launch_copy_kbb<double>(const DualMaps&, int64_t, const int32_t*, const double*, double*, hipStream_t);
+template void launch_copy_kbb<float>(const DualMaps&, int64_t, const int32_t*, const float*, float*, hipStream_t);
 
 // K_reg = K + rho Q Q^T at the fixing DOFs, rho = max_j K[j, j] (Remark 1)
 __global__ __launch_bounds__(256) void regularize_kernel(const SubDev* __restrict__ subs, int64_t count,

@@ -38,6 +38,11 @@ struct tfeti_handle {
   // band factors of the elastic stiffness of every subdomain, kept from the
   // first factorization in which every subdomain was elastic
   double* d_eband = nullptr;
+  double* d_ekbb = nullptr;     // kept elastic K_bb values (FP64 mode)
+  float* d_ekbb32 = nullptr;    // (FP32 mode)
+  uint8_t* d_need = nullptr;    // subdomains whose tangent the last assembly formed
+  int32_t* d_alist = nullptr;
+  int64_t last_assembled = 0;
   bool e_valid = false;
   int64_t last_restored = 0;
   int64_t last_refactored = 0;
@@ -664,8 +669,6 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
 // ------------------------------------------------------------------ assembly / factorization
 int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   const HostModel& M = h->M;
-  HIPCHK(hipMemsetAsync(h->d_band, 0, M.band_entries * sizeof(double), h->st));
-  std::fill(h->band_factored.begin(), h->band_factored.end(), 0);
   HIPCHK(hipMemsetAsync(fint, 0, M.n_torn * sizeof(double), h->st));
   HIPCHK(hipMemsetAsync(h->d_plcount, 0, sizeof(unsigned long long), h->st));
   AssembleArgs a{};
@@ -686,17 +689,56 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   a.plastic_count = h->d_plcount;
   a.fint = fint;
   a.band = h->d_band;
+  a.need = h->d_need;
+  // return map, increments and internal force of every element
   for (int c = 0; c < 8; ++c) {
     a.elems = h->d_colour[c];
     a.n_colour = h->n_colour[c];
-    launch_assemble(a, h->st);
+    launch_assemble(a, 1, h->st);
   }
-  launch_pad_identity(h->d_subs, M.n_sub, h->d_band, h->st);
-  // the lumped preconditioner uses the unregularized tangent
-  if (h->prec == TFETI_PREC_FP64)
-    launch_gather_kbb<double>(h->dm, h->d_band, h->d_kbb_val, h->st);
-  else
-    launch_gather_kbb<float>(h->dm, h->d_band, h->d_kbb_val32, h->st);
+  // the tangent only where factorize will need it (the same rule): plastic
+  // subdomains, and elastic ones that hold no elastic factor when none is
+  // kept; subdomains elastic again with a kept factor get the kept K_bb
+  launch_sub_plastic(h->d_subs, M.n_sub, h->d_plastic, h->d_subpl, h->st);
+  HIPCHK(hipMemcpyAsync(h->subpl.data(), h->d_subpl, M.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  std::vector<uint8_t> need(M.n_sub, 0);
+  std::vector<int32_t> alist, rlist;
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    if (h->opt.refactor_all || h->subpl[p] || (!h->fact_elastic[p] && !h->e_valid)) {
+      need[p] = 1;
+      alist.push_back((int32_t)p);
+    } else if (!h->fact_elastic[p]) {
+      rlist.push_back((int32_t)p);
+    }
+  }
+  h->last_assembled = (int64_t)alist.size();
+  HIPCHK(hipMemcpyAsync(h->d_need, need.data(), M.n_sub, hipMemcpyHostToDevice, h->st));
+  if (!alist.empty()) {
+    HIPCHK(hipMemcpyAsync(h->d_alist, alist.data(), alist.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
+    const int64_t na = (int64_t)alist.size();
+    launch_copy_band(h->d_subs, na, h->d_alist, nullptr, h->d_band, h->st);
+    for (int32_t p : alist) h->band_factored[p] = 0;
+    for (int c = 0; c < 8; ++c) {
+      a.elems = h->d_colour[c];
+      a.n_colour = h->n_colour[c];
+      launch_assemble(a, 2, h->st);
+    }
+    launch_pad_identity(h->d_subs, na, h->d_alist, h->d_band, h->st);
+    // the lumped preconditioner uses the unregularized tangent
+    if (h->prec == TFETI_PREC_FP64)
+      launch_gather_kbb<double>(h->dm, h->d_band, h->d_need, h->d_kbb_val, h->st);
+    else
+      launch_gather_kbb<float>(h->dm, h->d_band, h->d_need, h->d_kbb_val32, h->st);
+  }
+  if (!rlist.empty()) {
+    HIPCHK(hipMemcpyAsync(h->d_rlist, rlist.data(), rlist.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
+    const int64_t nr = (int64_t)rlist.size();
+    if (h->prec == TFETI_PREC_FP64)
+      launch_copy_kbb<double>(h->dm, nr, h->d_rlist, h->d_ekbb, h->d_kbb_val, h->st);
+    else
+      launch_copy_kbb<float>(h->dm, nr, h->d_rlist, h->d_ekbb32, h->d_kbb_val32, h->st);
+  }
   unsigned long long cnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
@@ -870,7 +912,10 @@ int factorize(tfeti_handle* h) {
     HIPCHK(hipMemcpyAsync(h->d_rlist, restore.data(), restore.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           h->st));
     pack(h, (int64_t)restore.size(), h->d_rlist, h->d_eband);
-    for (int32_t p : restore) h->fact_elastic[p] = 1;
+    for (int32_t p : restore) {
+      h->fact_elastic[p] = 1;
+      h->band_factored[p] = 0;
+    }
   }
   h->last_refactored = (int64_t)list.size();
   if (!list.empty()) {
@@ -915,6 +960,11 @@ int factorize(tfeti_handle* h) {
   if (!h->opt.refactor_all && !h->e_valid && h->d_eband && all_set(h->fact_elastic) && all_set(h->band_factored)) {
     HIPCHK(hipMemcpyAsync(h->d_eband, h->d_band, (size_t)M.band_entries * sizeof(double), hipMemcpyDeviceToDevice,
                           h->st));
+    const size_t nk = (size_t)M.kbb_goff.back();
+    if (h->prec == TFETI_PREC_FP64)
+      HIPCHK(hipMemcpyAsync(h->d_ekbb, h->d_kbb_val, nk * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    else
+      HIPCHK(hipMemcpyAsync(h->d_ekbb32, h->d_kbb_val32, nk * sizeof(float), hipMemcpyDeviceToDevice, h->st));
     h->e_valid = true;
   }
   return 0;
@@ -1022,6 +1072,12 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     RC(dalloc(h, &h->d_kbb_val, M.kbb_goff.back()));
   else
     RC(dalloc(h, &h->d_kbb_val32, M.kbb_goff.back()));
+  if (!h->opt.refactor_all) {
+    if (h->prec == TFETI_PREC_FP64)
+      RC(dalloc(h, &h->d_ekbb, M.kbb_goff.back()));
+    else
+      RC(dalloc(h, &h->d_ekbb32, M.kbb_goff.back()));
+  }
   RC(upload(h, &h->d_g_first, M.g_first));
   RC(upload(h, &h->d_g_rp, M.g_rp));
   RC(upload(h, &h->d_g_copies, M.g_copies));
@@ -1099,6 +1155,8 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   RC(dalloc(h, &h->d_subpl, M.n_sub));
   RC(dalloc(h, &h->d_flist, M.n_sub));
   RC(dalloc(h, &h->d_rlist, M.n_sub));
+  RC(dalloc(h, &h->d_alist, M.n_sub));
+  RC(dalloc(h, &h->d_need, M.n_sub));
   h->fact_elastic.assign(M.n_sub, 0);
   h->band_factored.assign(M.n_sub, 0);
   h->subpl.assign(M.n_sub, 0);

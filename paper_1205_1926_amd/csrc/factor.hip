@@ -24,8 +24,9 @@ void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st) {
 template void launch_convert_band<double>(const double*, double*, int64_t, hipStream_t);
 template void launch_convert_band<float>(const double*, float*, int64_t, hipStream_t);
 
-// Copy the row-band matrices of the listed subdomains: blockIdx.y picks the
-// subdomain, the blockIdx.x slices stride over its entries.
+// Copy the row-band matrices of the listed subdomains (zero them if src is
+// NULL): blockIdx.y picks the subdomain, the blockIdx.x slices stride over
+// its entries.
 __global__ __launch_bounds__(256) void copy_band_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                         const int32_t* __restrict__ list,
                                                         const double* __restrict__ src, double* __restrict__ dst) {
@@ -33,7 +34,7 @@ __global__ __launch_bounds__(256) void copy_band_kernel(const SubDev* __restrict
   const int64_t p = list[blockIdx.y];
   const int64_t off = subs[p].band_off, len = (int64_t)subs[p].npad * subs[p].Wb;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
-    dst[off + i] = src[off + i];
+    dst[off + i] = src ? src[off + i] : 0.0;
 }
 
 void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, const double* src, double* dst,

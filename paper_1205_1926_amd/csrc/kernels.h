@@ -26,16 +26,19 @@ struct AssembleArgs {
   unsigned long long* plastic_count;
   double* fint;               // torn internal force (accumulated)
   double* band;               // row-band tangent (accumulated)
+  const uint8_t* need;        // subdomains whose tangent is assembled (mode 2)
 };
 
 void launch_return_map(const tfeti_material& mat, int64_t npts, const double* sig, const double* kap,
                        const double* de, double* ds, double* dk, double* Dt, uint8_t* pl, hipStream_t st);
-void launch_assemble(const AssembleArgs& args, hipStream_t st);
-void launch_pad_identity(const SubDev* subs, int64_t nsub, double* band, hipStream_t st);
+// mode 1: return map, increments, internal force; mode 2: tangent of need[]
+void launch_assemble(const AssembleArgs& args, int mode, hipStream_t st);
+void launch_pad_identity(const SubDev* subs, int64_t nsub, const int32_t* list, double* band, hipStream_t st);
 // list: subdomain indices (count of them), or NULL for subdomains 0 .. count-1
 void launch_regularize(const SubDev* subs, int64_t count, const int32_t* list, const double* QQt, double* band,
                        hipStream_t st);
 void launch_sub_plastic(const SubDev* subs, int64_t nsub, const uint8_t* plastic, int32_t* flags, hipStream_t st);
+// src NULL: zero fill
 void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, const double* src, double* dst,
                       hipStream_t st);
 
@@ -137,9 +140,12 @@ void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
                      double* partials, const int32_t* done, hipStream_t st);
 // iface_out = K_bb (B^T w) per subdomain
-// K_bb values of every subdomain from the assembled (unregularized) band
+// K_bb values from the assembled (unregularized) band (subdomains flagged
+// in need, all if NULL); copy of the listed subdomains' values
 template <typename T>
-void launch_gather_kbb(const DualMaps& M, const double* band, T* out, hipStream_t st);
+void launch_gather_kbb(const DualMaps& M, const double* band, const uint8_t* need, T* out, hipStream_t st);
+template <typename T>
+void launch_copy_kbb(const DualMaps& M, int64_t count, const int32_t* list, const T* src, T* dst, hipStream_t st);
 template <typename TV>
 void launch_lumped(const DualMaps& M, const double* w, const TV* kbb_val, double* iface_out,
                    const int32_t* done, hipStream_t st);
