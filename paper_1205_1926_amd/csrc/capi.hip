@@ -265,13 +265,15 @@ void harvest_timing(tfeti_handle* h, int valid) {
   h->ev_used = 0;
 }
 
-// out = P x; optional partial sums of out.out.  The coarse solve stays in
-// FP64 in both modes: an FP32 copy of the explicit inverse of G G^T loses the
-// projector's accuracy in proportion to the coarse condition number.
-void project(tfeti_handle* h, const double* x, double* out, double* partials, const int32_t* done) {
+// out = P x; optional partial sums of out.out (of out.dotv if dotv is
+// given).  The coarse solve stays in FP64 in both modes: an FP32 copy of the
+// explicit inverse of G G^T loses the projector's accuracy in proportion to
+// the coarse condition number.
+void project(tfeti_handle* h, const double* x, double* out, double* partials, const int32_t* done,
+             const double* dotv = nullptr) {
   launch_g_apply(h->dm, x, h->d_c, done, h->st);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, done, h->st);
-  launch_gt_apply(h->dm, x, h->d_a, 1.0, out, partials, done, h->st);
+  launch_gt_apply(h->dm, x, h->d_a, 1.0, out, partials, done, h->st, dotv);
 }
 
 void precondition(tfeti_handle* h, const double* w, double* z, const int32_t* done) {
@@ -293,13 +295,13 @@ void enqueue_iteration_a(tfeti_handle* h, const int32_t* done) {
   const int64_t m = h->M.m;
   project(h, h->d_r, h->d_w, h->d_partials, done);
   launch_finalize(FIN_WW, h->d_S, h->d_partials, nred(h), h->st);
+  // y = P z with the partial sums of y.w from the same pass
   if (h->opt.preconditioner == 1) {
     precondition(h, h->d_w, h->d_z, done);
-    project(h, h->d_z, h->d_y, nullptr, done);
+    project(h, h->d_z, h->d_y, h->d_partials, done, h->d_w);
   } else {
-    project(h, h->d_w, h->d_y, nullptr, done);
+    project(h, h->d_w, h->d_y, h->d_partials, done, h->d_w);
   }
-  launch_dot_partials(h->d_y, h->d_w, m, h->d_partials, done, h->st);
   launch_finalize(FIN_YW, h->d_S, h->d_partials, nred(h), h->st);
   launch_update_p(m, h->d_y, h->d_p, h->d_S, h->st);
 }

@@ -300,6 +300,7 @@ void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double sc
 __global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* __restrict__ x,
                                                       const double* __restrict__ a, double sign,
                                                       double* __restrict__ out, double* __restrict__ partials,
+                                                      const double* __restrict__ dotv,
                                                       const int32_t* __restrict__ done) {
   __shared__ double sh[RB];
   if (done && *done) return;
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* 
     }
     double o = xr - sign * g;
     out[r] = o;
-    acc += o * o;
+    acc += o * (dotv ? dotv[r] : o);
   }
   if (partials) {
     double s = block_sum(acc, sh);
@@ -352,8 +353,8 @@ __global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* 
 }
 
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
-                     double* partials, const int32_t* done, hipStream_t st) {
-  gt_apply_kernel<<<dim3(reduction_blocks(M.m)), dim3(RB), 0, st>>>(M, x, a, sign, out, partials, done);
+                     double* partials, const int32_t* done, hipStream_t st, const double* dotv) {
+  gt_apply_kernel<<<dim3(reduction_blocks(M.m)), dim3(RB), 0, st>>>(M, x, a, sign, out, partials, dotv, done);
 }
 
 // ---------------------------------------------------------------- lumped preconditioner

@@ -42,12 +42,8 @@ void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, co
   if (count > 0) copy_band_kernel<<<dim3(32, (unsigned)count), dim3(256), 0, st>>>(subs, count, list, src, dst);
 }
 
-// Panels.  Tile rows TS, vector width V = 16 bytes / sizeof(T).
-// Forward panel of block row I: off-diagonal columns [I TS - w_I, I TS) then
-// the inverted diagonal tile; chunk (cc, r) of V consecutive columns of row
-// r is stored at ((cc TS) + r) V.  Backward panel of block column I: the
-// inverted diagonal tile rows first, then rows [(I+1) TS, (I+1) TS + w'_I);
-// chunk (rc, c) of V consecutive rows of column c is stored at (rc TS + c) V.
+// Panels (layout in kernels.h): tile rows TS, vector width V = 16 bytes /
+// sizeof(T).  Each workgroup takes block rows of one subdomain.
 template <typename TW, typename T, int TS>
 __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                           const int32_t* __restrict__ list,
@@ -73,20 +69,9 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
   const int b = s.b, Wb = s.Wb, n = s.npad, nb = n / TS;
   const int tid = threadIdx.x;
   auto L = [&](int r, int c) -> T { return (c <= r && r - c <= b && c >= 0) ? (T)A[(int64_t)r * Wb + (c - r + b)] : T(0); };
-  // block rows I = blockIdx.x, blockIdx.x + gridDim.x, ...; the panel
-  // offsets of block row I are sums over the rows before it (closed form:
-  // widths min(I TS, bo) forward and min(n - (I+1) TS, bo) backward)
+  // block rows I = blockIdx.x, blockIdx.x + gridDim.x, ...
   for (int I = blockIdx.x; I < nb; I += gridDim.x) {
-    int64_t offF = 0, offB = 0;
-    {
-      const int kF = (s.bo + TS - 1) / TS;  // block rows with I TS < bo
-      const int m1 = I < kF ? I : kF;
-      offF = (int64_t)TS * ((int64_t)TS * m1 * (m1 - 1) / 2 + (int64_t)(I - m1) * s.bo + (int64_t)I * TS);
-      for (int J = 0; J < I; ++J) {
-        const int remJ = n - (J + 1) * TS;
-        offB += (int64_t)TS * (TS + (remJ < s.bo ? remJ : s.bo));
-      }
-    }
+    const int64_t offF = panel_fwd_offset(I, TS, s.bo), offB = panel_bwd_offset(I, TS, s.bo, n);
     const int wF = I * TS < s.bo ? I * TS : s.bo;
     const int rem = n - (I + 1) * TS;
     const int wB = rem < s.bo ? rem : s.bo;
@@ -96,16 +81,7 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
     }
     __syncthreads();
     // inverse of the lower-triangular diagonal tile, one column per thread
-    if (tid < TS) {
-      const int j = tid;
-      const double xjj = 1.0 / sD[j][j];
-      sXd[j] = xjj;
-      for (int i = j + 1; i < TS; ++i) {
-        double v = sD[i][j] * xjj;
-        for (int k = j + 1; k < i; ++k) v += sD[i][k] * sD[j][k];
-        sD[j][i] = -v / sD[i][i];
-      }
-    }
+    if (tid < TS) tile_inverse_column(&sD[0][0], TS + 1, TS, tid, sXd);
     __syncthreads();
     // diagonal chunks of both layouts
     for (int q = tid; q < TS * TS; q += blockDim.x) {

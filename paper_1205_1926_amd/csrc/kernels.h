@@ -42,6 +42,38 @@ void launch_sub_plastic(const SubDev* subs, int64_t nsub, const uint8_t* plastic
 void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, const double* src, double* dst,
                       hipStream_t st);
 
+// ---- solve panels ----------------------------------------------------------
+// Panel geometry of one subdomain for tile TS (rows of a block row).
+// Forward panel of block row I: off-diagonal columns [I TS - wF, I TS), wF =
+// min(I TS, bo), then the inverted diagonal tile; chunk (cc, r) of V
+// consecutive columns of row r is stored at (cc TS + r) V.  Backward panel
+// of block column I: the inverted diagonal tile rows first, then rows
+// [(I+1) TS, (I+1) TS + wB), wB = min(n - (I+1) TS, bo); chunk (rc, c) of V
+// consecutive rows of column c is stored at (rc TS + c) V.  The offsets are
+// the sums of the panel sizes TS (w + TS) of the block rows before I.
+__host__ __device__ inline int64_t panel_fwd_offset(int64_t I, int64_t TS, int64_t bo) {
+  const int64_t kF = (bo + TS - 1) / TS;  // block rows with I TS < bo
+  const int64_t m1 = I < kF ? I : kF;
+  return TS * (TS * m1 * (m1 - 1) / 2 + (I - m1) * bo + I * TS);
+}
+__host__ __device__ inline int64_t panel_bwd_offset(int64_t I, int64_t TS, int64_t bo, int64_t n) {
+  int64_t K = n >= bo ? (n - bo) / TS : 0;  // block columns whose width is bo
+  K = K < I ? K : I;
+  return TS * (I * TS + K * bo + (I - K) * n - TS * (I * (I + 1) - K * (K + 1)) / 2);
+}
+// Column j of X = L^{-1} for the lower-triangular tile d (ts x ts, row
+// stride ld): X[i][j] (i > j) goes to d[j][i], the tile's strict upper
+// triangle, and X[j][j] = 1 / L[j][j] to xd[j].  One thread per column.
+__device__ inline void tile_inverse_column(double* d, int ld, int ts, int j, double* xd) {
+  const double xjj = 1.0 / d[j * ld + j];
+  xd[j] = xjj;
+  for (int i = j + 1; i < ts; ++i) {
+    double v = d[i * ld + j] * xjj;
+    for (int k = j + 1; k < i; ++k) v = fma(d[i * ld + k], d[j * ld + k], v);
+    d[j * ld + i] = -v / d[i * ld + i];
+  }
+}
+
 // ---- factorization -------------------------------------------------------
 // In-place band Cholesky of every subdomain's row-band matrix (type T).
 // bmax: largest half bandwidth; nb: block columns (0 = largest that fits LDS).
@@ -53,7 +85,7 @@ int band_cholesky_nb(int bmax, size_t elem);
 template <typename T>
 void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st);
 // Pack the factors into forward (F) and backward (B) panels with inverted
-// diagonal tiles.
+// diagonal tiles (layout above).
 // (factor in TW, panels in T: FP64 -> FP64 or FP64 -> FP32)
 template <typename TW, typename T>
 // Fq, Bq (optional): FP32 copies of the panels written in the same pass
@@ -136,9 +168,10 @@ void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double sc
 // tiles of the packed lower triangle of an l x l symmetric matrix (64 x 64)
 int64_t coarse_tiles(int64_t l);
 void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream_t st);
-// out = (x ? x : 0) - sign * G^T a; optional partial sums of out.out
+// out = (x ? x : 0) - sign * G^T a; optional partial sums of out.out, or of
+// out.dotv when dotv is given
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
-                     double* partials, const int32_t* done, hipStream_t st);
+                     double* partials, const int32_t* done, hipStream_t st, const double* dotv = nullptr);
 // iface_out = K_bb (B^T w) per subdomain
 // K_bb values from the assembled (unregularized) band (subdomains flagged
 // in need, all if NULL); copy of the listed subdomains' values

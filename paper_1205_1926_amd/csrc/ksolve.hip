@@ -16,7 +16,15 @@
 // not on the lower boundary), and the inverted diagonal tiles are
 // triangular.  Lanes skip the loads of chunks that lie entirely in those zero
 // parts (the backward pass with the interior envelope, a bound that is
-// monotone in the row), so the bytes read approach the envelope (skyline).
+// monotone in the row), so the bytes read approach the envelope (skyline);
+// in the forward pass the 8 rows that share a 128-byte line skip together,
+// up to the earliest of their envelopes, so that no line is requested by
+// two load instructions (a line requested twice may be fetched twice).  In
+// the backward pass a column also meets zero rows inside that bound (rows
+// of nodes on a lower boundary start later): a table of the first envelope
+// column of every chunk of rows sends such a lane's load to a line of zeros
+// instead, so the instruction stays unconditional and fetches only the lines
+// some lane needs.
 // Panel loads are non-temporal (each factor entry is read once per apply)
 // and issued four chunks at a time per lane (a sweep of 2..16 on MI355X put
 // the optimum at 4 for both precisions).
@@ -53,6 +61,9 @@ __device__ __forceinline__ double bcast<double>(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// zeros standing in for the panel chunks a lane skips (64 lanes x 16 bytes)
+__device__ __align__(256) double g_zero_chunks[128] = {};
+
 template <typename VT, int V>
 __device__ __forceinline__ auto vdot(const VT& a, const VT& b) -> decltype(a[0] * b[0]) {
   auto s = a[0] * b[0];
@@ -70,10 +81,12 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   constexpr int RPT = NT / TS;           // threads per tile row
   constexpr int UNR = 4;                 // panel chunks loaded back to back per lane
   extern __shared__ __align__(16) unsigned char smem[];
-  // NR right-hand sides, each a vector of vec_stride entries in LDS, then
-  // one partial sum per thread and right-hand side
+  // NR right-hand sides, each a vector of vec_stride entries in LDS, one
+  // partial sum per thread and right-hand side, then the first envelope
+  // column of each chunk of V rows
   T* xs0 = reinterpret_cast<T*>(smem);
   T* part0 = xs0 + NR * A.vec_stride;
+  int32_t* fcr = reinterpret_cast<int32_t*>(part0 + NR * NT);
   const int VS = A.vec_stride;
 
   if (A.done && *A.done) return;
@@ -87,10 +100,23 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   const int N0 = pa == 0 ? s.N[0] : (pa == 1 ? s.N[1] : s.N[2]);
   const int N1 = pb == 0 ? s.N[0] : (pb == 1 ? s.N[1] : s.N[2]);
 
+  // first envelope column of row `row` (padding rows: the diagonal)
+  auto first_col = [&](int row) {
+    if (row >= s.ndof) return row;
+    const int q = row / 3, i0 = q % N0, t = q / N0, i1 = t % N1, i2 = t / N1;
+    return 3 * (q - (i0 > 0) - (i1 > 0) * N0 - (i2 > 0) * N0 * N1);
+  };
+
   // ---- input: x_k = in_full (factor order) + lam_sign B^T lam_k ----
   for (int i = tid; i < n; i += NT)
 #pragma unroll
     for (int k = 0; k < NR; ++k) xs0[k * VS + i] = T(0);
+  for (int g = tid; g < n / V; g += NT) {
+    int f = first_col(g * V);
+#pragma unroll
+    for (int v = 1; v < V; ++v) f = min(f, first_col(g * V + v));
+    fcr[g] = f;
+  }
   __syncthreads();
   if (A.in_full) {
     for (int ld = tid; ld < s.ndof; ld += NT) {
@@ -130,11 +156,13 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
       for (int k = 0; k < NR; ++k) acc[k] = T(0);
       // first envelope column of the row (padding rows: the diagonal), and
       // the first chunk holding a column at or after it
-      int fc = I * TS + r;
-      if (fc < s.ndof) {
-        const int q = fc / 3, i0 = q % N0, t = q / N0, i1 = t % N1, i2 = t / N1;
-        fc = 3 * (q - (i0 > 0) - (i1 > 0) * N0 - (i2 > 0) * N0 * N1);
-      }
+      int fc = first_col(I * TS + r);
+      // the 8 rows of a 128-byte line (lanes 8k .. 8k+7 of the tile row)
+      // start at their earliest chunk together, so every line is requested
+      // by one load instruction and fetched once
+      fc = min(fc, __shfl_xor(fc, 1));
+      fc = min(fc, __shfl_xor(fc, 2));
+      fc = min(fc, __shfl_xor(fc, 4));
       const int cmin = fc > c0 ? (fc - c0) / V : 0;
       int cc = tid / TS;
       if (cc < cmin) cc += (cmin - cc + RPT - 1) / RPT * RPT;
@@ -221,13 +249,18 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
         cnt = cnt < 0 ? 0 : (cnt > nco * V ? nco * V : cnt);
         rend = (cnt + V - 1) / V;
       }
+      // chunk rr of this column, or zeros where its rows all start after it
+      const int col = I * TS + c;
+      const VT* zsrc = reinterpret_cast<const VT*>(g_zero_chunks) + (tid & 63);
+      auto src = [&](int rr) -> const VT* {
+        const VT* p = reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr) * TS + c) * V);
+        return fcr[rbase / V + rr] <= col ? p : zsrc;
+      };
       int rr = tid / TS;
       for (; rr + (UNR - 1) * RPT < rend; rr += UNR * RPT) {
         VT L[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-          L[u] = __builtin_nontemporal_load(
-              reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr + u * RPT) * TS + c) * V));
+        for (int u = 0; u < UNR; ++u) L[u] = __builtin_nontemporal_load(src(rr + u * RPT));
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -235,7 +268,7 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
             acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + (rr + u * RPT) * V));
       }
       for (; rr < rend; rr += RPT) {
-        VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr) * TS + c) * V);
+        VT L = *src(rr);
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           VT z = *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + rr * V);
@@ -323,13 +356,14 @@ static void launch_ts(const KsolveArgs<T>& b, int TS, size_t shm, hipStream_t st
 template <typename T>
 void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st) {
   // shared memory: NR vectors (npad_max entries each, rounded to 16 bytes)
-  // + NR partial sums per thread; a second right-hand side when lam2 is set
+  // + NR partial sums per thread + one envelope column per chunk of rows;
+  // a second right-hand side when lam2 is set
   // 1024 threads only with tiles of 16 or 32 rows (the 64-row kernel needs
   // more registers than 16 waves per compute unit leave)
   const int NT = (threads == 1024 && TS <= 32) ? 1024 : (threads == 512 ? 512 : 256);
   const int NR = a.lam2 ? 2 : 1;
   const size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
-  const size_t shm = NR * (vec + (size_t)NT * sizeof(T));
+  const size_t shm = NR * (vec + (size_t)NT * sizeof(T)) + (size_t)npad_max / (16 / sizeof(T)) * sizeof(int32_t);
   KsolveArgs<T> b = a;
   b.vec_stride = (int32_t)(vec / sizeof(T));
   if (NR == 2) {

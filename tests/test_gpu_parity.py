@@ -255,12 +255,26 @@ def test_newton_fp32_mode_matches_oracle(dev):
         assert rel(ug[o.untorn], o.u[o.untorn]) <= 1e-6, k
 
 
-@pytest.mark.parametrize("tile", [16, 64])
-def test_other_tiles(tile, dev):
-    P = Pair(W.small_cube(S=(2, 2, 1), n=(3, 4, 5), amp=300.0), dev, tile=tile)
+@pytest.mark.parametrize("tile,n,precision", [(16, (3, 4, 5), "fp64"), (32, (3, 4, 5), "fp64"),
+                                              (64, (3, 4, 5), "fp64"), (16, (10, 10, 10), "fp64"),
+                                              (32, (10, 10, 10), "fp32")])
+def test_other_tiles(tile, n, precision, dev):
+    """Tiles 16 and 32 have their panels written by the factorization
+    itself, tile 64 by the separate packing pass; 10^3-element subdomains
+    (half bandwidth 398) take the factorization's multi-pass panel path."""
+    P = Pair(W.small_cube(S=(2, 1, 1) if n[0] == 10 else (2, 2, 1), n=n, amp=300.0), dev, tile=tile,
+             precision=precision)
     rng = np.random.default_rng(6)
     lam = rng.standard_normal(P.mesh.m)
-    assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-9
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= tol
+    if precision == "fp32":
+        # the outer refinement runs on the FP64 panels written alongside
+        f = P.mesh.torn_load(1.0) - P.a["fint"]
+        ref = P.tf.solve(f, eps=1e-8)
+        lam, u, rep, rc = P.g.dual_pcg(T(f, dev))
+        assert rep["converged"] == 1
+        assert rel(N(u), ref["u"]) <= 1e-6
 
 
 def test_autotuner_choice_and_cache(tmp_path, monkeypatch, dev):
