@@ -184,7 +184,7 @@ double read_scalar(tfeti_handle* h, const double* d) {
 // ------------------------------------------------------------------ operators
 void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double lam_sign, double* out_iface,
             double* out_full, const double* alpha, const int32_t* done, bool use64 = false,
-            const double* lam2 = nullptr, double* out_iface2 = nullptr) {
+            const double* lam2 = nullptr, double* out_iface2 = nullptr, const PcgFold& fold = PcgFold{}) {
   if (h->prec == TFETI_PREC_FP64 || use64) {
     KsolveArgs<double> a{};
     a.subs = h->d_subs;
@@ -207,6 +207,7 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.done = done;
     a.lam2 = lam2;
     a.out_iface2 = out_iface2;
+    a.fold = fold;
     launch_ksolve<double>(a, h->TS, h->nt, h->npad_max, h->st);
   } else {
     KsolveArgs<float> a{};
@@ -230,6 +231,7 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.done = done;
     a.lam2 = lam2;
     a.out_iface2 = out_iface2;
+    a.fold = fold;
     launch_ksolve<float>(a, h->TS, h->nt, h->npad_max, h->st);
   }
 }
@@ -270,10 +272,10 @@ void harvest_timing(tfeti_handle* h, int valid) {
 // explicit inverse of G G^T loses the projector's accuracy in proportion to
 // the coarse condition number.
 void project(tfeti_handle* h, const double* x, double* out, double* partials, const int32_t* done,
-             const double* dotv = nullptr) {
-  launch_g_apply(h->dm, x, h->d_c, done, h->st);
+             const double* dotv = nullptr, const PcgFold& fold = PcgFold{}) {
+  launch_g_apply(h->dm, x, h->d_c, done, h->st, fold);
   launch_coarse_gemv(h->dm, h->d_c, h->d_a, 1.0, done, h->st);
-  launch_gt_apply(h->dm, x, h->d_a, 1.0, out, partials, done, h->st, dotv);
+  launch_gt_apply(h->dm, x, h->d_a, 1.0, out, partials, done, h->st, dotv, fold);
 }
 
 void precondition(tfeti_handle* h, const double* w, double* z, const int32_t* done) {
@@ -288,12 +290,20 @@ int nred(tfeti_handle* h) { return reduction_blocks(h->M.m); }
 
 // ------------------------------------------------------------------ PCGP
 // One PCGP iteration (Algorithm 3 loop body) on r, lambda_Ker, p with the
-// scalars in d_S; every kernel returns at once when S->done is set.
-// Part A: projection, preconditioner, re-projection, beta and the new
-// direction p.
+// scalars in d_S; every kernel returns at once when S->done is set.  The
+// vector updates have no kernels of their own: the new direction p = y +
+// beta p is formed by the subdomain solve as it reads p and stored by the q
+// gather, and r - gamma q, lambda_Ker + gamma p are formed and stored by the
+// first projection of the next iteration (PcgFold).
+PcgFold fold_direction(tfeti_handle* h) { return PcgFold{h->d_S, h->d_y, nullptr, h->d_p, nullptr, nullptr}; }
+PcgFold fold_residual(tfeti_handle* h) {
+  return PcgFold{h->d_S, nullptr, h->d_q, h->d_p, h->d_lam_ker, h->d_r};
+}
+
+// Part A: the previous iteration's updates and the projection of r, the
+// stopping test, preconditioner, re-projection and beta.
 void enqueue_iteration_a(tfeti_handle* h, const int32_t* done) {
-  const int64_t m = h->M.m;
-  project(h, h->d_r, h->d_w, h->d_partials, done);
+  project(h, h->d_r, h->d_w, h->d_partials, done, nullptr, fold_residual(h));
   launch_finalize(FIN_WW, h->d_S, h->d_partials, nred(h), h->st);
   // y = P z with the partial sums of y.w from the same pass
   if (h->opt.preconditioner == 1) {
@@ -303,23 +313,25 @@ void enqueue_iteration_a(tfeti_handle* h, const int32_t* done) {
     project(h, h->d_w, h->d_y, h->d_partials, done, h->d_w);
   }
   launch_finalize(FIN_YW, h->d_S, h->d_partials, nred(h), h->st);
-  launch_update_p(m, h->d_y, h->d_p, h->d_S, h->st);
 }
 
 // Part B (after the subdomain solves of q = F p): the B gather fused with
-// p.q, gamma, and the updates of lambda and r.
+// storing p and with p.q, then gamma.
 void enqueue_iteration_b(tfeti_handle* h, const int32_t* done) {
-  const int64_t m = h->M.m;
-  launch_gather(h->dm, h->d_iface, h->d_q, h->d_p, h->d_partials, done, h->st);
+  launch_gather(h->dm, h->d_iface, h->d_q, nullptr, h->d_partials, done, h->st, fold_direction(h));
   launch_finalize(FIN_PQ, h->d_S, h->d_partials, nred(h), h->st);
-  launch_update_lr(m, h->d_p, h->d_q, h->d_lam_ker, h->d_r, h->d_S, h->st);
+}
+
+// The subdomain-solve kernel of one iteration's F-apply, on p = y + beta p.
+void iteration_ksolve(tfeti_handle* h, const int32_t* done) {
+  ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done, false, nullptr, nullptr, fold_direction(h));
 }
 
 // The F-apply's subdomain-solve kernel of one iteration (timed if asked).
 void enqueue_iteration_solve(tfeti_handle* h, const int32_t* done, bool timed) {
   const bool rec = timed && h->timing && 2 * h->ev_used + 1 < (int)h->ev.size();
   if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], h->st);
-  ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done);
+  iteration_ksolve(h, done);
   if (rec) {
     (void)hipEventRecord(h->ev[2 * h->ev_used + 1], h->st);
     h->ev_used++;
@@ -344,7 +356,7 @@ bool capture_one(tfeti_handle* h, hipGraphExec_t* exec, int batch, int part) {
         // (events 2k, 2k+1; read after each replay)
         enqueue_iteration_a(h, done);
         ok = ok && hipEventRecordWithFlags(h->ev[2 * k], h->gs, hipEventRecordExternal) == hipSuccess;
-        ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done);
+        iteration_ksolve(h, done);
         ok = ok && hipEventRecordWithFlags(h->ev[2 * k + 1], h->gs, hipEventRecordExternal) == hipSuccess;
         enqueue_iteration_b(h, done);
         continue;

@@ -35,13 +35,17 @@ int reduction_blocks(int64_t n) {
 }
 
 // ---------------------------------------------------------------- gather
+// fold.S: the direction fold.p of the iteration is taken as fma(beta, p, y)
+// (the update the subdomain solve applied on the fly), stored back and
+// dotted with the output in place of dotv
 __global__ __launch_bounds__(RB) void gather_kernel(int64_t m, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ ent, const double* __restrict__ val,
                                                     const double* __restrict__ iface, double* __restrict__ out,
                                                     const double* __restrict__ dotv, double* __restrict__ partials,
-                                                    const int32_t* __restrict__ done) {
+                                                    PcgFold fold, const int32_t* __restrict__ done) {
   __shared__ double sh[RB];
   if (done && *done) return;
+  const double beta = fold.S ? fold.S->beta : 0.0;
   double acc = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < m; r += (int64_t)gridDim.x * RB) {
     // the first two entries' loads are issued together (most rows have two)
@@ -58,7 +62,13 @@ __global__ __launch_bounds__(RB) void gather_kernel(int64_t m, const int64_t* __
     q = h1 ? q2 : q;
     for (int64_t e = e0 + 2; e < e1; ++e) q += val[e] * iface[ent[e]];
     out[r] = q;
-    if (dotv) acc += q * dotv[r];
+    if (fold.S) {
+      const double pn = fma(beta, fold.p[r], fold.y[r]);
+      fold.p[r] = pn;
+      acc += q * pn;
+    } else if (dotv) {
+      acc += q * dotv[r];
+    }
   }
   if (partials) {
     double s = block_sum(acc, sh);
@@ -67,9 +77,9 @@ __global__ __launch_bounds__(RB) void gather_kernel(int64_t m, const int64_t* __
 }
 
 void launch_gather(const DualMaps& M, const double* iface, double* out, const double* dotv, double* partials,
-                   const int32_t* done, hipStream_t st) {
+                   const int32_t* done, hipStream_t st, const PcgFold& fold) {
   gather_kernel<<<dim3(reduction_blocks(M.m)), dim3(RB), 0, st>>>(M.m, M.b_rowptr, M.b_iface, M.b_val, iface, out,
-                                                                    dotv, partials, done);
+                                                                    dotv, partials, fold, done);
 }
 
 // ---------------------------------------------------------------- G w
@@ -95,10 +105,15 @@ __device__ __forceinline__ void block_sum6(double (&acc)[6], double (*sh)[6]) {
 // thread in flight): v = coef * w[row] lands on the raw modes of the entry's
 // node (translation of its component; rotations by its centred coordinates);
 // the six sums are scaled to the orthonormal modes at the end.
+// fold.S with S->pend: w is r of the previous iteration, taken as
+// fma(-gamma, q, r)
 __global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* __restrict__ w,
-                                                     double* __restrict__ c, const int32_t* __restrict__ done) {
+                                                     double* __restrict__ c, PcgFold fold,
+                                                     const int32_t* __restrict__ done) {
   __shared__ double sh[RB / 64][6];
   if (done && *done) return;
+  const bool pend = fold.S && fold.S->pend;
+  const double mg = pend ? -fold.S->gamma : 0.0;
   const int64_t p = blockIdx.x;
   const int64_t t0 = M.subs[p].iface_off;
   const int32_t e0 = M.if_rp[t0], e1 = M.if_rp[t0 + M.subs[p].n_iface];
@@ -118,6 +133,13 @@ __global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* _
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) wv[u] = w[row[u]];
+    if (pend) {
+      double qv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) qv[u] = fold.q[row[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) wv[u] = fma(mg, qv[u], wv[u]);
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const double v = cf[u] * wv[u];
@@ -138,8 +160,9 @@ __global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* _
   }
 }
 
-void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st) {
-  g_apply_kernel<<<dim3((unsigned)M.nsub), dim3(RB), 0, st>>>(M, w, c, done);
+void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st,
+                    const PcgFold& fold) {
+  g_apply_kernel<<<dim3((unsigned)M.nsub), dim3(RB), 0, st>>>(M, w, c, fold, done);
 }
 
 // ---------------------------------------------------------------- R^T f
@@ -297,18 +320,27 @@ void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double sc
 // ---------------------------------------------------------------- x - G^T a
 // One multiplier row per thread: (G^T a)_r = sum_e b_val[e] R(node_e) . a_p(e),
 // the mode values of the entry's node formed from its packed coordinates.
-__global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* __restrict__ x,
+// fold.S with S->pend: x is r of the previous iteration; fma(-gamma, q, r)
+// is used and stored to fold.r, and lambda takes fma(gamma, p, lambda)
+__global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* x,
                                                       const double* __restrict__ a, double sign,
                                                       double* __restrict__ out, double* __restrict__ partials,
-                                                      const double* __restrict__ dotv,
+                                                      const double* __restrict__ dotv, PcgFold fold,
                                                       const int32_t* __restrict__ done) {
   __shared__ double sh[RB];
   if (done && *done) return;
+  const bool pend = fold.S && fold.S->pend;
+  const double gam = pend ? fold.S->gamma : 0.0;
   const double hh[3] = {M.hh[0], M.hh[1], M.hh[2]};
   double acc = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < M.m; r += (int64_t)gridDim.x * RB) {
     const int64_t e0 = M.b_rowptr[r], e1 = M.b_rowptr[r + 1];
-    const double xr = x ? x[r] : 0.0;
+    double xr = x ? x[r] : 0.0;
+    if (pend) {
+      xr = fma(-gam, fold.q[r], xr);
+      fold.r[r] = xr;
+      fold.lam[r] = fma(gam, fold.p[r], fold.lam[r]);
+    }
     double g = 0.0;
     // entries two at a time, the second one's index clamped so that every
     // load is unconditional and in flight together
@@ -353,8 +385,10 @@ __global__ __launch_bounds__(RB) void gt_apply_kernel(DualMaps M, const double* 
 }
 
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
-                     double* partials, const int32_t* done, hipStream_t st, const double* dotv) {
-  gt_apply_kernel<<<dim3(reduction_blocks(M.m)), dim3(RB), 0, st>>>(M, x, a, sign, out, partials, dotv, done);
+                     double* partials, const int32_t* done, hipStream_t st, const double* dotv,
+                     const PcgFold& fold) {
+  gt_apply_kernel<<<dim3(reduction_blocks(M.m)), dim3(RB), 0, st>>>(M, x, a, sign, out, partials, dotv, fold,
+                                                                      done);
 }
 
 // ---------------------------------------------------------------- lumped preconditioner
@@ -440,22 +474,6 @@ template void launch_lumped<float>(const DualMaps&, const double*, const float*,
                                    hipStream_t);
 
 // ---------------------------------------------------------------- reductions
-__global__ __launch_bounds__(RB) void dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
-                                                 int64_t n, double* __restrict__ partials,
-                                                 const int32_t* __restrict__ done) {
-  __shared__ double sh[RB];
-  if (done && *done) return;
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) acc += x[i] * y[i];
-  double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-void launch_dot_partials(const double* x, const double* y, int64_t n, double* partials, const int32_t* done,
-                         hipStream_t st) {
-  dot_kernel<<<dim3(reduction_blocks(n)), dim3(RB), 0, st>>>(x, y, n, partials, done);
-}
-
 __global__ __launch_bounds__(RB) void finalize_kernel(int kind, PcgScalars* S, const double* __restrict__ partials,
                                                       int nparts) {
   __shared__ double sh[RB];
@@ -477,6 +495,7 @@ __global__ __launch_bounds__(RB) void finalize_kernel(int kind, PcgScalars* S, c
       } else if (S->iters >= S->maxit) {
         S->done = 2;
       }
+      S->pend = 0;  // the projection before this applied them
       break;
     }
     case FIN_YW:
@@ -488,6 +507,7 @@ __global__ __launch_bounds__(RB) void finalize_kernel(int kind, PcgScalars* S, c
       S->gamma = S->yw / sum;
       S->yw_prev = S->yw;
       S->iters += 1;
+      S->pend = 1;
       break;
     case FIN_RREF:
       S->r_ref = sqrt(sum);
@@ -530,32 +550,6 @@ __global__ void copy_kernel(int64_t n, const double* __restrict__ x, double* __r
 }
 void launch_copy(int64_t n, const double* x, double* y, hipStream_t st) {
   if (n > 0) copy_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, x, y);
-}
-
-__global__ void update_p_kernel(int64_t n, const double* __restrict__ y, double* __restrict__ p,
-                                const PcgScalars* __restrict__ S) {
-  if (S->done) return;
-  const double beta = S->beta;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = y[i] + beta * p[i];
-}
-void launch_update_p(int64_t n, const double* y, double* p, const PcgScalars* S, hipStream_t st) {
-  update_p_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, y, p, S);
-}
-
-__global__ void update_lr_kernel(int64_t n, const double* __restrict__ p, const double* __restrict__ q,
-                                 double* __restrict__ lam, double* __restrict__ r, const PcgScalars* __restrict__ S) {
-  if (S->done) return;
-  const double g = S->gamma;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    lam[i] += g * p[i];
-    r[i] -= g * q[i];
-  }
-}
-void launch_update_lr(int64_t n, const double* p, const double* q, double* lam, double* r, const PcgScalars* S,
-                      hipStream_t st) {
-  update_lr_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(n, p, q, lam, r, S);
 }
 
 __global__ void check_finite_kernel(int64_t n, const double* __restrict__ x, PcgScalars* S) {

@@ -118,6 +118,7 @@ struct KsolveArgs {
   const double* lam2;         // a second right-hand side in_full + lam_sign B^T lam2, or nullptr
   double* out_iface2;         // its z at the touched DOFs (with lam2)
   int32_t vec_stride;         // LDS entries per right-hand side; set by the launcher
+  PcgFold fold;               // fold.S: lam is p, taken as fma(beta, p, fold.y)
 };
 template <typename T>
 void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st);
@@ -155,9 +156,10 @@ struct DualMaps {
 
 // out[r] = sum_e b_val[e] * iface[b_iface[e]]; if dotv: partial sums of out.dotv
 void launch_gather(const DualMaps& M, const double* iface, double* out, const double* dotv, double* partials,
-                   const int32_t* done, hipStream_t st);
+                   const int32_t* done, hipStream_t st, const PcgFold& fold = PcgFold{});
 // c[6p+j] = sum_t R_iface[t][j] (B^T w)_t   (G w)
-void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st);
+void launch_g_apply(const DualMaps& M, const double* w, double* c, const int32_t* done, hipStream_t st,
+                    const PcgFold& fold = PcgFold{});
 // c[6p+j] = sum_ld R_full[ld][j] f[ld]       (R^T f)
 void launch_rt_apply(const DualMaps& M, const double* f, double* c, hipStream_t st);
 // u = z + R alpha per subdomain (torn vectors; alpha 6 per subdomain)
@@ -171,7 +173,8 @@ void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream
 // out = (x ? x : 0) - sign * G^T a; optional partial sums of out.out, or of
 // out.dotv when dotv is given
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,
-                     double* partials, const int32_t* done, hipStream_t st, const double* dotv = nullptr);
+                     double* partials, const int32_t* done, hipStream_t st, const double* dotv = nullptr,
+                     const PcgFold& fold = PcgFold{});
 // iface_out = K_bb (B^T w) per subdomain
 // K_bb values from the assembled (unregularized) band (subdomains flagged
 // in need, all if NULL); copy of the listed subdomains' values
@@ -184,8 +187,6 @@ void launch_lumped(const DualMaps& M, const double* w, const TV* kbb_val, double
                    const int32_t* done, hipStream_t st);
 
 int reduction_blocks(int64_t n);
-void launch_dot_partials(const double* x, const double* y, int64_t n, double* partials, const int32_t* done,
-                         hipStream_t st);
 // scalar finalizers (single thread); see dual.hip
 void launch_finalize(int kind, PcgScalars* S, const double* partials, int nparts, hipStream_t st);
 enum FinalizeKind { FIN_WW = 0, FIN_YW = 1, FIN_PQ = 2, FIN_RREF = 3, FIN_SUM_TMP0 = 4 };
@@ -193,11 +194,6 @@ enum FinalizeKind { FIN_WW = 0, FIN_YW = 1, FIN_PQ = 2, FIN_RREF = 3, FIN_SUM_TM
 // y = a x + b y style helpers (guarded by done when given)
 void launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 void launch_copy(int64_t n, const double* x, double* y, hipStream_t st);
-// p = y + beta p  (beta from S)
-void launch_update_p(int64_t n, const double* y, double* p, const PcgScalars* S, hipStream_t st);
-// lam += gamma p; r -= gamma q  (gamma from S)
-void launch_update_lr(int64_t n, const double* p, const double* q, double* lam, double* r, const PcgScalars* S,
-                      hipStream_t st);
 // nonfinite check: S->nonfinite |= any(!isfinite(x))
 void launch_check_finite(int64_t n, const double* x, PcgScalars* S, hipStream_t st);
 

@@ -128,6 +128,7 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
     __syncthreads();
   }
   if (A.lam) {
+    const double beta = A.fold.S ? A.fold.S->beta : 0.0;
     for (int t = tid; t < s.n_iface; t += NT) {
       const int64_t it = s.iface_off + t;
       double v = A.in_full ? A.in_full[s.dof_off + A.if_ldof[it]] : 0.0;
@@ -135,7 +136,11 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
       for (int k = 0; k < NR; ++k) {
         const double* lam = k == 0 ? A.lam : A.lam2;
         double bt = 0.0;
-        for (int e = A.if_rp[it]; e < A.if_rp[it + 1]; ++e) bt += A.if_coef[e] * lam[A.if_row[e]];
+        for (int e = A.if_rp[it]; e < A.if_rp[it + 1]; ++e) {
+          const int32_t row = A.if_row[e];
+          const double lv = (k == 0 && A.fold.S) ? fma(beta, lam[row], A.fold.y[row]) : lam[row];
+          bt += A.if_coef[e] * lv;
+        }
         xs0[k * VS + A.if_fidx[it]] = (T)(v + A.lam_sign * bt);
       }
     }

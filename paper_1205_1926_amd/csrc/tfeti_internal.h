@@ -102,7 +102,23 @@ struct PcgScalars {
   double ww, yw, yw_prev, pq, beta, gamma, r_ref, eps;
   double rr, tmp0, tmp1, tmp2;
   int32_t done, iters, maxit, nonfinite;
-  int32_t spd_fail, pad[3];
+  int32_t spd_fail;
+  int32_t pend;  // the updates r -= gamma q, lambda += gamma p are still to apply
+  int32_t pad[2];
+};
+
+// Vector updates of a PCGP iteration folded into the kernels that read the
+// vectors next (S == nullptr: none).  In the subdomain solve and the q
+// gather, the direction is p = y + beta p (the gather stores it); in the
+// first projection of the next iteration, r - gamma q replaces r and
+// lambda + gamma p replaces lambda while S->pend is set.
+struct PcgFold {
+  const PcgScalars* S;
+  const double* y;  // p = fma(beta, p, y)
+  const double* q;  // r = fma(-gamma, q, r)
+  double* p;        // lambda = fma(gamma, p, lambda)
+  double* lam;
+  double* r;
 };
 
 struct DeviceBuffers;
