@@ -260,10 +260,12 @@ int tfeti_set_state(tfeti_handle* h, const double* sigma, const double* kappa,
 /* Multipliers of the last PCGP solve (m, FP64, device). */
 int tfeti_get_lambda(const tfeti_handle* h, double* lambda);
 
-/* Timing of the dominant kernel: when on, every F-apply's subdomain-solve
- * kernel is bracketed by HIP events on the handle's stream; get returns the
- * summed kernel milliseconds and the number of kernels that did work since
- * the last set (set also resets the totals). */
+/* Timing of the dominant kernel: when on, F-apply subdomain-solve kernels
+ * are bracketed by HIP events on the stream they run on (inside a replayed
+ * PCGP graph, those of one graph batch in four, the rest replay a graph
+ * without event nodes); get returns the summed milliseconds and the number
+ * of timed kernels that did work since the last set (set also resets the
+ * totals). */
 int tfeti_set_timing(tfeti_handle* h, int on);
 int tfeti_get_timing(tfeti_handle* h, double* ms_host, int64_t* count_host);
 

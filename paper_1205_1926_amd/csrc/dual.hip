@@ -14,14 +14,16 @@ namespace {
 constexpr int RB = 256;            // threads of reduction blocks
 constexpr int kMaxRedBlocks = 4096;
 
+// sum over a workgroup of RB threads: wavefront shuffles, then the
+// wavefronts' sums in order (fixed order, deterministic); every thread gets
+// the result
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = RB / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
   double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < RB / 64; ++w) r += sh[w];
   __syncthreads();
   return r;
 }
@@ -398,10 +400,13 @@ void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double
 // stored slot-major, so every load is 64 consecutive values) and walks the
 // lanes' neighbour masks LU nodes at a time, summing values x neighbour
 // components in bit order (fixed order, deterministic); lanes with fewer
-// nodes than the group read zero values against their own node.
+// nodes than the group read zero values against their own node.  A
+// wavefront's first group (slot data and first block of values) does not
+// depend on the scatter and is requested before it, so its loads are in
+// flight during the scatter's chain of dependent loads.
 namespace {
-constexpr int LT = 512;  // threads of the preconditioner workgroups
-constexpr int LU = 4;    // neighbour nodes per step
+constexpr int LT = 1024;  // threads of the preconditioner workgroups
+constexpr int LU = 4;     // neighbour nodes per step
 }  // namespace
 
 template <typename TV>
@@ -413,43 +418,59 @@ __global__ __launch_bounds__(LT) void lumped_kernel(DualMaps M, const double* __
   const int64_t p = blockIdx.x;
   const int32_t nif = M.subs[p].n_iface, ndof = M.subs[p].ndof, N0 = M.subs[p].N[0], N1 = M.subs[p].N[1];
   const int64_t ioff = M.subs[p].iface_off;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int32_t gend = M.kbb_g0[p + 1];
+  // the wavefront's current group: output row, neighbour mask, node, node
+  // count, values, and the block of values of LU nodes from b0 on (past the
+  // group's count the last node's values again, zeroed)
+  int32_t g = M.kbb_g0[p] + wave, it = -1, a = 0, nb = 1;
+  uint32_t mask = 0;
+  const TV* v = kv;
+  TV x[3 * LU];
+  auto load_block = [&](int b0) {
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const bool in = b0 + u < nb;
+      const int bb = in ? b0 + u : nb - 1;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const TV t = v[(int64_t)(3 * bb + c) * 64];
+        x[3 * u + c] = in ? t : TV(0);
+      }
+    }
+  };
+  auto start_group = [&]() {
+    const int64_t slot = 64 * (int64_t)g + lane;
+    it = M.kbb_row[slot];
+    mask = M.kbb_mask[slot];
+    a = M.kbb_node[slot];
+    nb = M.kbb_gnb[g];
+    v = kv + M.kbb_goff[g] + lane;
+    load_block(0);
+  };
+  if (g < gend) start_group();
+
   for (int q = threadIdx.x; q < ndof; q += LT) vloc[q] = 0.0;
   __syncthreads();
   for (int t = threadIdx.x; t < nif; t += LT) {
     // every touched DOF has an entry: the first one's loads are unconditional
-    const int64_t it = ioff + t;
-    const int32_t e0 = M.if_rp[it], e1 = M.if_rp[it + 1], ld = M.if_ldof[it];
-    double v = M.if_coef[e0] * w[M.if_row[e0]];
-    for (int e = e0 + 1; e < e1; ++e) v += M.if_coef[e] * w[M.if_row[e]];
-    vloc[ld] = v;
+    const int64_t i = ioff + t;
+    const int32_t e0 = M.if_rp[i], e1 = M.if_rp[i + 1], ld = M.if_ldof[i];
+    double s = M.if_coef[e0] * w[M.if_row[e0]];
+    for (int e = e0 + 1; e < e1; ++e) s += M.if_coef[e] * w[M.if_row[e]];
+    vloc[ld] = s;
   }
   __syncthreads();
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int32_t g1 = M.kbb_g0[p + 1];
-  for (int32_t g = M.kbb_g0[p] + wave; g < g1; g += LT / 64) {
-    const int64_t slot = 64 * (int64_t)g + lane;
-    const int32_t it = M.kbb_row[slot];
-    uint32_t mask = M.kbb_mask[slot];
-    const int nb = M.kbb_gnb[g];
-    const TV* v = kv + M.kbb_goff[g] + lane;
-    const int32_t a = it >= 0 ? M.if_ldof[it] / 3 : 0;
+  while (g < gend) {
     double y = 0.0;
     for (int b0 = 0; b0 < nb; b0 += LU) {
+      if (b0 > 0) load_block(b0);
       int a2[LU];
-      TV x[3 * LU];
 #pragma unroll
       for (int u = 0; u < LU; ++u) {
         const int k = mask ? __ffs(mask) - 1 : 13;  // 13: the node itself
         mask &= mask - 1;
         a2[u] = a + (k % 3 - 1) + N0 * ((k / 3) % 3 - 1 + N1 * (k / 9 - 1));
-        // past the group's count: the last block is read again and zeroed
-        const bool in = b0 + u < nb;
-        const int bb = in ? b0 + u : nb - 1;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const TV t = v[(int64_t)(3 * bb + c) * 64];
-          x[3 * u + c] = in ? t : TV(0);
-        }
       }
 #pragma unroll
       for (int u = 0; u < LU; ++u)
@@ -457,6 +478,8 @@ __global__ __launch_bounds__(LT) void lumped_kernel(DualMaps M, const double* __
         for (int c = 0; c < 3; ++c) y += (double)x[3 * u + c] * vloc[3 * a2[u] + c];
     }
     if (it >= 0) out[it] = y;
+    g += LT / 64;
+    if (g < gend) start_group();
   }
 }
 

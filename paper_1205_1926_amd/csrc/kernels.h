@@ -143,6 +143,7 @@ struct DualMaps {
   // K_bb in wavefront groups of 64 touched DOFs (lane slot = 64 group + lane)
   const int32_t* kbb_row;      // touched DOF of each lane slot, -1 past the end
   const uint32_t* kbb_mask;    // its touched nodes among the 27 around its node
+  const int32_t* kbb_node;     // its node (local natural index)
   const int64_t* kbb_goff;     // value offset of each group
   const int32_t* kbb_gnb;      // neighbour blocks of each group (values 3 x 64 per block)
   const int32_t* kbb_gsub;     // subdomain of each group

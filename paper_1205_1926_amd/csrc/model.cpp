@@ -385,6 +385,7 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
     M.kbb_g0.assign(M.n_sub + 1, 0);
     M.kbb_row.clear();
     M.kbb_mask.clear();
+    M.kbb_node.clear();
     M.kbb_goff.assign(1, 0);
     M.kbb_gnb.clear();
     M.kbb_gsub.clear();
@@ -419,10 +420,12 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
           if (q < s.n_iface) {
             M.kbb_row.push_back((int32_t)(s.iface_off + ord[q]));
             M.kbb_mask.push_back(mask[ord[q]]);
+            M.kbb_node.push_back(M.if_ldof[s.iface_off + ord[q]] / 3);
             nb = std::max(nb, __builtin_popcount(mask[ord[q]]));
           } else {
             M.kbb_row.push_back(-1);
             M.kbb_mask.push_back(0u);
+            M.kbb_node.push_back(0);
           }
         }
         M.kbb_gnb.push_back(nb);

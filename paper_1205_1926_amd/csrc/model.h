@@ -51,6 +51,7 @@ struct HostModel {
   // offset, the block count and the subdomain; per subdomain its first group
   std::vector<int32_t> kbb_row;         // 64 per group
   std::vector<uint32_t> kbb_mask;       // 64 per group
+  std::vector<int32_t> kbb_node;        // 64 per group: local node of the slot's DOF (0 past the end)
   std::vector<int64_t> kbb_goff;        // groups + 1
   std::vector<int32_t> kbb_gnb;         // groups
   std::vector<int32_t> kbb_gsub;        // groups

@@ -220,7 +220,7 @@ def test_graph_replay_matches_eager(dev):
     # one fixed tile: the autotuner could pick different kernels per handle
     ge = GpuSolver(w, use_graph=0, tile=32)
     gg = GpuSolver(w, use_graph=1, tile=32)
-    gt = GpuSolver(w, use_graph=1, tile=32)  # split replay with timed solve kernels
+    gt = GpuSolver(w, use_graph=1, tile=32)  # replay with timed solve kernels in one batch of four
     gt.set_timing(True)
     du = torch.zeros(ge.sizes["n_torn"], dtype=torch.float64, device=dev)
     for g in (ge, gg, gt):
@@ -240,7 +240,9 @@ def test_graph_replay_matches_eager(dev):
         total += re["iters"]
     assert gg.graph_active() == 1 and gt.graph_active() == 1
     ms, cnt = gt.timing()
-    assert cnt == total and ms > 0
+    # the solve kernels of the first batch of 8 iterations (and of every
+    # fourth batch after it) are timed, the others replay without events
+    assert min(total, 8) <= cnt < total and ms > 0
 
 
 def test_newton_fp32_mode_matches_oracle(dev):
