@@ -429,16 +429,12 @@ bool capture_graph(tfeti_handle* h, int batch) {
 }
 
 // Run PCGP iterations from the current r, lambda_Ker (p = 0) until
-// ||P r|| <= eps * S.r_ref or maxit.  Returns the final scalars.
-int pcg_loop(tfeti_handle* h, double eps, int maxit, PcgScalars* out) {
+// ||P r|| <= eps * rref or maxit.  Returns the final scalars.
+int pcg_loop(tfeti_handle* h, double rref, double eps, int maxit, PcgScalars* out) {
   const int64_t m = h->M.m;
-  // reset the iteration scalars, keep r_ref
+  // reset the iteration scalars with the reference norm of the stopping test
   {
     PcgScalars S0{};
-    HIPCHK(hipMemcpyAsync(&S0, h->d_S, sizeof(PcgScalars), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    double rref = S0.r_ref;
-    S0 = PcgScalars{};
     S0.r_ref = rref;
     S0.eps = eps;
     S0.maxit = maxit;
@@ -612,8 +608,7 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
   bool converged = false;
   double r_final = r_ref;
   if (!mixed) {
-    set_rref(h, h->d_dt, h->d_w);  // S.r_ref = ||P d~|| for the stopping test
-    int st = pcg_loop(h, h->opt.eps_pcg, h->opt.max_pcg, &Sh);
+    int st = pcg_loop(h, r_ref, h->opt.eps_pcg, h->opt.max_pcg, &Sh);
     if (st < 0) return st;
     status = st;
     total_iters = Sh.iters;
@@ -658,7 +653,7 @@ int pcg_solve(tfeti_handle* h, const double* f, const double* guess, const doubl
       // inner tolerance: the reduction still needed (with a factor 2 of
       // margin), but not below what the FP32 operator can be trusted with
       const double eps_in = std::min(0.5, std::max(eps_floor, 0.5 * h->opt.eps_pcg * r_ref / nrho));
-      int st = pcg_loop(h, eps_in, h->opt.max_pcg - total_iters, &Sh);
+      int st = pcg_loop(h, nrho, eps_in, h->opt.max_pcg - total_iters, &Sh);
       if (st < 0) return st;
       total_iters += Sh.iters;
       fapplies += Sh.iters;
