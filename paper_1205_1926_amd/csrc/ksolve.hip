@@ -147,35 +147,65 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   }
   __syncthreads();
 
+  // Both passes walk the block rows; per block row all lanes stream their
+  // off-diagonal chunks (UNR loads in flight) into partial dots, then wave 0
+  // reduces them and applies the inverted diagonal tile.  Two kinds of load
+  // do not depend on the block row just solved and are requested before the
+  // barriers that order the work: wave 0's diagonal-tile chunks (before the
+  // first barrier, when the tile is small enough to hold in registers), and
+  // every lane's first batch of chunks of the next block row (before the
+  // second barrier, while wave 0 solves the diagonal block).
+  constexpr bool DIAG_PRE = TS / V <= 8;
+
   // ---- forward substitution L y = x (in place) ----
   {
     const T* P = A.Fp + s.panel_off;
-    int64_t off = 0;
     const int r = tid % TS;
-    for (int I = 0; I < nb; ++I) {
+    // block row I: chunk count, first column, and this lane's first chunk
+    // (the 8 rows of a 128-byte line, lanes 8k .. 8k+7 of the tile row,
+    // start at their earliest envelope chunk together, so every line is
+    // requested by one load instruction and fetched once)
+    auto start = [&](int I, int& nco, int& c0) {
       const int w = I * TS < s.bo ? I * TS : s.bo;
-      const int nco = w / V;
-      const int c0 = I * TS - w;
-      T acc[NR];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = T(0);
-      // first envelope column of the row (padding rows: the diagonal), and
-      // the first chunk holding a column at or after it
+      nco = w / V;
+      c0 = I * TS - w;
       int fc = first_col(I * TS + r);
-      // the 8 rows of a 128-byte line (lanes 8k .. 8k+7 of the tile row)
-      // start at their earliest chunk together, so every line is requested
-      // by one load instruction and fetched once
       fc = min(fc, __shfl_xor(fc, 1));
       fc = min(fc, __shfl_xor(fc, 2));
       fc = min(fc, __shfl_xor(fc, 4));
       const int cmin = fc > c0 ? (fc - c0) / V : 0;
       int cc = tid / TS;
       if (cc < cmin) cc += (cmin - cc + RPT - 1) / RPT * RPT;
-      // UNR chunk loads in flight per lane, then their products
+      return cc;
+    };
+    auto chunk = [&](int64_t off, int cc) {
+      return reinterpret_cast<const VT*>(P + off + ((int64_t)cc * TS + r) * V);
+    };
+    int64_t off = 0;
+    int nco, c0;
+    int cc0 = start(0, nco, c0);
+    VT Lp[UNR];
+    bool pre = cc0 + (UNR - 1) * RPT < nco;
+    if (pre)
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) Lp[u] = __builtin_nontemporal_load(chunk(off, cc0 + u * RPT));
+    for (int I = 0; I < nb; ++I) {
+      T acc[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[k] = T(0);
+      int cc = cc0;
+      if (pre) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            acc[k] += vdot<VT, V>(Lp[u], *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + (cc + u * RPT) * V));
+        cc += UNR * RPT;
+      }
       for (; cc + (UNR - 1) * RPT < nco; cc += UNR * RPT) {
         VT L[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) L[u] = __builtin_nontemporal_load(reinterpret_cast<const VT*>(P + off + ((int64_t)(cc + u * RPT) * TS + r) * V));
+        for (int u = 0; u < UNR; ++u) L[u] = __builtin_nontemporal_load(chunk(off, cc + u * RPT));
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -183,16 +213,37 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
             acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + (cc + u * RPT) * V));
       }
       for (; cc < nco; cc += RPT) {
-        VT L = *reinterpret_cast<const VT*>(P + off + ((int64_t)cc * TS + r) * V);
+        VT L = *chunk(off, cc);
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           VT y = *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + cc * V);
           acc[k] += vdot<VT, V>(L, y);
         }
       }
+      // the inverse of a lower triangle is lower: lane tid < TS needs the
+      // diagonal chunks dc with dc V <= tid
+      auto diag = [&](int dc) -> VT {
+        return (tid < TS && dc * V <= tid) ? *reinterpret_cast<const VT*>(P + off + ((int64_t)(nco + dc) * TS + tid) * V)
+                                           : VT(T(0));
+      };
+      VT Ld[DIAG_PRE ? TS / V : 1];
+      if (DIAG_PRE && tid < 64)
+#pragma unroll
+        for (int dc = 0; dc < (DIAG_PRE ? TS / V : 1); ++dc) Ld[dc] = diag(dc);
 #pragma unroll
       for (int k = 0; k < NR; ++k) part0[k * NT + tid] = acc[k];
       __syncthreads();
+      // the next block row's first batch
+      const int64_t offn = off + (int64_t)TS * (nco * V + TS);
+      int ncon = 0, c0n = 0, ccn = 0;
+      bool pren = false;
+      if (I + 1 < nb) {
+        ccn = start(I + 1, ncon, c0n);
+        pren = ccn + (UNR - 1) * RPT < ncon;
+        if (pren)
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) Lp[u] = __builtin_nontemporal_load(chunk(offn, ccn + u * RPT));
+      }
       if (tid < 64) {
         T a[NR], y[NR];
 #pragma unroll
@@ -207,65 +258,85 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           }
         }
 #pragma unroll
-        for (int cc = 0; cc < TS / V; ++cc) {
+        for (int dc = 0; dc < TS / V; ++dc) {
           VT L;
-          if (tid < TS && cc * V <= tid)  // the inverse of a lower triangle is lower
-            L = *reinterpret_cast<const VT*>(P + off + ((int64_t)(nco + cc) * TS + tid) * V);
+          if constexpr (DIAG_PRE)
+            L = Ld[dc];
           else
-            L = VT(T(0));
+            L = diag(dc);
 #pragma unroll
           for (int k = 0; k < NR; ++k)
 #pragma unroll
-            for (int v = 0; v < V; ++v) y[k] += L[v] * bcast<T>(a[k], cc * V + v);
+            for (int v = 0; v < V; ++v) y[k] += L[v] * bcast<T>(a[k], dc * V + v);
         }
         if (tid < TS)
 #pragma unroll
           for (int k = 0; k < NR; ++k) xs0[k * VS + I * TS + tid] = y[k];
       }
       __syncthreads();
-      off += (int64_t)TS * (w + TS);
+      off = offn;
+      nco = ncon;
+      c0 = c0n;
+      cc0 = ccn;
+      pre = pren;
     }
   }
 
   // ---- backward substitution L^T z = y (in place) ----
   {
     const T* P = A.Bp + s.panel_off;
-    int64_t off = s.panel_len;
     const int c = tid % TS;
-    for (int I = nb - 1; I >= 0; --I) {
+    const VT* zsrc = reinterpret_cast<const VT*>(g_zero_chunks) + (tid & 63);
+    // block row I: panel offset (blocks are stored in increasing order),
+    // chunk count of the rows below, and this lane's chunk bound: no row of
+    // node q starts before node q - 1 - N0 - N0 N1, so rows past the last
+    // DOF of node col/3 + 1 + N0 + N0 N1 are zero in column col, and so are
+    // the padding rows
+    auto start = [&](int I, int64_t offI1, int64_t& offI, int& nco, int& rend) {
       const int rem = n - (I + 1) * TS;
       const int w = rem < s.bo ? rem : s.bo;
-      off -= (int64_t)TS * (TS + w);
-      const int nco = w / V;
+      offI = offI1 - (int64_t)TS * (TS + w);
+      nco = w / V;
+      const int col = I * TS + c, rbase = (I + 1) * TS;
+      int last = 3 * (col / 3 + 1 + N0 + N0 * N1) + 2;
+      if (last > s.ndof - 1) last = s.ndof - 1;
+      int cnt = last + 1 - rbase;
+      cnt = cnt < 0 ? 0 : (cnt > nco * V ? nco * V : cnt);
+      rend = (cnt + V - 1) / V;
+    };
+    // chunk rr below block row I of this column, or zeros where its rows all
+    // start after the column
+    auto src = [&](int64_t offI, int I, int rr) -> const VT* {
+      const VT* q = reinterpret_cast<const VT*>(P + offI + ((int64_t)(TS / V + rr) * TS + c) * V);
+      return fcr[(I + 1) * TS / V + rr] <= I * TS + c ? q : zsrc;
+    };
+    int64_t off;
+    int nco, rend;
+    start(nb - 1, s.panel_len, off, nco, rend);
+    const int rr0 = tid / TS;
+    VT Lp[UNR];
+    bool pre = rr0 + (UNR - 1) * RPT < rend;
+    if (pre)
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) Lp[u] = __builtin_nontemporal_load(src(off, nb - 1, rr0 + u * RPT));
+    for (int I = nb - 1; I >= 0; --I) {
       const int rbase = (I + 1) * TS;
       T acc[NR];
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[k] = T(0);
-      // rows below the block that can reach column I TS + c: no row of node
-      // q starts before node q - 1 - N0 - N0 N1, so rows past the last DOF of
-      // node col/3 + 1 + N0 + N0 N1 are zero in this column, and so are the
-      // padding rows; rend = the chunks before that row
-      int rend;
-      {
-        const int col = I * TS + c;
-        int last = 3 * (col / 3 + 1 + N0 + N0 * N1) + 2;
-        if (last > s.ndof - 1) last = s.ndof - 1;
-        int cnt = last + 1 - rbase;
-        cnt = cnt < 0 ? 0 : (cnt > nco * V ? nco * V : cnt);
-        rend = (cnt + V - 1) / V;
+      int rr = rr0;
+      if (pre) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            acc[k] += vdot<VT, V>(Lp[u], *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + (rr + u * RPT) * V));
+        rr += UNR * RPT;
       }
-      // chunk rr of this column, or zeros where its rows all start after it
-      const int col = I * TS + c;
-      const VT* zsrc = reinterpret_cast<const VT*>(g_zero_chunks) + (tid & 63);
-      auto src = [&](int rr) -> const VT* {
-        const VT* p = reinterpret_cast<const VT*>(P + off + ((int64_t)(TS / V + rr) * TS + c) * V);
-        return fcr[rbase / V + rr] <= col ? p : zsrc;
-      };
-      int rr = tid / TS;
       for (; rr + (UNR - 1) * RPT < rend; rr += UNR * RPT) {
         VT L[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) L[u] = __builtin_nontemporal_load(src(rr + u * RPT));
+        for (int u = 0; u < UNR; ++u) L[u] = __builtin_nontemporal_load(src(off, I, rr + u * RPT));
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -273,16 +344,38 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
             acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + (rr + u * RPT) * V));
       }
       for (; rr < rend; rr += RPT) {
-        VT L = *src(rr);
+        VT L = *src(off, I, rr);
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
           VT z = *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + rr * V);
           acc[k] += vdot<VT, V>(L, z);
         }
       }
+      // the inverse transpose is upper: lane tid < TS needs the diagonal
+      // chunks dc with dc V + V - 1 >= tid
+      auto diag = [&](int dc) -> VT {
+        return (tid < TS && dc * V + V - 1 >= tid)
+                   ? *reinterpret_cast<const VT*>(P + off + ((int64_t)dc * TS + tid) * V)
+                   : VT(T(0));
+      };
+      VT Ld[DIAG_PRE ? TS / V : 1];
+      if (DIAG_PRE && tid < 64)
+#pragma unroll
+        for (int dc = 0; dc < (DIAG_PRE ? TS / V : 1); ++dc) Ld[dc] = diag(dc);
 #pragma unroll
       for (int k = 0; k < NR; ++k) part0[k * NT + tid] = acc[k];
       __syncthreads();
+      // the next block row's (I - 1) first batch
+      int64_t offn = 0;
+      int ncon = 0, rendn = 0;
+      bool pren = false;
+      if (I > 0) {
+        start(I - 1, off, offn, ncon, rendn);
+        pren = rr0 + (UNR - 1) * RPT < rendn;
+        if (pren)
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) Lp[u] = __builtin_nontemporal_load(src(offn, I - 1, rr0 + u * RPT));
+      }
       if (tid < 64) {
         T a[NR], z[NR];
 #pragma unroll
@@ -297,22 +390,26 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           }
         }
 #pragma unroll
-        for (int rc = 0; rc < TS / V; ++rc) {
+        for (int dc = 0; dc < TS / V; ++dc) {
           VT L;
-          if (tid < TS && rc * V + V - 1 >= tid)  // the inverse transpose is upper
-            L = *reinterpret_cast<const VT*>(P + off + ((int64_t)rc * TS + tid) * V);
+          if constexpr (DIAG_PRE)
+            L = Ld[dc];
           else
-            L = VT(T(0));
+            L = diag(dc);
 #pragma unroll
           for (int k = 0; k < NR; ++k)
 #pragma unroll
-            for (int v = 0; v < V; ++v) z[k] += L[v] * bcast<T>(a[k], rc * V + v);
+            for (int v = 0; v < V; ++v) z[k] += L[v] * bcast<T>(a[k], dc * V + v);
         }
         if (tid < TS)
 #pragma unroll
           for (int k = 0; k < NR; ++k) xs0[k * VS + I * TS + tid] = z[k];
       }
       __syncthreads();
+      off = offn;
+      nco = ncon;
+      rend = rendn;
+      pre = pren;
     }
   }
 
