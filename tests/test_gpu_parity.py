@@ -177,6 +177,27 @@ def test_dual_pcg(name, request, dev):
     assert abs(rep["r_ref"] - ref["r_ref"]) <= 1e-9 * ref["r_ref"]
 
 
+@pytest.mark.parametrize("use_graph,check_every", [(0, 8), (1, 8), (1, 3)])
+def test_dual_pcg_iteration_cap(use_graph, check_every, pair0, dev):
+    """Stopped at max_pcg iterations (at the end of a replayed batch of 8, or
+    inside a batch of 3), lambda and u are the oracle's after the same number
+    of PCGP iterations: the updates folded into the next iteration's first
+    projection are applied before the stopping test ends the loop."""
+    from paper_1205_1926_amd import GpuSolver
+    P = pair0
+    g = GpuSolver(P.w, use_graph=use_graph, check_every=check_every, max_pcg=7, tile=32)
+    g.assemble(T(P.du, dev))
+    g.factorize()
+    f = P.mesh.torn_load(1.0) - P.a["fint"]
+    ref = P.tf.solve(f, eps=1e-8, maxit=7)
+    assert not ref["converged"] and ref["iters"] == 7
+    lam, u, rep, rc = g.dual_pcg(T(f, dev))
+    assert rc == 2 and rep["converged"] == 0 and rep["iters"] == 7
+    assert rel(N(lam), ref["lam"]) <= 1e-9
+    assert rel(N(u), ref["u"]) <= 1e-9
+    g.close()
+
+
 def test_dual_pcg_warm_start_and_rejection(pair0, dev):
     P = pair0
     f = P.mesh.torn_load(1.0)
