@@ -50,19 +50,8 @@ __global__ __launch_bounds__(RB) void gather_kernel(int64_t m, const int64_t* __
   const double beta = fold.S ? fold.S->beta : 0.0;
   double acc = 0.0;
   for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < m; r += (int64_t)gridDim.x * RB) {
-    // the first two entries' loads are issued together (most rows have two)
-    // every row has an entry; the second one's index is clamped so that all
-    // loads are unconditional and in flight together
-    const int64_t e0 = rp[r], e1 = rp[r + 1];
-    const bool h1 = e0 + 1 < e1;
-    const int64_t f1 = h1 ? e0 + 1 : e0;
-    const int32_t i0 = ent[e0], i1 = ent[f1];
-    const double v0 = val[e0], v1 = val[f1];
-    const double x0 = iface[i0], x1 = iface[i1];
-    double q = v0 * x0;
-    const double q2 = q + v1 * x1;
-    q = h1 ? q2 : q;
-    for (int64_t e = e0 + 2; e < e1; ++e) q += val[e] * iface[ent[e]];
+    // every row has an entry; most have two, nearly all at most four
+    const double q = seg_dot<4>(rp[r], rp[r + 1], ent, val, [&](int32_t i) { return iface[i]; });
     out[r] = q;
     if (fold.S) {
       const double pn = fma(beta, fold.p[r], fold.y[r]);
@@ -453,12 +442,10 @@ __global__ __launch_bounds__(LT) void lumped_kernel(DualMaps M, const double* __
   for (int q = threadIdx.x; q < ndof; q += LT) vloc[q] = 0.0;
   __syncthreads();
   for (int t = threadIdx.x; t < nif; t += LT) {
-    // every touched DOF has an entry: the first one's loads are unconditional
+    // every touched DOF has an entry; nearly all have at most four
     const int64_t i = ioff + t;
-    const int32_t e0 = M.if_rp[i], e1 = M.if_rp[i + 1], ld = M.if_ldof[i];
-    double s = M.if_coef[e0] * w[M.if_row[e0]];
-    for (int e = e0 + 1; e < e1; ++e) s += M.if_coef[e] * w[M.if_row[e]];
-    vloc[ld] = s;
+    vloc[M.if_ldof[i]] = seg_dot<4>(M.if_rp[i], M.if_rp[i + 1], M.if_row, M.if_coef,
+                                    [&](int32_t row) { return w[row]; });
   }
   __syncthreads();
   while (g < gend) {

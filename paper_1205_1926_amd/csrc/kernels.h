@@ -74,6 +74,32 @@ __device__ inline void tile_inverse_column(double* d, int ld, int ts, int j, dou
   }
 }
 
+// ---- sparse rows -----------------------------------------------------------
+// sum over e in [e0, e1) of coef[e] * fetch(idx[e]), in order of e (e1 > e0):
+// the first K entries' loads are issued together with clamped indices (every
+// load unconditional, one chain of dependent loads instead of one per entry),
+// the rest one by one.  fetch(i) returns the vector value at index i.
+template <int K, typename E, typename I, typename F>
+__device__ __forceinline__ double seg_dot(E e0, E e1, const I* __restrict__ idx, const double* __restrict__ coef,
+                                          F fetch) {
+  I ii[K];
+  double cc[K], xx[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const E e = e0 + k < e1 ? e0 + k : e1 - 1;
+    ii[k] = idx[e];
+    cc[k] = coef[e];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) xx[k] = fetch(ii[k]);
+  double s = cc[0] * xx[0];
+#pragma unroll
+  for (int k = 1; k < K; ++k)
+    if (e0 + k < e1) s = fma(cc[k], xx[k], s);
+  for (E e = e0 + K; e < e1; ++e) s = fma(coef[e], fetch(idx[e]), s);
+  return s;
+}
+
 // ---- factorization -------------------------------------------------------
 // In-place band Cholesky of every subdomain's row-band matrix (type T).
 // bmax: largest half bandwidth; nb: block columns (0 = largest that fits LDS).

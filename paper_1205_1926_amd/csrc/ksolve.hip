@@ -135,12 +135,10 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
         const double* lam = k == 0 ? A.lam : A.lam2;
-        double bt = 0.0;
-        for (int e = A.if_rp[it]; e < A.if_rp[it + 1]; ++e) {
-          const int32_t row = A.if_row[e];
-          const double lv = (k == 0 && A.fold.S) ? fma(beta, lam[row], A.fold.y[row]) : lam[row];
-          bt += A.if_coef[e] * lv;
-        }
+        const bool fold = k == 0 && A.fold.S;
+        const double bt = seg_dot<4>(A.if_rp[it], A.if_rp[it + 1], A.if_row, A.if_coef, [&](int32_t row) {
+          return fold ? fma(beta, lam[row], A.fold.y[row]) : lam[row];
+        });
         xs0[k * VS + A.if_fidx[it]] = (T)(v + A.lam_sign * bt);
       }
     }
