@@ -44,6 +44,8 @@ void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, co
 
 // Panels (layout in kernels.h): tile rows TS, vector width V = 16 bytes /
 // sizeof(T).  Each workgroup takes block rows of one subdomain.
+constexpr int PB = 8;  // band entries in flight per thread while packing
+
 template <typename TW, typename T, int TS>
 __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                           const int32_t* __restrict__ list,
@@ -95,21 +97,44 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
         B2[offB + ((int64_t)(r / V2) * TS + c) * V2 + (r % V2)] = (float)x;
       }
     }
-    // off-diagonal part of the forward panel: columns I TS - wF .. I TS - 1
-    for (int64_t q = tid; q < (int64_t)TS * wF; q += blockDim.x) {
-      int r = (int)(q % TS), cc = (int)(q / TS);
-      int col = I * TS - wF + cc;
-      const T v = L(I * TS + r, col);
-      F[offF + ((int64_t)(cc / V) * TS + r) * V + (cc % V)] = v;
-      if (F2) F2[offF + ((int64_t)(cc / V2) * TS + r) * V2 + (cc % V2)] = (float)v;
+    // off-diagonal part of the forward panel, columns I TS - wF .. I TS - 1,
+    // and of the backward panel, rows (I+1) TS .. + wB - 1: PB band entries
+    // requested per thread before any is stored, so that the loads overlap
+    // (one at a time, every entry paid a full memory latency)
+    const int nF = TS * wF, nB = TS * wB;
+    for (int q0 = tid; q0 < nF; q0 += PB * (int)blockDim.x) {
+      T v[PB];
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const int q = q0 + u * (int)blockDim.x;
+        v[u] = q < nF ? L(I * TS + q % TS, I * TS - wF + q / TS) : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const int q = q0 + u * (int)blockDim.x;
+        if (q < nF) {
+          const int r = q % TS, cc = q / TS;
+          F[offF + ((int64_t)(cc / V) * TS + r) * V + (cc % V)] = v[u];
+          if (F2) F2[offF + ((int64_t)(cc / V2) * TS + r) * V2 + (cc % V2)] = (float)v[u];
+        }
+      }
     }
-    // off-diagonal part of the backward panel: rows (I+1) TS .. + wB - 1
-    for (int64_t q = tid; q < (int64_t)TS * wB; q += blockDim.x) {
-      int c = (int)(q % TS), rr = (int)(q / TS);
-      int row = (I + 1) * TS + rr;
-      const T v = L(row, I * TS + c);
-      Bk[offB + ((int64_t)((TS + rr) / V) * TS + c) * V + ((TS + rr) % V)] = v;
-      if (B2) B2[offB + ((int64_t)((TS + rr) / V2) * TS + c) * V2 + ((TS + rr) % V2)] = (float)v;
+    for (int q0 = tid; q0 < nB; q0 += PB * (int)blockDim.x) {
+      T v[PB];
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const int q = q0 + u * (int)blockDim.x;
+        v[u] = q < nB ? L((I + 1) * TS + q / TS, I * TS + q % TS) : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const int q = q0 + u * (int)blockDim.x;
+        if (q < nB) {
+          const int c = q % TS, rr = q / TS;
+          Bk[offB + ((int64_t)((TS + rr) / V) * TS + c) * V + ((TS + rr) % V)] = v[u];
+          if (B2) B2[offB + ((int64_t)((TS + rr) / V2) * TS + c) * V2 + ((TS + rr) % V2)] = (float)v[u];
+        }
+      }
     }
     __syncthreads();
   }
