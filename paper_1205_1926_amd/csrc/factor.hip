@@ -1,4 +1,4 @@
-// Factor format conversion, panel packing for the triangular solves, and
+// Band copies, panel packing for the triangular solves, and
 // the dense inverse of the coarse matrix G G^T.
 //
 // Storage: row-band, row r holds columns r-b..r (entry (r, k) is column
@@ -7,22 +7,6 @@
 #include "kernels.h"
 
 namespace tfeti {
-
-template <typename T>
-__global__ void convert_band_kernel(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = (T)src[i];
-}
-
-template <typename T>
-void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st) {
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (n > 0) convert_band_kernel<T><<<dim3((unsigned)blocks), dim3(256), 0, st>>>(src, dst, n);
-}
-template void launch_convert_band<double>(const double*, double*, int64_t, hipStream_t);
-template void launch_convert_band<float>(const double*, float*, int64_t, hipStream_t);
 
 // Copy the row-band matrices of the listed subdomains (zero them if src is
 // NULL): blockIdx.y picks the subdomain, the blockIdx.x slices stride over

@@ -107,9 +107,6 @@ template <typename T>
 int launch_band_cholesky(const SubDev* subs, int64_t nsub, const int32_t* list, T* band, int32_t* fail, int bmax,
                          int nb, hipStream_t st);
 int band_cholesky_nb(int bmax, size_t elem);
-// Convert the FP64 row-band K_reg into the factor work buffer of type T.
-template <typename T>
-void launch_convert_band(const double* src, T* dst, int64_t n, hipStream_t st);
 // Pack the factors into forward (F) and backward (B) panels with inverted
 // diagonal tiles (layout above).
 // (factor in TW, panels in T: FP64 -> FP64 or FP64 -> FP32)
