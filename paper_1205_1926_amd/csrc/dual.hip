@@ -110,7 +110,7 @@ __global__ __launch_bounds__(RB) void g_apply_kernel(DualMaps M, const double* _
   const int32_t e0 = M.if_rp[t0], e1 = M.if_rp[t0 + M.subs[p].n_iface];
   const double hh[3] = {M.hh[0], M.hh[1], M.hh[2]};
   double acc[6] = {0, 0, 0, 0, 0, 0};
-  constexpr int U = 4;
+  constexpr int U = 8;  // entries per thread in flight: one pass covers an 8^3 subdomain's B^T
   for (int32_t eb = e0 + (int32_t)threadIdx.x; eb < e1; eb += U * RB) {
     int32_t row[U];
     uint32_t pk[U];
@@ -484,13 +484,26 @@ template void launch_lumped<float>(const DualMaps&, const double*, const float*,
                                    hipStream_t);
 
 // ---------------------------------------------------------------- reductions
-__global__ __launch_bounds__(RB) void finalize_kernel(int kind, PcgScalars* S, const double* __restrict__ partials,
-                                                      int nparts) {
-  __shared__ double sh[RB];
-  if (kind != FIN_RREF && kind != FIN_SUM_TMP0 && S->done) return;
+// one workgroup of FB threads: the partials (up to 4096) in at most four
+// loads per thread, wavefront shuffles, then the wavefronts' sums in order
+constexpr int FB = 1024;
+__device__ __forceinline__ double final_sum(const double* __restrict__ partials, int n) {
+  __shared__ double sh[FB / 64];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += RB) acc += partials[i];
-  double sum = block_sum(acc, sh);
+  for (int i = threadIdx.x; i < n; i += FB) acc += partials[i];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  double s = sh[0];
+#pragma unroll
+  for (int w = 1; w < FB / 64; ++w) s += sh[w];
+  return s;
+}
+
+__global__ __launch_bounds__(FB) void finalize_kernel(int kind, PcgScalars* S, const double* __restrict__ partials,
+                                                      int nparts) {
+  if (kind != FIN_RREF && kind != FIN_SUM_TMP0 && S->done) return;
+  const double sum = final_sum(partials, nparts);
   if (threadIdx.x != 0) return;
   switch (kind) {
     case FIN_WW: {
@@ -529,19 +542,17 @@ __global__ __launch_bounds__(RB) void finalize_kernel(int kind, PcgScalars* S, c
 }
 
 void launch_finalize(int kind, PcgScalars* S, const double* partials, int nparts, hipStream_t st) {
-  finalize_kernel<<<dim3(1), dim3(RB), 0, st>>>(kind, S, partials, nparts);
+  finalize_kernel<<<dim3(1), dim3(FB), 0, st>>>(kind, S, partials, nparts);
 }
 
-__global__ void sum_partials_kernel(const double* __restrict__ partials, int n, double* __restrict__ out) {
-  __shared__ double sh[RB];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += RB) acc += partials[i];
-  double s = block_sum(acc, sh);
+__global__ __launch_bounds__(FB) void sum_partials_kernel(const double* __restrict__ partials, int n,
+                                                         double* __restrict__ out) {
+  const double s = final_sum(partials, n);
   if (threadIdx.x == 0) *out = s;
 }
 
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st) {
-  sum_partials_kernel<<<dim3(1), dim3(RB), 0, st>>>(partials, n, out);
+  sum_partials_kernel<<<dim3(1), dim3(FB), 0, st>>>(partials, n, out);
 }
 
 // ---------------------------------------------------------------- vector updates
