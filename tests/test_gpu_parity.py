@@ -177,6 +177,24 @@ def test_dual_pcg(name, request, dev):
     assert abs(rep["r_ref"] - ref["r_ref"]) <= 1e-9 * ref["r_ref"]
 
 
+@pytest.mark.parametrize("S,n", [((1, 1, 1), (3, 3, 3)), ((3, 1, 2), (1, 1, 1))],
+                         ids=["single_subdomain", "one_element_subdomains"])
+def test_dual_pcg_degenerate_decompositions(S, n, dev):
+    """Degenerate decompositions: one subdomain (B holds only the Dirichlet
+    rows, G G^T is 6 x 6) and subdomains of a single element (24 DOFs padded
+    to 64 rows, every node touched).  The solve matches the oracle's."""
+    w = W.small_cube(S=S, n=n, amp=500.0, shear=100.0)
+    P = Pair(w, dev, tile=16)
+    f = P.mesh.torn_load(1.0) - P.a["fint"]
+    ref = P.tf.solve(f, eps=1e-8)
+    lam, u, rep, rc = P.g.dual_pcg(T(f, dev))
+    assert rep["converged"] == 1
+    assert abs(rep["iters"] - ref["iters"]) <= 1
+    assert rel(N(u), ref["u"]) <= 1e-6
+    assert rel(N(lam), ref["lam"]) <= 1e-5
+    P.g.close()
+
+
 @pytest.mark.parametrize("use_graph,check_every", [(0, 8), (1, 8), (1, 3)])
 def test_dual_pcg_iteration_cap(use_graph, check_every, pair0, dev):
     """Stopped at max_pcg iterations (at the end of a replayed batch of 8, or
