@@ -138,8 +138,6 @@ void launch_pack_panels(const SubDev* subs, int64_t count, const int32_t* list, 
 }
 template void launch_pack_panels<double, double>(const SubDev*, int64_t, const int32_t*, const double*, double*,
                                                  double*, int, hipStream_t, float*, float*);
-template void launch_pack_panels<double, float>(const SubDev*, int64_t, const int32_t*, const double*, float*,
-                                                float*, int, hipStream_t, float*, float*);
 
 // Dense inverse of the coarse matrix from its banded Cholesky factor L
 // (row-band, l rows, half bandwidth b): thread j solves L L^T x = e_j and

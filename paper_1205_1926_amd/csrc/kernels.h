@@ -109,9 +109,9 @@ int launch_band_cholesky(const SubDev* subs, int64_t nsub, const int32_t* list, 
 int band_cholesky_nb(int bmax, size_t elem);
 // Pack the factors into forward (F) and backward (B) panels with inverted
 // diagonal tiles (layout above).
-// (factor in TW, panels in T: FP64 -> FP64 or FP64 -> FP32)
+// (factor in TW, panels in T; both FP64 in this library); Fq, Bq
+// (optional): FP32 copies of the panels written in the same pass
 template <typename TW, typename T>
-// Fq, Bq (optional): FP32 copies of the panels written in the same pass
 void launch_pack_panels(const SubDev* subs, int64_t count, const int32_t* list, const TW* band, T* Fp, T* Bp, int TS,
                         hipStream_t st, float* Fq = nullptr, float* Bq = nullptr);
 // Dense inverse of the coarse matrix from its banded Cholesky factor.
