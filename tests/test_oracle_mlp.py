@@ -61,3 +61,42 @@ def test_adam_reduces_loss():
         Y, c = mlp.forward(p, X)
         mlp.adam(p, mlp.backward(p, c, Y, T, M), st, lr=1e-2)
     assert mlp.loss(mlp.forward(p, X)[0], T, M) < 0.5 * l0
+
+
+def _two_steps(adam, lr=1e-3, eps=1e-8):
+    """A scalar parameter theta = 0 driven by the gradients +1, then -1."""
+    p = {"w": np.zeros(1)}
+    st = {}
+    adam(p, {"w": np.array([1.0])}, st, lr=lr, b1=0.9, b2=0.999, eps=eps)
+    t1 = p["w"][0]
+    adam(p, {"w": np.array([-1.0])}, st, lr=lr, b1=0.9, b2=0.999, eps=eps)
+    return t1, p["w"][0]
+
+
+def test_adam_closed_form_first_two_steps():
+    """Adam (Kingma and Ba 2015, Algorithm 1) from zero moments.  Step 1: the
+    bias-corrected moments are g and g^2, so theta moves by -lr g/(|g| + eps),
+    i.e. -lr for g = 1.  Step 2 with g = -1: m = 0.9*0.1 - 0.1 = -0.01 and
+    m_hat = -0.01/(1 - 0.81) = -1/19; v = 0.999*0.001 + 0.001 = 0.001999 and
+    v_hat = 0.001999/(1 - 0.998001) = 1, so theta moves by +lr/19.  Variants
+    without the bias correction, or with beta1 and beta2 swapped, move
+    differently and fail the same check."""
+    lr, eps = 1e-3, 1e-8
+    t1, t2 = _two_steps(mlp.adam, lr, eps)
+    assert abs(t1 - (-lr / (1.0 + eps))) <= 1e-15
+    assert abs(t2 - (t1 + lr * (1.0 / 19.0) / (1.0 + eps))) <= 1e-15
+
+    def no_bias_correction(p, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        for k in p:
+            m = state.setdefault("m_" + k, np.zeros_like(p[k]))
+            v = state.setdefault("v_" + k, np.zeros_like(p[k]))
+            m[:] = b1 * m + (1 - b1) * g[k]
+            v[:] = b2 * v + (1 - b2) * g[k] ** 2
+            p[k] -= lr * m / (np.sqrt(v) + eps)
+
+    def swapped_betas(p, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        return mlp.adam(p, g, state, lr=lr, b1=b2, b2=b1, eps=eps)
+
+    for bad in (no_bias_correction, swapped_betas):
+        b1_, b2_ = _two_steps(bad, lr, eps)
+        assert abs(b1_ - t1) > 1e-6 or abs(b2_ - t2) > 1e-6
