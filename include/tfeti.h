@@ -100,7 +100,7 @@ typedef struct {
                                    the first factorization, every tile 16/32/64
                                    with either subdomain order and 256, 512 or
                                    1024 threads per subdomain is timed (median
-                                   of 20 F-applies x 40 + one panel packing) and
+                                   of 20 F-applies x 70 + one panel packing) and
                                    the cheapest is kept;
                                    the choice is cached in the file named by the
                                    environment variable TFETI_AUTOTUNE_CACHE (if
@@ -234,7 +234,10 @@ int tfeti_assemble(tfeti_handle* h, const double* du, double* fint, int64_t* pla
 
 /* Regularize (fixing nodes, Remark 1) and factorize the assembled tangents
  * (of the subdomains that have a plastic Gauss point or whose factor is not
- * of the elastic tangent, unless options.refactor_all). */
+ * of the elastic tangent, unless options.refactor_all).  TFETI_E_NOT_SPD if
+ * a pivot is <= 0 or not finite; the factorized bands are then unusable and
+ * every further call fails the same way until tfeti_assemble (or a Newton
+ * step) forms a new tangent. */
 int tfeti_factorize(tfeti_handle* h);
 
 /* q = F lambda = B K^+ B^T lambda (m -> m, FP64) with the current factors in

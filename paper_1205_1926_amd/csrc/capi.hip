@@ -115,6 +115,10 @@ struct tfeti_handle {
   double dlf = 0.0, df_norm = 0.0;
   int newton_i = 0;
   bool step_active = false, have_lambda = false, factored = false, assembled_at_du = false;
+  // the last factorization met a bad pivot: the band holds neither the
+  // assembled tangent nor a factor of the subdomains it factorized, so every
+  // factorization fails until the next assembly
+  bool fact_failed = false;
   int64_t last_plastic = 0;
   // timing of the F-apply solve kernel
   bool timing = false;
@@ -772,6 +776,7 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   HIPCHK(hipStreamSynchronize(h->st));
   h->last_plastic = (int64_t)cnt;
   h->factored = false;
+  h->fact_failed = false;
   return 0;
 }
 
@@ -920,6 +925,8 @@ int autotune(tfeti_handle* h) {
 // factorized again.
 int factorize(tfeti_handle* h) {
   const HostModel& M = h->M;
+  if (h->fact_failed)
+    return fail(h, TFETI_E_NOT_SPD, "the last factorization met a pivot <= 0; assemble a new tangent first");
   std::vector<int32_t>& list = h->flist;
   list.clear();
   std::vector<int32_t> restore;
@@ -962,7 +969,6 @@ int factorize(tfeti_handle* h) {
       const int64_t nf = (int64_t)fresh.size();
       launch_regularize(h->d_subs, nf, h->d_flist, h->d_QQt, h->d_band, h->st);
       launch_band_cholesky<double>(h->d_subs, nf, h->d_flist, h->d_band, h->d_fail, h->bmax, h->chol_nb, h->st);
-      for (int32_t p : fresh) h->band_factored[p] = 1;
     }
     HIPCHK(hipMemcpyAsync(h->d_flist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
     const int64_t cnt = (int64_t)list.size();
@@ -972,10 +978,15 @@ int factorize(tfeti_handle* h) {
     HIPCHK(hipStreamSynchronize(h->st));
     HIPCHK(hipGetLastError());
     if (bad) {
+      // the bands of the fresh subdomains were overwritten by a failed
+      // factorization: none of them holds a usable factor or tangent
       for (int32_t p : list) h->fact_elastic[p] = 0;
+      for (int32_t p : fresh) h->band_factored[p] = 0;
       h->factored = false;
+      h->fact_failed = true;
       return fail(h, TFETI_E_NOT_SPD, "a subdomain factorization met a pivot <= 0");
     }
+    for (int32_t p : fresh) h->band_factored[p] = 1;
     for (int32_t p : list) h->fact_elastic[p] = h->opt.refactor_all ? 0 : (h->subpl[p] ? 0 : 1);
   }
   h->factored = true;
