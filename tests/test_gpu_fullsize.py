@@ -2,17 +2,16 @@
 configuration bench.py times (FP64 and FP32 panels, autotuned tile, graph
 replay on):
 
+* the 10x10x10-subdomain cube and the uneven 8x8x8-subdomain mesh against
+  the FP64 oracle at full size on the first (elastic) tangent: F-applies
+  entry by entry and load step 1 (displacements and multipliers), FP64 and
+  FP32 panels on the same oracle reference;
 * the 4x4x4-subdomain cube (139 968 torn DOFs): the first load steps against
   the FP64 oracle, displacement bar 1e-6;
-* the uneven 8x8x8-subdomain mesh (512 subdomains of 6..10 elements per
-  axis): a dual solve's properties and the FP32/FP64 agreement;
 * the 10x10x10-subdomain cube (2 187 000 torn DOFs): K^+ on sampled
-  subdomains against the oracle's factor of the same 8^3 subdomain (outputs
-  the oracle can compute one by one), and properties that hold at any size
-  for a whole dual solve: continuity B u = 0 to the solver tolerance, the
-  self-equilibrium R^T (f - B^T lambda) = 0 of every subdomain (the
-  feasibility G lambda = e), and the FP32-panel solve matching the FP64 one
-  at the 1e-6 bar.
+  subdomains against the oracle's factor of the same 8^3 subdomain;
+* both large meshes: properties that hold at any size for a whole dual
+  solve (continuity, subdomain equilibrium, FP32 against FP64).
 """
 
 import numpy as np
@@ -47,8 +46,66 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
 
 
-SOLVED = {}
-UNEVEN = {}
+def emax(a, b):
+    """Largest entry difference relative to the largest entry of b."""
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def _log(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ref_cube10(dev):
+    from oracle import reference
+    return reference.elastic_first_step(W.config(4), log=_log, fapply_seed=17)
+
+
+@pytest.fixture(scope="module")
+def ref_uneven8(dev):
+    from oracle import reference
+    return reference.elastic_first_step(W.config(2), log=_log, fapply_seed=17)
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("which", ["ref_cube10", "ref_uneven8"])
+def test_full_size_fapply_and_first_load_step_match_oracle(which, request, dev):
+    """Full-size oracle parity on the elastic tangent of load step 1.
+
+    F-apply: the cube's subdomains are cubes, whose fixing nodes are the
+    oracle's, so F itself agrees entry by entry (FP64 panels to 1e-9 of the
+    largest entry, FP32 panels to 1e-5); on the uneven mesh the library's
+    factor ordering picks other fixing nodes, and P F agrees on Ker G
+    (Section 4.2).  Load step 1 (one Newton solve, elastic): displacements
+    within 1e-6 and multipliers within 1e-5 of the oracle's, relative 2-norm
+    over untorn DOFs, in both precisions."""
+    from paper_1205_1926_amd import GpuSolver
+    ref = request.getfixturevalue(which)
+    w = W.config(4 if which == "ref_cube10" else 2)
+    tf, idx = ref["tf"], ref["untorn"]
+    cube = which == "ref_cube10"
+    lam = ref["lam_F"] if cube else tf.project(ref["lam_F"])
+    q_ref = ref["F_lam"] if cube else tf.project(tf.F(lam))
+    for precision, tol in (("fp64", 1e-9), ("fp32", 1e-5)):
+        g = GpuSolver(w, use_graph=1, precision=precision)
+        g.begin_load_step()
+        g.assemble(g.zeros(g.sizes["n_torn"]))
+        g.factorize()
+        q = g.fapply(T(lam, dev)).cpu().numpy()
+        e_f = emax(q if cube else tf.project(q), q_ref)
+        g.close()
+        g = GpuSolver(w, use_graph=1, precision=precision)
+        hist = g.load_step()
+        u = g.state()["u"].cpu().numpy()
+        e_u = rel(u[idx], ref["du"][idx])
+        e_l = rel(g.lam().cpu().numpy(), ref["lam"])
+        _log(f"{w.name} {precision}: F entry error {e_f:.2e}, load step 1: {len(hist)} solve(s), "
+             f"PCGP {[r['pcg_iters'] for r in hist]} (oracle {ref['iters']}), u {e_u:.2e}, lambda {e_l:.2e}")
+        g.close()
+        assert e_f <= tol, (precision, e_f)
+        assert len(hist) == 1 and hist[0]["plastic_gp"] == 0
+        assert e_u <= 1e-6, (precision, e_u)
+        assert e_l <= 1e-5, (precision, e_l)
 
 
 @pytest.fixture(scope="module")
@@ -104,61 +161,40 @@ def test_cube10_kplus_on_sampled_subdomains(dev, mesh4):
         s = mesh4.subs[p]
         sl = slice(s.off, s.off + s.n_dofs)
         mask[sl] = True
-        assert rel(y[sl], sla.cho_solve_banded((fac, True), x[sl])) <= 1e-9, p
+        assert emax(y[sl], sla.cho_solve_banded((fac, True), x[sl])) <= 1e-9, p
     assert not np.any(y[~mask])
     g.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_cube10_dual_solve_properties(precision, dev, mesh4):
+@pytest.mark.parametrize("config", [4, 2], ids=["cube10", "uneven8"])
+def test_dual_solve_properties(config, dev):
+    """Properties that hold at any size for a whole dual solve, in both
+    precisions inside one test: continuity B u = 0 to the solver tolerance,
+    the self-equilibrium R^T (f - B^T lambda) = 0 of every subdomain (the
+    feasibility G lambda = e), and the FP32-panel solve within the 1e-6 bar
+    of the FP64 one."""
     from paper_1205_1926_amd import GpuSolver
-    w = W.config(4)
-    g = GpuSolver(w, use_graph=1, precision=precision)
-    n = g.sizes["n_torn"]
-    g.begin_load_step()
-    g.assemble(g.zeros(n))
-    g.factorize()
-    f = mesh4.torn_load(w.load_factor(1))
-    lam, u, rep, rc = g.dual_pcg(T(f, dev))
-    assert rep["converged"] == 1
-    lam, u = lam.cpu().numpy(), u.cpu().numpy()
-    # continuity across the interfaces and the Dirichlet face
-    assert np.linalg.norm(mesh4.B @ u) <= 1e-7 * np.linalg.norm(u)
-    # every subdomain in equilibrium with its interface forces
-    r = f - mesh4.B.T @ lam
-    worst = 0.0
-    for s in mesh4.subs:
-        sl = slice(s.off, s.off + s.n_dofs)
-        worst = max(worst, np.abs(rigid_modes(s).T @ r[sl]).max() / max(np.abs(f[sl]).max(), np.abs(r[sl]).max()))
-    assert worst <= 1e-9
-    g.close()
-    SOLVED[precision] = u
-    if "fp64" in SOLVED and "fp32" in SOLVED:
-        assert rel(SOLVED["fp32"], SOLVED["fp64"]) <= 1e-6
-
-
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_uneven8_dual_solve_properties(precision, dev):
-    from paper_1205_1926_amd import GpuSolver
-    w = W.config(2)
-    mesh = UNEVEN.setdefault("mesh", Mesh(w))
-    g = GpuSolver(w, use_graph=1, precision=precision)
-    n = g.sizes["n_torn"]
-    g.begin_load_step()
-    g.assemble(g.zeros(n))
-    g.factorize()
+    w = W.config(config)
+    mesh = Mesh(w)
     f = mesh.torn_load(w.load_factor(1))
-    lam, u, rep, rc = g.dual_pcg(T(f, dev))
-    assert rep["converged"] == 1
-    lam, u = lam.cpu().numpy(), u.cpu().numpy()
-    assert np.linalg.norm(mesh.B @ u) <= 1e-7 * np.linalg.norm(u)
-    r = f - mesh.B.T @ lam
-    worst = 0.0
-    for s in mesh.subs:
-        sl = slice(s.off, s.off + s.n_dofs)
-        worst = max(worst, np.abs(rigid_modes(s).T @ r[sl]).max() / max(np.abs(f[sl]).max(), np.abs(r[sl]).max()))
-    assert worst <= 1e-9
-    g.close()
-    UNEVEN[precision] = u
-    if "fp64" in UNEVEN and "fp32" in UNEVEN:
-        assert rel(UNEVEN["fp32"], UNEVEN["fp64"]) <= 1e-6
+    us = {}
+    for precision in ("fp64", "fp32"):
+        g = GpuSolver(w, use_graph=1, precision=precision)
+        n = g.sizes["n_torn"]
+        g.begin_load_step()
+        g.assemble(g.zeros(n))
+        g.factorize()
+        lam, u, rep, rc = g.dual_pcg(T(f, dev))
+        g.close()
+        assert rep["converged"] == 1
+        lam, u = lam.cpu().numpy(), u.cpu().numpy()
+        assert np.linalg.norm(mesh.B @ u) <= 1e-7 * np.linalg.norm(u)
+        r = f - mesh.B.T @ lam
+        worst = 0.0
+        for s in mesh.subs:
+            sl = slice(s.off, s.off + s.n_dofs)
+            worst = max(worst, np.abs(rigid_modes(s).T @ r[sl]).max() / max(np.abs(f[sl]).max(),
+                                                                              np.abs(r[sl]).max()))
+        assert worst <= 1e-9, precision
+        us[precision] = u
+    assert rel(us["fp32"], us["fp64"]) <= 1e-6

@@ -6,7 +6,11 @@ conditioning of each stage: the return map and assembly are well conditioned
 (1e-12); the regularized subdomain matrices have condition numbers of 1e4-1e5
 on these meshes, so K^+ and F agree to ~1e-11 and are tested at 1e-9; PCGP
 results agree to the solver tolerance and are tested at the 1e-6 displacement
-bar.  FP32 factors (unit roundoff 6e-8) are tested at 5e-3 for single F-applies.
+bar.  Operators (K^+, F, P, the preconditioner) are compared entry by entry:
+the largest entry difference relative to the largest entry of the oracle's
+result.  FP32 panels of the FP64 factor (unit roundoff 6e-8 per entry,
+amplified by the subdomain condition numbers) give F-applies within about
+1e-6 of FP64; they are tested at 1e-5.
 """
 
 import numpy as np
@@ -42,6 +46,12 @@ def N(t):
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def emax(a, b):
+    """Largest entry difference relative to the largest entry of b."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 # ---------------------------------------------------------------- return map
@@ -118,7 +128,7 @@ def pair_uneven(dev):
 @pytest.mark.parametrize("name", ["pair0", "pair_plastic", "pair_uneven"])
 def test_assembly_internal_force(name, request, dev):
     P = request.getfixturevalue(name)
-    assert rel(N(P.fint_g), P.a["fint"]) <= 1e-12
+    assert emax(N(P.fint_g), P.a["fint"]) <= 1e-12
     st = P.g.state()
     pl_g = N(st["plastic"]).astype(bool)
     away = np.abs(P.a["phi"].ravel()) > 1e-10 * P.w.material.sigma_y
@@ -133,9 +143,9 @@ def test_kplus_and_fapply(name, request, dev):
     P = request.getfixturevalue(name)
     rng = np.random.default_rng(3)
     x = rng.standard_normal(P.mesh.n_torn)
-    assert rel(N(P.g.kplus(T(x, dev))), P.tf.kplus(x)) <= 1e-9
+    assert emax(N(P.g.kplus(T(x, dev))), P.tf.kplus(x)) <= 1e-9
     lam = rng.standard_normal(P.mesh.m)
-    assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-9
+    assert emax(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-9
 
 
 @pytest.mark.parametrize("name", ["pair0", "pair_plastic", "pair_uneven"])
@@ -149,10 +159,10 @@ def test_kplus_and_fapply_invariant_parts(name, request, dev):
     R = P.tf.Rmat
     off = lambda v: v - R @ (R.T @ v)
     zg = N(P.g.kplus(T(x, dev)))
-    assert rel(off(zg), off(P.tf.kplus(x))) <= 1e-9
-    assert rel(P.tf.K @ zg, x) <= 1e-9
+    assert emax(off(zg), off(P.tf.kplus(x))) <= 1e-9
+    assert emax(P.tf.K @ zg, x) <= 1e-9
     lam = P.tf.project(rng.standard_normal(P.mesh.m))
-    assert rel(P.tf.project(N(P.g.fapply(T(lam, dev)))), P.tf.project(P.tf.F(lam))) <= 1e-9
+    assert emax(P.tf.project(N(P.g.fapply(T(lam, dev)))), P.tf.project(P.tf.F(lam))) <= 1e-9
 
 
 @pytest.mark.parametrize("name", ["pair0", "pair_plastic", "pair_uneven"])
@@ -160,8 +170,8 @@ def test_projector_and_preconditioner(name, request, dev):
     P = request.getfixturevalue(name)
     rng = np.random.default_rng(4)
     w = rng.standard_normal(P.mesh.m)
-    assert rel(N(P.g.project(T(w, dev))), P.tf.project(w)) <= 1e-12
-    assert rel(N(P.g.precondition(T(w, dev))), P.tf.precondition(w)) <= 1e-12
+    assert emax(N(P.g.project(T(w, dev))), P.tf.project(w)) <= 1e-12
+    assert emax(N(P.g.precondition(T(w, dev))), P.tf.precondition(w)) <= 1e-12
 
 
 @pytest.mark.parametrize("name", ["pair0", "pair_plastic", "pair_uneven"])
@@ -229,12 +239,28 @@ def test_dual_pcg_warm_start_and_rejection(pair0, dev):
     assert rel(N(u), ref["u"]) <= 1e-6
 
 
-def test_fp32_fapply(dev):
-    """FP32 panels of the FP64 factor: single F-applies agree to FP32 level."""
-    P = Pair(W.config(0), dev, precision="fp32")
+@pytest.mark.parametrize("name", ["pair0", "pair_plastic", "pair_uneven"])
+def test_fp32_fapply(name, request, dev):
+    """FP32 panels of the FP64 factor: single F-applies and K^+ solves agree
+    entry by entry with the oracle's and with the FP64 panels of the same
+    factor (an FP64-mode handle on the same tangent) to FP32 level."""
+    P64 = request.getfixturevalue(name)
+    P = Pair(P64.w, dev, precision="fp32", plastic_step=(name == "pair_plastic"))
     rng = np.random.default_rng(5)
     lam = rng.standard_normal(P.mesh.m)
-    assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 5e-3
+    q32 = N(P.g.fapply(T(lam, dev)))
+    q64 = N(P64.g.fapply(T(lam, dev)))
+    if name != "pair_uneven":
+        # cubes: the oracle's fixing nodes, so F itself agrees
+        assert emax(q32, P.tf.F(lam)) <= 1e-5
+    else:
+        # other fixing nodes: P F agrees on Ker G (Section 4.2)
+        lk = P.tf.project(lam)
+        assert emax(P.tf.project(N(P.g.fapply(T(lk, dev)))), P.tf.project(P.tf.F(lk))) <= 1e-5
+    assert emax(q32, q64) <= 1e-5
+    x = rng.standard_normal(P.mesh.n_torn)
+    assert emax(N(P.g.kplus(T(x, dev))), N(P64.g.kplus(T(x, dev)))) <= 1e-5
+    P.g.close()
 
 
 @pytest.mark.parametrize("name", ["pair0", "pair_plastic", "pair_uneven"])
@@ -298,6 +324,7 @@ def test_newton_fp32_mode_matches_oracle(dev):
 
 @pytest.mark.parametrize("tile,n,precision", [(16, (3, 4, 5), "fp64"), (32, (3, 4, 5), "fp64"),
                                               (64, (3, 4, 5), "fp64"), (16, (10, 10, 10), "fp64"),
+                                              (16, (3, 4, 5), "fp32"), (64, (3, 4, 5), "fp32"),
                                               (32, (10, 10, 10), "fp32")])
 def test_other_tiles(tile, n, precision, dev):
     """Tiles 16 and 32 have their panels written by the factorization
@@ -307,8 +334,8 @@ def test_other_tiles(tile, n, precision, dev):
              precision=precision)
     rng = np.random.default_rng(6)
     lam = rng.standard_normal(P.mesh.m)
-    tol = 1e-9 if precision == "fp64" else 1e-4
-    assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= tol
+    tol = 1e-9 if precision == "fp64" else 1e-5
+    assert emax(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= tol
     if precision == "fp32":
         # the outer refinement runs on the FP64 panels written alongside
         f = P.mesh.torn_load(1.0) - P.a["fint"]
@@ -329,7 +356,7 @@ def test_autotuner_choice_and_cache(tmp_path, monkeypatch, dev):
     assert sz["autotuned"] == 1 and sz["tile"] in (16, 32, 64) and sz["schedule"] in (0, 1)
     rng = np.random.default_rng(12)
     lam = rng.standard_normal(P.mesh.m)
-    assert rel(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-9
+    assert emax(N(P.g.fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-9
     lines = cache.read_text().splitlines()
     assert len(lines) == 1 and '"tile": %d' % sz["tile"] in lines[0]
     Q = Pair(W.config(0), dev, tile=0)
