@@ -1,5 +1,5 @@
-"""TFETI dual solver: rigid modes, generalized inverse, projector, lumped
-preconditioner and the projected preconditioned CG (Algorithm 3).
+"""TFETI dual solver: rigid modes, generalized inverse, projector, lumped and
+Dirichlet preconditioners and the projected preconditioned CG (Algorithm 3).
 
 Oracle (test infrastructure), float64, plain numpy/scipy.
 
@@ -138,10 +138,56 @@ class TFETI:
         """Lumped preconditioner B K B^T w (Section 4.2) with the unregularized K."""
         return self.B @ (self.K @ (self.Bt @ w))
 
+    # ---------------------------------------------------- Dirichlet preconditioner
+    def boundary_dofs(self, p: int) -> np.ndarray:
+        """Local DOFs of subdomain p's boundary nodes: every DOF of a node that
+        carries a gluing or Dirichlet row of B (Section 4.2: the nodes with
+        imposed Dirichlet and gluing conditions).  The others are interior."""
+        sub = self.mesh.subs[p]
+        cols = self.B.indices[(self.B.indices >= sub.off) & (self.B.indices < sub.off + sub.n_dofs)] - sub.off
+        nodes = np.unique(cols // 3)
+        return (3 * nodes[:, None] + np.arange(3)[None, :]).ravel()
+
+    def schur_complements(self):
+        """Dense Schur complements S_p = K_bb - K_bi K_ii^{-1} K_ib of the
+        unregularized subdomain tangents onto their boundary DOFs."""
+        out = []
+        for p, sub in enumerate(self.mesh.subs):
+            sl = slice(sub.off, sub.off + sub.n_dofs)
+            Kp = self.K[sl, sl].toarray()
+            b = self.boundary_dofs(p)
+            i = np.setdiff1d(np.arange(sub.n_dofs), b)
+            S = Kp[np.ix_(b, b)]
+            if len(i):
+                S = S - Kp[np.ix_(b, i)] @ np.linalg.solve(Kp[np.ix_(i, i)], Kp[np.ix_(i, b)])
+            out.append((b, S))
+        return out
+
+    def precondition_dirichlet(self, w: np.ndarray) -> np.ndarray:
+        """Dirichlet preconditioner Bbar Sbar Bbar^T w (Section 4.2): B^T w
+        restricted to the boundary DOFs of each subdomain, multiplied by that
+        subdomain's Schur complement, and gathered by B."""
+        if getattr(self, "_schur_of", None) is not self.K:
+            self._schur = self.schur_complements()
+            self._schur_of = self.K
+        x = self.Bt @ w
+        y = np.zeros_like(x)
+        for sub, (b, S) in zip(self.mesh.subs, self._schur):
+            y[sub.off + b] = S @ x[sub.off + b]
+        return self.B @ y
+
     # ------------------------------------------------------------- Algorithm 3
     def solve(self, f: np.ndarray, eps: float = 1e-8, maxit: int = 5000,
-              lam_guess: np.ndarray | None = None, precond: bool = True,
+              lam_guess: np.ndarray | None = None, precond=True,
               record: bool = False):
+        """Algorithm 3.  precond: True or "lumped" (B K B^T), "dirichlet"
+        (Bbar Sbar Bbar^T), False or None (no preconditioner)."""
+        if precond is True or precond == "lumped":
+            apply_prec = self.precondition
+        elif precond == "dirichlet":
+            apply_prec = self.precondition_dirichlet
+        else:
+            apply_prec = None
         Rtf = self.Rmat.T @ f                                   # = -e
         lam_im = self.Gt @ self.coarse(Rtf)                     # N^T H e
         d = self.B @ self.kplus(f)
@@ -167,7 +213,7 @@ class TFETI:
                 break
             if it >= maxit:
                 break
-            z = self.precondition(w) if precond else w
+            z = apply_prec(w) if apply_prec else w
             y = self.project(z)
             yw = y @ w
             if p is None:
