@@ -82,7 +82,13 @@ typedef struct {
                                    and return map                               */
 typedef struct {
   int32_t precision;            /* TFETI_PREC_*                                 */
-  int32_t preconditioner;       /* 0 none, 1 lumped B K B^T (Section 4.2)       */
+  int32_t preconditioner;       /* 0 none, 1 lumped B K B^T, 2 Dirichlet
+                                   Bbar Sbar Bbar^T (Section 4.2): Sbar the Schur
+                                   complement of the unregularized tangent onto
+                                   the DOFs of the nodes carrying rows of B,
+                                   applied through banded Cholesky factors of
+                                   the interior blocks K_ii (FP64; the interior
+                                   nodes of a box subdomain form a box)         */
   double eps_pcg;               /* PCGP relative tolerance                      */
   double eps_newton;            /* Newton relative-residual tolerance           */
   int32_t max_pcg;              /* PCGP iteration cap (default 5000)            */
@@ -250,7 +256,10 @@ int tfeti_kplus(tfeti_handle* h, const double* x, double* y);
 /* out = P w = w - G^T (G G^T)^{-1} G w (m -> m, FP64). */
 int tfeti_project(tfeti_handle* h, const double* w, double* out);
 
-/* out = B K B^T w with the unregularized tangent (lumped preconditioner). */
+/* out = the handle's preconditioner applied to w (m -> m, FP64): B K B^T w
+ * with the unregularized tangent (lumped), or Bbar Sbar Bbar^T w
+ * (Dirichlet, options.preconditioner = 2; needs a factorization).  With
+ * preconditioner 0 the lumped product. */
 int tfeti_precondition(tfeti_handle* h, const double* w, double* out);
 
 /* State access: sigma (n_gp*6), kappa (n_gp), u (n_torn), du (n_torn),

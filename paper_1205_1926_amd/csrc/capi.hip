@@ -127,6 +127,22 @@ struct tfeti_handle {
   std::vector<hipEvent_t> ev;   // pairs (start, stop) around F-apply solve kernels
   int ev_used = 0;
   int last_f64 = 0;             // FP64 F-applies of the last solve
+  // Dirichlet preconditioner (options.preconditioner = 2): band and panels
+  // of the interior problems (FP64), kept elastic interior factors, coupling
+  // values in the precision of K_bb, interior vectors
+  bool dirichlet = false;
+  std::vector<uint8_t> has_int;                 // subdomain has interior DOFs
+  std::vector<int32_t> ilist_keep[4];           // host copies of the uploaded interior lists
+  SubDev* d_isubs = nullptr;
+  int32_t* d_ilo = nullptr;
+  int32_t *d_iorder = nullptr, *d_ilist_a = nullptr, *d_ilist_f = nullptr, *d_ilist_p = nullptr,
+          *d_ilist_r = nullptr;
+  int64_t n_iorder = 0, ipanel_alloc = 0;
+  int ipad_max = 0, ibmax = 0;
+  double *d_iband = nullptr, *d_eiband = nullptr, *d_iF = nullptr, *d_iB = nullptr;
+  double *d_xint = nullptr, *d_sint = nullptr;
+  NbGroups kit{}, kti{};
+  void *d_kit_val = nullptr, *d_kti_val = nullptr, *d_ekit = nullptr, *d_ekti = nullptr;
   // graph replay of the PCGP iteration batch
   hipStream_t gs = nullptr;     // internal stream for graph capture and replay
   hipEvent_t sync_ev = nullptr;
@@ -285,15 +301,64 @@ void project(tfeti_handle* h, const double* x, double* out, double* partials, co
   launch_gt_apply(h->dm, x, h->d_a, 1.0, out, partials, done, h->st, dotv, fold);
 }
 
+
+int nred(tfeti_handle* h) { return reduction_blocks(h->M.m); }
+
+// ------------------------------------------------------------------ Dirichlet preconditioner
+// The entries of list whose subdomain has interior DOFs, uploaded to dst
+// (stream-ordered; the host vector `keep` must live until the stream syncs).
+int64_t interior_list(tfeti_handle* h, const int32_t* list, int64_t count, std::vector<int32_t>& keep,
+                      int32_t* dst) {
+  keep.clear();
+  for (int64_t q = 0; q < count; ++q) {
+    const int32_t p = list ? list[q] : (int32_t)q;
+    if (h->has_int[p]) keep.push_back(p);
+  }
+  if (!keep.empty())
+    (void)hipMemcpyAsync(dst, keep.data(), keep.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st);
+  return (int64_t)keep.size();
+}
+
+void pack_interior(tfeti_handle* h, int64_t count, const int32_t* list, const double* band) {
+  launch_pack_panels<double, double>(h->d_isubs, count, list, band, h->d_iF, h->d_iB, h->TS, h->st);
+}
+
+template <typename TV>
+void dirichlet_apply(tfeti_handle* h, const double* w, const TV* kbb, double* z, const int32_t* done) {
+  launch_dirichlet_a<TV>(h->dm, h->kit, w, kbb, (const TV*)h->d_kit_val, h->d_iface, h->d_xint, done, h->st);
+  if (h->n_iorder > 0) {
+    KsolveArgs<double> a{};
+    a.subs = h->d_isubs;
+    a.order = h->d_iorder;
+    a.nsub = h->n_iorder;
+    a.Fp = h->d_iF;
+    a.Bp = h->d_iB;
+    a.in_full = h->d_xint;
+    a.out_full = h->d_sint;
+    a.done = done;
+    launch_ksolve<double>(a, h->TS, h->nt, h->ipad_max, h->st);
+    launch_dirichlet_c<TV>(h->dm, h->kti, h->d_isubs, h->d_ilo, h->d_sint, (const TV*)h->d_kti_val, h->d_iface, done,
+                           h->st);
+  }
+  launch_gather(h->dm, h->d_iface, z, nullptr, nullptr, done, h->st);
+}
+
+// z = Bbar^T-side preconditioner applied to w: lumped B K B^T w, or the
+// Dirichlet Bbar Sbar Bbar^T w (Section 4.2)
 void precondition(tfeti_handle* h, const double* w, double* z, const int32_t* done) {
+  if (h->dirichlet) {
+    if (h->prec == TFETI_PREC_FP64)
+      dirichlet_apply<double>(h, w, h->d_kbb_val, z, done);
+    else
+      dirichlet_apply<float>(h, w, h->d_kbb_val32, z, done);
+    return;
+  }
   if (h->prec == TFETI_PREC_FP64)
     launch_lumped<double>(h->dm, w, h->d_kbb_val, h->d_iface, done, h->st);
   else
     launch_lumped<float>(h->dm, w, h->d_kbb_val32, h->d_iface, done, h->st);
   launch_gather(h->dm, h->d_iface, z, nullptr, nullptr, done, h->st);
 }
-
-int nred(tfeti_handle* h) { return reduction_blocks(h->M.m); }
 
 // ------------------------------------------------------------------ PCGP
 // One PCGP iteration (Algorithm 3 loop body) on r, lambda_Ker, p with the
@@ -313,7 +378,7 @@ void enqueue_iteration_a(tfeti_handle* h, const int32_t* done) {
   project(h, h->d_r, h->d_w, h->d_partials, done, nullptr, fold_residual(h));
   launch_finalize(FIN_WW, h->d_S, h->d_partials, nred(h), h->st);
   // y = P z with the partial sums of y.w from the same pass
-  if (h->opt.preconditioner == 1) {
+  if (h->opt.preconditioner >= 1) {
     precondition(h, h->d_w, h->d_z, done);
     project(h, h->d_z, h->d_y, h->d_partials, done, h->d_w);
   } else {
@@ -762,6 +827,18 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
       launch_gather_kbb<double>(h->dm, h->d_band, h->d_need, h->d_kbb_val, h->st);
     else
       launch_gather_kbb<float>(h->dm, h->d_band, h->d_need, h->d_kbb_val32, h->st);
+    // so does the Dirichlet preconditioner: K_ii, K_it, K_ti
+    if (h->dirichlet) {
+      const int64_t ni = interior_list(h, alist.data(), na, h->ilist_keep[0], h->d_ilist_a);
+      launch_gather_interior_band(h->d_subs, h->d_isubs, h->d_ilo, ni, h->d_ilist_a, h->d_band, h->d_iband, h->st);
+      if (h->prec == TFETI_PREC_FP64) {
+        launch_gather_groups<double>(h->kit, h->d_subs, h->d_band, h->d_need, (double*)h->d_kit_val, h->st);
+        launch_gather_groups<double>(h->kti, h->d_subs, h->d_band, h->d_need, (double*)h->d_kti_val, h->st);
+      } else {
+        launch_gather_groups<float>(h->kit, h->d_subs, h->d_band, h->d_need, (float*)h->d_kit_val, h->st);
+        launch_gather_groups<float>(h->kti, h->d_subs, h->d_band, h->d_need, (float*)h->d_kti_val, h->st);
+      }
+    }
   }
   if (!rlist.empty()) {
     HIPCHK(hipMemcpyAsync(h->d_rlist, rlist.data(), rlist.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
@@ -770,6 +847,15 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
       launch_copy_kbb<double>(h->dm, nr, h->d_rlist, h->d_ekbb, h->d_kbb_val, h->st);
     else
       launch_copy_kbb<float>(h->dm, nr, h->d_rlist, h->d_ekbb32, h->d_kbb_val32, h->st);
+    if (h->dirichlet) {
+      if (h->prec == TFETI_PREC_FP64) {
+        launch_copy_groups<double>(h->kit, nr, h->d_rlist, (const double*)h->d_ekit, (double*)h->d_kit_val, h->st);
+        launch_copy_groups<double>(h->kti, nr, h->d_rlist, (const double*)h->d_ekti, (double*)h->d_kti_val, h->st);
+      } else {
+        launch_copy_groups<float>(h->kit, nr, h->d_rlist, (const float*)h->d_ekit, (float*)h->d_kit_val, h->st);
+        launch_copy_groups<float>(h->kti, nr, h->d_rlist, (const float*)h->d_ekti, (float*)h->d_kti_val, h->st);
+      }
+    }
   }
   unsigned long long cnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
@@ -819,6 +905,13 @@ int retile(tfeti_handle* h, int TS, int natural, int threads) {
   HIPCHK(hipMemcpyAsync(h->d_subs, M.subs.data(), M.subs.size() * sizeof(SubDev), hipMemcpyHostToDevice, h->st));
   HIPCHK(hipMemcpyAsync(h->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
   pack(h, M.n_sub, nullptr);
+  if (h->dirichlet) {
+    if (assign_interior_panels(M, TS) > h->ipanel_alloc)
+      return fail(h, TFETI_E_INVALID, "internal: interior panel storage too small for the tile");
+    HIPCHK(hipMemcpyAsync(h->d_isubs, M.isubs.data(), M.isubs.size() * sizeof(SubDev), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (h->n_iorder > 0) pack_interior(h, h->n_iorder, h->d_iorder, h->d_iband);
+  }
   HIPCHK(hipStreamSynchronize(h->st));
   HIPCHK(hipGetLastError());
   return 0;
@@ -949,6 +1042,10 @@ int factorize(tfeti_handle* h) {
     HIPCHK(hipMemcpyAsync(h->d_rlist, restore.data(), restore.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           h->st));
     pack(h, (int64_t)restore.size(), h->d_rlist, h->d_eband);
+    if (h->dirichlet) {
+      const int64_t ni = interior_list(h, restore.data(), (int64_t)restore.size(), h->ilist_keep[1], h->d_ilist_r);
+      pack_interior(h, ni, h->d_ilist_r, h->d_eiband);
+    }
     for (int32_t p : restore) {
       h->fact_elastic[p] = 1;
       h->band_factored[p] = 0;
@@ -969,10 +1066,19 @@ int factorize(tfeti_handle* h) {
       const int64_t nf = (int64_t)fresh.size();
       launch_regularize(h->d_subs, nf, h->d_flist, h->d_QQt, h->d_band, h->st);
       launch_band_cholesky<double>(h->d_subs, nf, h->d_flist, h->d_band, h->d_fail, h->bmax, h->chol_nb, h->st);
+      if (h->dirichlet) {
+        const int64_t ni = interior_list(h, fresh.data(), nf, h->ilist_keep[2], h->d_ilist_f);
+        if (ni > 0)
+          launch_band_cholesky<double>(h->d_isubs, ni, h->d_ilist_f, h->d_iband, h->d_fail, h->ibmax, 0, h->st);
+      }
     }
     HIPCHK(hipMemcpyAsync(h->d_flist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
     const int64_t cnt = (int64_t)list.size();
     pack(h, cnt, h->d_flist);
+    if (h->dirichlet) {
+      const int64_t ni = interior_list(h, list.data(), cnt, h->ilist_keep[3], h->d_ilist_p);
+      pack_interior(h, ni, h->d_ilist_p, h->d_iband);
+    }
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
@@ -1006,6 +1112,13 @@ int factorize(tfeti_handle* h) {
       HIPCHK(hipMemcpyAsync(h->d_ekbb, h->d_kbb_val, nk * sizeof(double), hipMemcpyDeviceToDevice, h->st));
     else
       HIPCHK(hipMemcpyAsync(h->d_ekbb32, h->d_kbb_val32, nk * sizeof(float), hipMemcpyDeviceToDevice, h->st));
+    if (h->dirichlet) {
+      const size_t vb = h->prec == TFETI_PREC_FP64 ? sizeof(double) : sizeof(float);
+      HIPCHK(hipMemcpyAsync(h->d_eiband, h->d_iband, (size_t)M.iband_entries * sizeof(double),
+                            hipMemcpyDeviceToDevice, h->st));
+      HIPCHK(hipMemcpyAsync(h->d_ekit, h->d_kit_val, (size_t)M.kit.goff.back() * vb, hipMemcpyDeviceToDevice, h->st));
+      HIPCHK(hipMemcpyAsync(h->d_ekti, h->d_kti_val, (size_t)M.kti.goff.back() * vb, hipMemcpyDeviceToDevice, h->st));
+    }
     h->e_valid = true;
   }
   return 0;
@@ -1119,6 +1232,64 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
       RC(dalloc(h, &h->d_ekbb, M.kbb_goff.back()));
     else
       RC(dalloc(h, &h->d_ekbb32, M.kbb_goff.back()));
+  }
+  if (h->opt.preconditioner < 0 || h->opt.preconditioner > 2)
+    return fail(h, TFETI_E_INVALID, "preconditioner must be 0 (none), 1 (lumped) or 2 (Dirichlet)");
+  h->dirichlet = h->opt.preconditioner == 2;
+  if (h->dirichlet) {
+    // interior problems: panels for the largest layout among the tiles in
+    // use (assign_interior_panels leaves the current tile's layout set)
+    h->ipanel_alloc = 0;
+    if (h->tune_pending)
+      for (int T : {16, 32, 64}) h->ipanel_alloc = std::max(h->ipanel_alloc, assign_interior_panels(M, T));
+    h->ipanel_alloc = std::max(h->ipanel_alloc, assign_interior_panels(M, TS));
+    h->has_int.assign(M.n_sub, 0);
+    std::vector<int32_t> iorder;
+    for (int64_t p = 0; p < M.n_sub; ++p)
+      if (M.isubs[p].ndof > 0) {
+        h->has_int[p] = 1;
+        iorder.push_back((int32_t)p);
+        h->ipad_max = std::max(h->ipad_max, M.isubs[p].npad);
+        h->ibmax = std::max(h->ibmax, M.isubs[p].b);
+      }
+    std::stable_sort(iorder.begin(), iorder.end(),
+                     [&](int32_t a, int32_t b) { return M.isubs[a].npad > M.isubs[b].npad; });
+    h->n_iorder = (int64_t)iorder.size();
+    RC(upload(h, &h->d_isubs, M.isubs));
+    RC(upload(h, &h->d_ilo, M.ilo));
+    RC(upload(h, &h->d_iorder, iorder));
+    for (int32_t** l : {&h->d_ilist_a, &h->d_ilist_f, &h->d_ilist_p, &h->d_ilist_r}) RC(dalloc(h, l, M.n_sub));
+    RC(dalloc(h, &h->d_iband, M.iband_entries));
+    if (!h->opt.refactor_all) RC(dalloc(h, &h->d_eiband, M.iband_entries));
+    RC(dalloc(h, &h->d_iF, h->ipanel_alloc));
+    RC(dalloc(h, &h->d_iB, h->ipanel_alloc));
+    RC(dalloc(h, &h->d_xint, M.n_int));
+    RC(dalloc(h, &h->d_sint, M.n_int));
+    auto groups = [&](const NbGroupsHost& G, NbGroups& D) -> int {
+      int32_t *out = nullptr, *ld = nullptr, *gnb = nullptr, *gsub = nullptr, *g0 = nullptr;
+      uint32_t* mask = nullptr;
+      int64_t* goff = nullptr;
+      RC(upload(h, &out, G.out));
+      RC(upload(h, &ld, G.ldof));
+      RC(upload(h, &mask, G.mask));
+      RC(upload(h, &goff, G.goff));
+      RC(upload(h, &gnb, G.gnb));
+      RC(upload(h, &gsub, G.gsub));
+      RC(upload(h, &g0, G.g0));
+      D = NbGroups{out, ld, mask, goff, gnb, gsub, g0, (int64_t)G.gnb.size()};
+      return 0;
+    };
+    RC(groups(M.kit, h->kit));
+    RC(groups(M.kti, h->kti));
+    for (void** v : {&h->d_kit_val, &h->d_ekit, &h->d_kti_val, &h->d_ekti}) {
+      const bool elastic = v == &h->d_ekit || v == &h->d_ekti;
+      if (elastic && h->opt.refactor_all) continue;
+      const int64_t n = (v == &h->d_kit_val || v == &h->d_ekit) ? M.kit.goff.back() : M.kti.goff.back();
+      if (h->prec == TFETI_PREC_FP64)
+        RC(dalloc(h, (double**)v, n));
+      else
+        RC(dalloc(h, (float**)v, n));
+    }
   }
   RC(upload(h, &h->d_g_first, M.g_first));
   RC(upload(h, &h->d_g_rp, M.g_rp));
@@ -1564,6 +1735,8 @@ int tfeti_project(tfeti_handle* h, const double* w, double* out) {
 
 int tfeti_precondition(tfeti_handle* h, const double* w, double* out) {
   if (!h || !w || !out) return TFETI_E_INVALID;
+  if (h->dirichlet && !h->factored)
+    return fail(h, TFETI_E_INVALID, "the Dirichlet preconditioner needs factorized interior problems");
   precondition(h, w, out, nullptr);
   HIPCHK(hipGetLastError());
   return TFETI_OK;

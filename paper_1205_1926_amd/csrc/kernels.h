@@ -210,6 +210,36 @@ template <typename TV>
 void launch_lumped(const DualMaps& M, const double* w, const TV* kbb_val, double* iface_out,
                    const int32_t* done, hipStream_t st);
 
+// ---- Dirichlet preconditioner (dirichlet.hip) -------------------------------
+// Sparse rows in wavefront groups of 64 (layout of NbGroupsHost in model.h).
+struct NbGroups {
+  const int32_t* out;          // output index of each lane slot, -1 past the end
+  const int32_t* ldof;         // local natural DOF of the slot's row
+  const uint32_t* mask;        // column nodes among the 27 around the row's node
+  const int64_t* goff;         // value offset of each group
+  const int32_t* gnb;          // neighbour blocks of each group
+  const int32_t* gsub;         // subdomain of each group
+  const int32_t* g0;           // first group of each subdomain (nsub + 1)
+  int64_t groups;
+};
+// K_ii of the listed subdomains from the assembled band into the interior
+// problems' row-band storage
+void launch_gather_interior_band(const SubDev* subs, const SubDev* isubs, const int32_t* ilo, int64_t count,
+                                 const int32_t* list, const double* band, double* iband, hipStream_t st);
+template <typename T>
+void launch_gather_groups(const NbGroups& G, const SubDev* subs, const double* band, const uint8_t* need, T* out,
+                          hipStream_t st);
+template <typename T>
+void launch_copy_groups(const NbGroups& G, int64_t count, const int32_t* list, const T* src, T* dst, hipStream_t st);
+// out_iface = K_tt B^T w, xint = K_it B^T w
+template <typename TV>
+void launch_dirichlet_a(const DualMaps& M, const NbGroups& kit, const double* w, const TV* kbb, const TV* kitv,
+                        double* out, double* xint, const int32_t* done, hipStream_t st);
+// out_iface -= K_ti sint
+template <typename TV>
+void launch_dirichlet_c(const DualMaps& M, const NbGroups& kti, const SubDev* isubs, const int32_t* ilo,
+                        const double* sint, const TV* ktiv, double* out, const int32_t* done, hipStream_t st);
+
 int reduction_blocks(int64_t n);
 // scalar finalizers (single thread); see dual.hip
 void launch_finalize(int kind, PcgScalars* S, const double* partials, int nparts, hipStream_t st);

@@ -436,6 +436,143 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
     }
   }
 
+  // ---- Dirichlet preconditioner: interior boxes and the couplings of the
+  //      interior with the touched nodes ----
+  {
+    std::vector<uint8_t> node_touched(M.n_torn / 3, 0);
+    for (int64_t e = 0; e < nnz; ++e) node_touched[M.b_col[e] / 3] = 1;
+    M.isubs.assign(M.n_sub, SubDev{});
+    M.ilo.assign(3 * M.n_sub, 0);
+    int64_t ioff = 0, iband = 0;
+    for (int64_t p = 0; p < M.n_sub; ++p) {
+      const SubDev& s = M.subs[p];
+      SubDev& si = M.isubs[p];
+      std::memset(&si, 0, sizeof(SubDev));
+      // bounding box of the nodes without a row of B
+      int32_t lo[3] = {s.N[0], s.N[1], s.N[2]}, hi[3] = {-1, -1, -1};
+      int64_t cnt_in = 0;
+      for (int32_t k = 0; k < s.N[2]; ++k)
+        for (int32_t j = 0; j < s.N[1]; ++j)
+          for (int32_t i = 0; i < s.N[0]; ++i) {
+            const int32_t a = i + s.N[0] * (j + s.N[1] * k);
+            if (node_touched[s.dof_off / 3 + a]) continue;
+            ++cnt_in;
+            const int32_t c[3] = {i, j, k};
+            for (int d = 0; d < 3; ++d) {
+              lo[d] = std::min(lo[d], c[d]);
+              hi[d] = std::max(hi[d], c[d]);
+            }
+          }
+      if (cnt_in == 0) continue;
+      int64_t box = 1;
+      for (int d = 0; d < 3; ++d) box *= hi[d] - lo[d] + 1;
+      if (box != cnt_in) return "the interior nodes of a subdomain do not form a box";
+      for (int d = 0; d < 3; ++d) {
+        M.ilo[3 * p + d] = lo[d];
+        si.N[d] = hi[d] - lo[d] + 1;
+        si.n[d] = si.N[d] - 1;
+      }
+      int ord[3] = {0, 1, 2};
+      std::stable_sort(ord, ord + 3, [&](int x, int y) { return si.N[x] < si.N[y]; });
+      for (int d = 0; d < 3; ++d) si.perm[d] = ord[d];
+      si.fs[ord[0]] = 1;
+      si.fs[ord[1]] = si.N[ord[0]];
+      si.fs[ord[2]] = si.N[ord[0]] * si.N[ord[1]];
+      si.ndof = (int32_t)(3 * cnt_in);
+      si.npad = (si.ndof + kPadRows - 1) / kPadRows * kPadRows;
+      const int32_t N0 = si.N[si.perm[0]], N1 = si.N[si.perm[1]];
+      si.b = std::min(3 * (N0 * N1 + N0 + 1) + 2, si.npad - 1);
+      si.Wb = si.b + 1;
+      si.bo = (si.b + 3) / 4 * 4;
+      si.dof_off = ioff;
+      si.band_off = iband;
+      ioff += si.ndof;
+      iband += (int64_t)si.npad * si.Wb;
+    }
+    M.n_int = ioff;
+    M.iband_entries = iband;
+    // rows in groups of 64 sorted by neighbour count; cols(p, node) tells
+    // whether a neighbour node is a column node
+    auto build = [&](NbGroupsHost& G, bool keep_empty, auto rows_of, auto is_col) {
+      G = NbGroupsHost{};
+      G.g0.assign(M.n_sub + 1, 0);
+      for (int64_t p = 0; p < M.n_sub; ++p) {
+        const SubDev& s = M.subs[p];
+        std::vector<int32_t> ld, out;
+        rows_of(p, ld, out);
+        std::vector<uint32_t> mask(ld.size(), 0u);
+        std::vector<int32_t> ord;
+        for (size_t t = 0; t < ld.size(); ++t) {
+          const int32_t a = ld[t] / 3;
+          const int32_t i = a % s.N[0], j = (a / s.N[0]) % s.N[1], k = a / (s.N[0] * s.N[1]);
+          uint32_t mk = 0;
+          for (int dk = -1; dk <= 1; ++dk)
+            for (int dj = -1; dj <= 1; ++dj)
+              for (int di = -1; di <= 1; ++di) {
+                const int32_t ii = i + di, jj = j + dj, kk = k + dk;
+                if (ii < 0 || jj < 0 || kk < 0 || ii >= s.N[0] || jj >= s.N[1] || kk >= s.N[2]) continue;
+                if (is_col(p, ii + s.N[0] * (jj + s.N[1] * kk)))
+                  mk |= 1u << (9 * (dk + 1) + 3 * (dj + 1) + (di + 1));
+              }
+          mask[t] = mk;
+          if (mk || keep_empty) ord.push_back((int32_t)t);
+        }
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+          return __builtin_popcount(mask[x]) > __builtin_popcount(mask[y]);
+        });
+        const int32_t nrow = (int32_t)ord.size(), ng = (nrow + 63) / 64;
+        for (int32_t g = 0; g < ng; ++g) {
+          int32_t nb = 0;
+          for (int32_t l = 0; l < 64; ++l) {
+            const int32_t q = 64 * g + l;
+            if (q < nrow) {
+              G.out.push_back(out[ord[q]]);
+              G.ldof.push_back(ld[ord[q]]);
+              G.mask.push_back(mask[ord[q]]);
+              nb = std::max(nb, __builtin_popcount(mask[ord[q]]));
+            } else {
+              G.out.push_back(-1);
+              G.ldof.push_back(ld[ord[0]]);
+              G.mask.push_back(0u);
+            }
+          }
+          G.gnb.push_back(nb);
+          G.gsub.push_back((int32_t)p);
+          G.goff.push_back(G.goff.back() + (int64_t)3 * nb * 64);
+        }
+        G.g0[p + 1] = G.g0[p] + ng;
+      }
+    };
+    auto interior = [&](int64_t p, int32_t a) { return M.isubs[p].ndof > 0 && !node_touched[M.subs[p].dof_off / 3 + a]; };
+    // K_it: every DOF of an interior node (rows without a touched neighbour
+    // too, so that every interior entry is written); output at its interior DOF
+    build(M.kit, true,
+          [&](int64_t p, std::vector<int32_t>& ld, std::vector<int32_t>& out) {
+            const SubDev& s = M.subs[p];
+            const SubDev& si = M.isubs[p];
+            const int32_t* lo = &M.ilo[3 * p];
+            for (int32_t li = 0; li < si.ndof; ++li) {
+              const int32_t ai = li / 3, c = li % 3;
+              const int32_t ii = ai % si.N[0], jj = (ai / si.N[0]) % si.N[1], kk = ai / (si.N[0] * si.N[1]);
+              const int32_t a = (ii + lo[0]) + s.N[0] * ((jj + lo[1]) + s.N[1] * (kk + lo[2]));
+              ld.push_back(3 * a + c);
+              out.push_back((int32_t)(si.dof_off + li));
+            }
+          },
+          [&](int64_t p, int32_t a) { return node_touched[M.subs[p].dof_off / 3 + a] != 0; });
+    // K_ti: the touched DOFs next to an interior node; output at the touched index
+    build(M.kti, false,
+          [&](int64_t p, std::vector<int32_t>& ld, std::vector<int32_t>& out) {
+            const SubDev& s = M.subs[p];
+            for (int32_t t = 0; t < s.n_iface; ++t) {
+              ld.push_back(M.if_ldof[s.iface_off + t]);
+              out.push_back((int32_t)(s.iface_off + t));
+            }
+          },
+          interior);
+    if (M.n_int >= (int64_t)1 << 31) return "too many interior DOFs for 32-bit indices";
+  }
+
   // ---- untorn maps ----
   M.g_first.resize(M.n_gdof);
   M.g_rp.assign(M.n_gdof + 1, 0);
@@ -609,6 +746,16 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   for (size_t q = 0; q < M.wn_elems.size(); ++q)
     if (M.wn_elems[q] < 0 || M.wn_elems[q] >= M.n_elem) return "internal: warm-start element map out of range";
   return "";
+}
+
+int64_t assign_interior_panels(HostModel& M, int TS) {
+  int64_t off = 0;
+  for (SubDev& s : M.isubs) {
+    s.panel_off = off;
+    s.panel_len = s.ndof > 0 ? panel_entries(s.npad, s.bo, TS) : 0;
+    off += s.panel_len;
+  }
+  return off;
 }
 
 int64_t assign_panels(HostModel& M, int TS) {

@@ -11,6 +11,19 @@
 
 namespace tfeti {
 
+// Sparse rows in wavefront groups of 64 (the layout of the lumped K_bb):
+// per lane slot the output index (-1 past the end), the local natural DOF of
+// the row and its mask of column nodes among the 27 around its node (bit
+// 9 (dk+1) + 3 (dj+1) + di+1); per group the value offset, the neighbour
+// count and the subdomain; per subdomain its first group.  Values are stored
+// slot-major: value (3 b + c) of lane l at goff + (3 b + c) 64 + l.
+struct NbGroupsHost {
+  std::vector<int32_t> out, ldof;
+  std::vector<uint32_t> mask;
+  std::vector<int64_t> goff{0};
+  std::vector<int32_t> gnb, gsub, g0;
+};
+
 struct HostModel {
   // problem
   int32_t S[3];
@@ -82,6 +95,15 @@ struct HostModel {
   std::vector<int32_t> wn_elems;        // elements containing the node (all copies)
   double load_dir[3] = {0, 0, 0};       // traction of the loaded face at factor 1
   double load_area = 0.0;               // element face area of that face
+  // Dirichlet preconditioner (Section 4.2): the interior nodes of each
+  // subdomain (those carrying no row of B) form a box of the node lattice,
+  // solved as a problem of its own
+  std::vector<SubDev> isubs;            // n_sub; ndof 0 where no node is interior
+  std::vector<int32_t> ilo;             // 3 per subdomain: first interior node per local axis
+  int64_t n_int = 0;                    // interior DOFs of all subdomains
+  int64_t iband_entries = 0;            // sum npad * Wb of the interior problems
+  NbGroupsHost kit;                     // K_it: interior rows x touched neighbour nodes
+  NbGroupsHost kti;                     // K_ti: touched rows x interior neighbour nodes
   // sizes
   int64_t band_entries = 0;             // sum npad * Wb
   int64_t skyline_entries = 0;          // sum of envelope widths of the factors
@@ -92,5 +114,7 @@ std::string build_model(const tfeti_problem& prob, HostModel& M);
 
 // Assign panel offsets for tile TS; returns entries of one layout.
 int64_t assign_panels(HostModel& M, int TS);
+// The same for the interior problems of the Dirichlet preconditioner.
+int64_t assign_interior_panels(HostModel& M, int TS);
 
 }  // namespace tfeti
