@@ -187,6 +187,7 @@ typedef struct tfeti_handle tfeti_handle;
 int tfeti_setup(const tfeti_problem* prob_host, const tfeti_options* opt_host,
                 void* stream, tfeti_handle** out);
 void tfeti_destroy(tfeti_handle* h);
+/* h NULL: the message of the last failed handle-less call on this thread. */
 const char* tfeti_last_error(const tfeti_handle* h);
 int tfeti_get_sizes(const tfeti_handle* h, tfeti_sizes* out_host);
 
@@ -317,6 +318,18 @@ int tfeti_mlp_work_size(const tfeti_mlp* net_host, int64_t n, int64_t* floats_ho
 int tfeti_mlp_sync_bf16(const tfeti_mlp* net_host, void* stream);
 /* Y (n x d_out, FP32) = network(X (n x d_in, FP32, rounded to bf16)). */
 int tfeti_mlp_forward(const tfeti_mlp* net_host, int64_t n, const float* X, float* Y, float* work, void* stream);
+/* The forward pass of tfeti_mlp_forward without a workspace argument and
+ * without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Its scratch (the bf16 inputs and both hidden layers) is a
+ * fixed device array of 8 MiB per GPU, held until the process ends: n rows
+ * need 4 ((n d_in + 1)/2 + 2 ((n d_h + 1)/2)) bytes, so about 7700 rows of
+ * the 31 -> 256 -> 256 -> 21 warm-start network per call; larger n is
+ * rejected with TFETI_E_INVALID (message in tfeti_last_error(NULL)) and
+ * must be split.  Every call on one GPU uses the same array: calls that
+ * overlap on one GPU (other streams, other threads) race.  Nothing in it
+ * needs to start at zero.  Results are bitwise those of tfeti_mlp_forward. */
+int tfeti_mlp_forward_noalloc(const tfeti_mlp* net_host, int64_t n, const float* X, float* Y, void* stream);
 /* Forward, masked mean squared error L = 1/(2n) sum M (Y - T)^2 into *loss
  * (device scalar), and the gradients of L into gW, gb. */
 int tfeti_mlp_loss_grad(const tfeti_mlp* net_host, int64_t n, const float* X, const float* T, const float* M,

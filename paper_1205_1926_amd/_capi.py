@@ -105,6 +105,7 @@ SIGNATURES = {
     "tfeti_mlp_work_size": (I32, [C.POINTER(Mlp), I64, C.POINTER(I64)]),
     "tfeti_mlp_sync_bf16": (I32, [C.POINTER(Mlp), P]),
     "tfeti_mlp_forward": (I32, [C.POINTER(Mlp), I64, P, P, P, P]),
+    "tfeti_mlp_forward_noalloc": (I32, [C.POINTER(Mlp), I64, P, P, P]),
     "tfeti_mlp_loss_grad": (I32, [C.POINTER(Mlp), I64, P, P, P, P, P, P, P]),
     "tfeti_mlp_adam": (I32, [C.POINTER(Mlp), I32, C.c_float, C.c_float, C.c_float, C.c_float, P]),
 }

@@ -1461,7 +1461,11 @@ void tfeti_destroy(tfeti_handle* h) {
   delete h;
 }
 
-const char* tfeti_last_error(const tfeti_handle* h) { return h ? h->err.c_str() : "null handle"; }
+const char* tfeti_last_error(const tfeti_handle* h) {
+  if (h) return h->err.c_str();
+  const char* e = noalloc_error();
+  return e ? e : "null handle";
+}
 
 int tfeti_get_sizes(const tfeti_handle* h, tfeti_sizes* o) {
   if (!h || !o) return TFETI_E_INVALID;

@@ -241,6 +241,8 @@ void launch_dirichlet_c(const DualMaps& M, const NbGroups& kti, const SubDev* is
                         const double* sint, const TV* ktiv, double* out, const int32_t* done, hipStream_t st);
 
 int reduction_blocks(int64_t n);
+// message of the last failed allocation-free call on this thread (or nullptr)
+const char* noalloc_error();
 // scalar finalizers (single thread); see dual.hip
 void launch_finalize(int kind, PcgScalars* S, const double* partials, int nparts, hipStream_t st);
 enum FinalizeKind { FIN_WW = 0, FIN_YW = 1, FIN_PQ = 2, FIN_RREF = 3, FIN_SUM_TMP0 = 4 };

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "kernels.h"
 
@@ -240,9 +242,10 @@ struct MlpWork {
   float *dY, *dA, *dB, *part, *slices, *bslices;
 };
 
-static MlpWork carve(const tfeti_mlp* net, int64_t n, float* work) {
-  MlpWork w;
-  int64_t din = net->d_in, dh = net->d_h, dout = net->d_out;
+// the buffers of the forward pass (bf16 inputs, both hidden layers) at the
+// start of the workspace; returns the first float past them
+static float* carve_forward(const tfeti_mlp* net, int64_t n, float* work, MlpWork& w) {
+  const int64_t din = net->d_in, dh = net->d_h;
   float* p = work;
   w.Xb = reinterpret_cast<uint16_t*>(p);
   p += (n * din + 1) / 2;
@@ -250,6 +253,13 @@ static MlpWork carve(const tfeti_mlp* net, int64_t n, float* work) {
   p += (n * dh + 1) / 2;
   w.h2 = reinterpret_cast<uint16_t*>(p);
   p += (n * dh + 1) / 2;
+  return p;
+}
+
+static MlpWork carve(const tfeti_mlp* net, int64_t n, float* work) {
+  MlpWork w;
+  int64_t din = net->d_in, dh = net->d_h, dout = net->d_out;
+  float* p = carve_forward(net, n, work, w);
   w.dY = p;
   p += n * dout;
   w.dA = p;
@@ -278,11 +288,77 @@ static void forward(const tfeti_mlp* net, int64_t n, const float* X, float* Y, c
                                                       net->b[2], nullptr, st);
 }
 
+// ------------------------------------------------------------------ allocation-free forward pass
+// Device scratch of tfeti_mlp_forward_noalloc: the bf16 inputs and both
+// hidden layers (the three buffers the forward pass carves from the caller's
+// workspace).  One copy per GPU for the life of the process.
+constexpr int64_t kNoallocBytes = 8 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+thread_local std::string g_noalloc_err;
+}  // namespace
+
+// Bytes of scratch the forward pass of n rows needs (carve_forward()).
+static int64_t mlp_forward_scratch_bytes(const tfeti_mlp* net, int64_t n) {
+  return 4 * ((n * net->d_in + 1) / 2 + 2 * ((n * net->d_h + 1) / 2));
+}
+
+// Device address of this GPU's scratch array, looked up once per device
+// with that device current; nullptr on failure.
+static void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+const char* noalloc_error() { return g_noalloc_err.empty() ? nullptr : g_noalloc_err.c_str(); }
+
 }  // namespace tfeti
 
 using namespace tfeti;
 
 extern "C" {
+
+int tfeti_mlp_forward_noalloc(const tfeti_mlp* net, int64_t n, const float* X, float* Y, void* stream) {
+  g_noalloc_err.clear();
+  if (mlp_check(net) || n < 0 || (n > 0 && (!X || !Y))) {
+    g_noalloc_err = "tfeti_mlp_forward_noalloc: invalid network or buffers";
+    return TFETI_E_INVALID;
+  }
+  if (n == 0) return TFETI_OK;
+  const int64_t need = mlp_forward_scratch_bytes(net, n);
+  if (need > kNoallocBytes) {
+    g_noalloc_err = "tfeti_mlp_forward_noalloc: " + std::to_string(n) + " rows need " + std::to_string(need) +
+                    " bytes of scratch; the maximum is " + std::to_string(kNoallocBytes) +
+                    " bytes (split the rows into smaller calls)";
+    return TFETI_E_INVALID;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    g_noalloc_err = "tfeti_mlp_forward_noalloc: no usable current device";
+    return TFETI_E_HIP;
+  }
+  void* ptr = scratch_ptr(dev);
+  if (!ptr) {
+    g_noalloc_err = "tfeti_mlp_forward_noalloc: hipGetSymbolAddress of the scratch array failed";
+    return TFETI_E_HIP;
+  }
+  MlpWork w{};
+  (void)carve_forward(net, n, static_cast<float*>(ptr), w);
+  forward(net, n, X, Y, w, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? TFETI_OK : TFETI_E_HIP;
+}
 
 int tfeti_mlp_work_size(const tfeti_mlp* net, int64_t n, int64_t* floats) {
   if (mlp_check(net) || n < 0 || !floats) return TFETI_E_INVALID;
