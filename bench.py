@@ -14,7 +14,9 @@ The same load steps run in three forms (legs), each on a fresh handle:
                   from a HIP graph (the headline line; --learned adds the
                   learned warm-start candidate);
   fp64_plain      FP64 factors, cold start, eager launches (plain GPU TFETI);
-  fp64_graph_warm FP64 factors with the warm start and the graph.
+  fp64_graph_warm FP64 factors with the warm start and the graph;
+  fp64_dirichlet, fp32_dirichlet  the same with the Dirichlet preconditioner
+                  Bbar Sbar Bbar^T instead of the lumped one (Section 4.2).
 
 value = F-applies inside the timed load steps of the headline leg / their
 wall time; newton_step_ms = wall time / Newton iterations with a solve.
@@ -54,6 +56,8 @@ LEGS = {
     "fp32_all": dict(precision="fp32", use_graph=1, warm_start=1),
     "fp64_plain": dict(precision="fp64", use_graph=0, warm_start=0),
     "fp64_graph_warm": dict(precision="fp64", use_graph=1, warm_start=1),
+    "fp64_dirichlet": dict(precision="fp64", use_graph=1, warm_start=1, preconditioner=2),
+    "fp32_dirichlet": dict(precision="fp32", use_graph=1, warm_start=1, preconditioner=2),
 }
 SAMPLE_S, SAMPLE_N = (2, 2, 2), (8, 8, 8)
 
