@@ -8,11 +8,14 @@ PCGP (Algorithm 3) with its F-applies, projections and lumped preconditioner;
 then the commit.  Default workload: the 10x10x10 cube of 8^3-element
 subdomains; W untimed load steps, then K timed ones.
 
-The same load steps run in three forms (legs), each on a fresh handle:
+The same load steps run in several forms (legs), each on a fresh handle
+(default: fp32_all, fp64_plain, fp64_graph_warm, fp64_dirichlet, fp32_learned):
   fp32_all        FP32 panels of the FP64 factor in the inner PCGP with FP64
                   outer dual refinement, warm start, PCGP iteration replayed
                   from a HIP graph (the headline line; --learned adds the
                   learned warm-start candidate);
+  fp32_learned    fp32_all with the learned warm-start candidate of the
+                  network in the package (trained on the uneven 8x8x8 mesh);
   fp64_plain      FP64 factors, cold start, eager launches (plain GPU TFETI);
   fp64_graph_warm FP64 factors with the warm start and the graph;
   fp64_dirichlet, fp32_dirichlet  the same with the Dirichlet preconditioner
@@ -58,7 +61,10 @@ LEGS = {
     "fp64_graph_warm": dict(precision="fp64", use_graph=1, warm_start=1),
     "fp64_dirichlet": dict(precision="fp64", use_graph=1, warm_start=1, preconditioner=2),
     "fp32_dirichlet": dict(precision="fp32", use_graph=1, warm_start=1, preconditioner=2),
+    "fp32_learned": dict(precision="fp32", use_graph=1, warm_start=1),
 }
+# the learned candidate of the fp32_learned leg (and of fp32_all with --learned)
+DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_1205_1926_amd", "weights", "warmstart_cube8x8x8_uneven.safetensors")
 SAMPLE_S, SAMPLE_N = (2, 2, 2), (8, 8, 8)
 
 
@@ -246,7 +252,7 @@ def run_leg(name, w, args, net, detail):
     sz = g.sizes
     log(f"{name}: setup in {time.perf_counter() - t0:.1f} s ({sz['n_sub']} subdomains, n={sz['n_torn']}, "
         f"m={sz['m']})")
-    leg_net = net if name == "fp32_all" else None
+    leg_net = net if name in ("fp32_all", "fp32_learned") else None
     first = None
 
     def step():
@@ -341,7 +347,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed load steps before them (at least 1)")
     ap.add_argument("--learned", default=None, help="safetensors weights of the warm-start network (fp32_all leg)")
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--legs", default="fp32_all,fp64_plain,fp64_graph_warm",
+    ap.add_argument("--legs", default="fp32_all,fp64_plain,fp64_graph_warm,fp64_dirichlet,fp32_learned",
                     help="comma-separated forms; the first is the headline line")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--refine-eps", type=float, default=0.0, help="FP32 mode: inner PCGP tolerance")
@@ -402,14 +408,17 @@ def main() -> int:
     import numpy as np
     import torch
 
-    net = None
-    if args.learned:
+    nets = {}
+    if args.learned or "fp32_learned" in legs:
         from paper_1205_1926_amd.warmstart import WarmNet
-        net = WarmNet.load(args.learned, device="cuda:0")
+        if args.learned:
+            nets["fp32_all"] = WarmNet.load(args.learned, device="cuda:0")
+        if "fp32_learned" in legs:
+            nets["fp32_learned"] = WarmNet.load(args.learned or DEFAULT_WEIGHTS, device="cuda:0")
     detail = {}
     results = {}
     for name in legs:
-        results[name] = run_leg(name, w, args, net, detail)
+        results[name] = run_leg(name, w, args, nets.get(name), detail)
     if args.detail:
         with open(args.detail, "w") as fh:
             json.dump(detail, fh)
@@ -435,8 +444,9 @@ def main() -> int:
         else:
             log(f"oracle reference failed (exit {rc})")
     head = results[legs[0]]
-    if "fp64_plain" in results and legs[0] != "fp64_plain":
-        acc["u_after_timed_vs_fp64_plain"] = rel(head["u_final"], results["fp64_plain"]["u_final"])
+    if "fp64_plain" in results:
+        acc["u_after_timed_vs_fp64_plain"] = {n: rel(r["u_final"], results["fp64_plain"]["u_final"])
+                                              for n, r in results.items() if n != "fp64_plain"}
     if cpu is not None and full_1core is not None:
         cpu["oracle_full_size_1core"] = full_1core
 

@@ -87,8 +87,9 @@ typedef struct {
                                    complement of the unregularized tangent onto
                                    the DOFs of the nodes carrying rows of B,
                                    applied through banded Cholesky factors of
-                                   the interior blocks K_ii (FP64; the interior
-                                   nodes of a box subdomain form a box)         */
+                                   the interior blocks K_ii (the interior nodes
+                                   of a box subdomain form a box; factors in
+                                   FP64, solved in the F-apply's precision)     */
   double eps_pcg;               /* PCGP relative tolerance                      */
   double eps_newton;            /* Newton relative-residual tolerance           */
   int32_t max_pcg;              /* PCGP iteration cap (default 5000)            */

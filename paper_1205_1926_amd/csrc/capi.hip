@@ -139,7 +139,9 @@ struct tfeti_handle {
           *d_ilist_r = nullptr;
   int64_t n_iorder = 0, ipanel_alloc = 0;
   int ipad_max = 0, ibmax = 0;
+  int iTS = 32, int_nt = 256;                   // tile and threads of the interior solves
   double *d_iband = nullptr, *d_eiband = nullptr, *d_iF = nullptr, *d_iB = nullptr;
+  float *d_iF32 = nullptr, *d_iB32 = nullptr;   // FP32 mode: FP32 interior panels (the preconditioner's solves)
   double *d_xint = nullptr, *d_sint = nullptr;
   NbGroups kit{}, kti{};
   void *d_kit_val = nullptr, *d_kti_val = nullptr, *d_ekit = nullptr, *d_ekti = nullptr;
@@ -320,23 +322,40 @@ int64_t interior_list(tfeti_handle* h, const int32_t* list, int64_t count, std::
 }
 
 void pack_interior(tfeti_handle* h, int64_t count, const int32_t* list, const double* band) {
-  launch_pack_panels<double, double>(h->d_isubs, count, list, band, h->d_iF, h->d_iB, h->TS, h->st);
+  launch_pack_panels<double, double>(h->d_isubs, count, list, band, h->d_iF, h->d_iB, h->iTS, h->st, h->d_iF32,
+                                     h->d_iB32);
 }
 
 template <typename TV>
 void dirichlet_apply(tfeti_handle* h, const double* w, const TV* kbb, double* z, const int32_t* done) {
   launch_dirichlet_a<TV>(h->dm, h->kit, w, kbb, (const TV*)h->d_kit_val, h->d_iface, h->d_xint, done, h->st);
   if (h->n_iorder > 0) {
-    KsolveArgs<double> a{};
-    a.subs = h->d_isubs;
-    a.order = h->d_iorder;
-    a.nsub = h->n_iorder;
-    a.Fp = h->d_iF;
-    a.Bp = h->d_iB;
-    a.in_full = h->d_xint;
-    a.out_full = h->d_sint;
-    a.done = done;
-    launch_ksolve<double>(a, h->TS, h->nt, h->ipad_max, h->st);
+    // interior solves in the precision of the F-apply: FP64, or FP32 panels
+    // of the FP64 interior factor in FP32 mode (a preconditioner needs no
+    // more)
+    if (h->prec == TFETI_PREC_FP64) {
+      KsolveArgs<double> a{};
+      a.subs = h->d_isubs;
+      a.order = h->d_iorder;
+      a.nsub = h->n_iorder;
+      a.Fp = h->d_iF;
+      a.Bp = h->d_iB;
+      a.in_full = h->d_xint;
+      a.out_full = h->d_sint;
+      a.done = done;
+      launch_ksolve<double>(a, h->iTS, h->int_nt, h->ipad_max, h->st);
+    } else {
+      KsolveArgs<float> a{};
+      a.subs = h->d_isubs;
+      a.order = h->d_iorder;
+      a.nsub = h->n_iorder;
+      a.Fp = h->d_iF32;
+      a.Bp = h->d_iB32;
+      a.in_full = h->d_xint;
+      a.out_full = h->d_sint;
+      a.done = done;
+      launch_ksolve<float>(a, h->iTS, h->int_nt, h->ipad_max, h->st);
+    }
     launch_dirichlet_c<TV>(h->dm, h->kti, h->d_isubs, h->d_ilo, h->d_sint, (const TV*)h->d_kti_val, h->d_iface, done,
                            h->st);
   }
@@ -905,13 +924,20 @@ int retile(tfeti_handle* h, int TS, int natural, int threads) {
   HIPCHK(hipMemcpyAsync(h->d_subs, M.subs.data(), M.subs.size() * sizeof(SubDev), hipMemcpyHostToDevice, h->st));
   HIPCHK(hipMemcpyAsync(h->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
   pack(h, M.n_sub, nullptr);
-  if (h->dirichlet) {
-    if (assign_interior_panels(M, TS) > h->ipanel_alloc)
-      return fail(h, TFETI_E_INVALID, "internal: interior panel storage too small for the tile");
-    HIPCHK(hipMemcpyAsync(h->d_isubs, M.isubs.data(), M.isubs.size() * sizeof(SubDev), hipMemcpyHostToDevice, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    if (h->n_iorder > 0) pack_interior(h, h->n_iorder, h->d_iorder, h->d_iband);
-  }
+  HIPCHK(hipStreamSynchronize(h->st));
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Re-pack the interior factors of the Dirichlet preconditioner for tile TS.
+int retile_interior(tfeti_handle* h, int TS) {
+  HostModel& M = h->M;
+  if (assign_interior_panels(M, TS) > h->ipanel_alloc)
+    return fail(h, TFETI_E_INVALID, "internal: interior panel storage too small for the tile");
+  drop_graphs(h);
+  h->iTS = TS;
+  HIPCHK(hipMemcpyAsync(h->d_isubs, M.isubs.data(), M.isubs.size() * sizeof(SubDev), hipMemcpyHostToDevice, h->st));
+  if (h->n_iorder > 0) pack_interior(h, h->n_iorder, h->d_iorder, h->d_iband);
   HIPCHK(hipStreamSynchronize(h->st));
   HIPCHK(hipGetLastError());
   return 0;
@@ -1011,6 +1037,70 @@ int autotune(tfeti_handle* h) {
   return 0;
 }
 
+// Interior solves of the Dirichlet preconditioner: the interior boxes are
+// smaller than the subdomains (7^3 nodes in an 8^3-element subdomain), so
+// their solves are latency-bound at other tiles than the F-apply's; every
+// tile 16/32/64 with 256, 512 or 1024 threads is timed (median of 10 on the
+// factors of the first factorization) and the fastest kept.
+int autotune_interior(tfeti_handle* h) {
+  if (h->n_iorder == 0) return 0;
+  launch_axpby(h->M.n_int, 0.0, nullptr, 0.0, h->d_xint, h->st);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(h, TFETI_E_HIP, "autotuner: events");
+  int best_ts = h->iTS, best_nt = h->int_nt;
+  double best = -1.0;
+  for (int TS : {16, 32, 64}) {
+    RC(retile_interior(h, TS));
+    for (int nt : {256, 512, 1024}) {
+      if (nt == 1024 && TS > 32) continue;
+      h->int_nt = nt;
+      std::vector<float> t;
+      for (int r = 0; r < 12; ++r) {
+        (void)hipEventRecord(e0, h->st);
+        if (h->prec == TFETI_PREC_FP64) {
+          KsolveArgs<double> a{};
+          a.subs = h->d_isubs;
+          a.order = h->d_iorder;
+          a.nsub = h->n_iorder;
+          a.Fp = h->d_iF;
+          a.Bp = h->d_iB;
+          a.in_full = h->d_xint;
+          a.out_full = h->d_sint;
+          launch_ksolve<double>(a, TS, nt, h->ipad_max, h->st);
+        } else {
+          KsolveArgs<float> a{};
+          a.subs = h->d_isubs;
+          a.order = h->d_iorder;
+          a.nsub = h->n_iorder;
+          a.Fp = h->d_iF32;
+          a.Bp = h->d_iB32;
+          a.in_full = h->d_xint;
+          a.out_full = h->d_sint;
+          launch_ksolve<float>(a, TS, nt, h->ipad_max, h->st);
+        }
+        (void)hipEventRecord(e1, h->st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (r >= 2 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) t.push_back(ms);
+      }
+      if (t.empty()) continue;
+      std::sort(t.begin(), t.end());
+      const double med = t[t.size() / 2];
+      if (best < 0 || med < best) {
+        best = med;
+        best_ts = TS;
+        best_nt = nt;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  RC(retile_interior(h, best_ts));
+  h->int_nt = best_nt;
+  return 0;
+}
+
 // Regularize, factorize and pack.  The tangent of a subdomain without a
 // plastic Gauss point is the elastic stiffness, which depends on geometry and
 // material only; a subdomain whose current factor is of that matrix keeps it
@@ -1099,6 +1189,7 @@ int factorize(tfeti_handle* h) {
   if (h->tune_pending) {
     h->tune_pending = false;
     RC(autotune(h));
+    if (h->dirichlet) RC(autotune_interior(h));
   }
   // keep the elastic factors once the band holds every subdomain's one
   auto all_set = [](const std::vector<uint8_t>& v) {
@@ -1243,6 +1334,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     if (h->tune_pending)
       for (int T : {16, 32, 64}) h->ipanel_alloc = std::max(h->ipanel_alloc, assign_interior_panels(M, T));
     h->ipanel_alloc = std::max(h->ipanel_alloc, assign_interior_panels(M, TS));
+    h->iTS = TS;
     h->has_int.assign(M.n_sub, 0);
     std::vector<int32_t> iorder;
     for (int64_t p = 0; p < M.n_sub; ++p)
@@ -1263,6 +1355,10 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     if (!h->opt.refactor_all) RC(dalloc(h, &h->d_eiband, M.iband_entries));
     RC(dalloc(h, &h->d_iF, h->ipanel_alloc));
     RC(dalloc(h, &h->d_iB, h->ipanel_alloc));
+    if (h->prec == TFETI_PREC_FP32) {
+      RC(dalloc(h, &h->d_iF32, h->ipanel_alloc));
+      RC(dalloc(h, &h->d_iB32, h->ipanel_alloc));
+    }
     RC(dalloc(h, &h->d_xint, M.n_int));
     RC(dalloc(h, &h->d_sint, M.n_int));
     auto groups = [&](const NbGroupsHost& G, NbGroups& D) -> int {
@@ -1433,7 +1529,9 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     RC(upload(h, &d_cs, csv));
     HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
     launch_band_cholesky<double>(d_cs, 1, nullptr, d_cb, h->d_fail, M.bc, 0, h->st);
-    launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st);
+    double* d_ct = nullptr;  // transposed factor (setup scratch)
+    RC(dalloc(h, &d_ct, (int64_t)M.lc_pad * (M.bc + 1)));
+    launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st, d_ct);
     launch_coarse_pack(M.lc, h->d_Ginv, h->d_Gpk, h->st);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));

@@ -168,7 +168,71 @@ __global__ __launch_bounds__(64) void coarse_inverse_kernel(const double* __rest
   }
 }
 
-void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st) {
+// Lt[i][k] = L[i + k][i] (row-band storage of the transpose; zero past l).
+__global__ __launch_bounds__(256) void band_transpose_kernel(const double* __restrict__ L, int32_t l, int32_t b,
+                                                             int32_t Wc, double* __restrict__ Lt) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)l * Wc) return;
+  const int32_t i = (int32_t)(q / Wc), k = (int32_t)(q - (int64_t)i * Wc);
+  Lt[q] = (k <= b && i + k < l) ? L[(int64_t)(i + k) * Wc + (b - k)] : 0.0;
+}
+
+// One wavefront per column j of the inverse: y = L^{-1} e_j (rows j..l-1)
+// and then x = L^{-T} y, with the vector in LDS; every step's sum over the
+// band is split across the 64 lanes (coalesced row reads of L and of its
+// transpose) and reduced by lane shuffles in a fixed order.  Column j of
+// the symmetric inverse is written as row j.
+__global__ __launch_bounds__(64) void coarse_inverse_wave_kernel(const double* __restrict__ L,
+                                                                 const double* __restrict__ Lt, int32_t l, int32_t b,
+                                                                 int32_t Wc, double* __restrict__ G) {
+  extern __shared__ double yv[];
+  const int j = blockIdx.x, lane = threadIdx.x;
+  for (int i = lane; i < l; i += 64) yv[i] = 0.0;
+  __syncthreads();
+  auto wave_sum = [&](double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+  };
+  for (int i = j; i < l; ++i) {
+    const int t0 = i - b > j ? i - b : j;
+    const double* Li = L + (int64_t)i * Wc + (b - i);
+    double s = 0.0;
+    for (int t = t0 + lane; t < i; t += 64) s = fma(Li[t], yv[t], s);
+    s = wave_sum(s);
+    if (lane == 0) yv[i] = ((i == j ? 1.0 : 0.0) - s) / Li[i];
+    __syncthreads();
+  }
+  for (int i = l - 1; i >= 0; --i) {
+    const int t1 = i + b < l - 1 ? i + b : l - 1;
+    const double* Ti = Lt + (int64_t)i * Wc - i;
+    double s = 0.0;
+    for (int t = i + 1 + lane; t <= t1; t += 64) s = fma(Ti[t], yv[t], s);
+    s = wave_sum(s);
+    if (lane == 0) yv[i] = (yv[i] - s) / Ti[i];
+    __syncthreads();
+  }
+  for (int i = lane; i < l; i += 64) G[(int64_t)j * l + i] = yv[i];
+}
+
+// Lt: scratch of l * Wc entries for the transposed factor (may be NULL:
+// then the one-thread-per-column kernel runs, as it does when a column does
+// not fit the LDS of a workgroup).
+void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st,
+                           double* Lt) {
+  int dev = 0, lds = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
+  const size_t shm = (size_t)l * sizeof(double);
+  if (Lt && l > 0 && shm <= (size_t)lds) {
+    const int64_t nt = (int64_t)l * Wc;
+    band_transpose_kernel<<<dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st>>>(L, l, b, Wc, Lt);
+    if (shm > 65536)
+      (void)hipFuncSetAttribute((const void*)coarse_inverse_wave_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)shm);
+    coarse_inverse_wave_kernel<<<dim3((unsigned)l), dim3(64), shm, st>>>(L, Lt, l, b, Wc, Ginv);
+    return;
+  }
   int blocks = (l + 63) / 64;
   coarse_inverse_kernel<<<dim3(blocks), dim3(64), 0, st>>>(L, l, b, Wc, Ginv);
 }

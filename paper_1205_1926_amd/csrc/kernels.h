@@ -115,7 +115,9 @@ template <typename TW, typename T>
 void launch_pack_panels(const SubDev* subs, int64_t count, const int32_t* list, const TW* band, T* Fp, T* Bp, int TS,
                         hipStream_t st, float* Fq = nullptr, float* Bq = nullptr);
 // Dense inverse of the coarse matrix from its banded Cholesky factor.
-void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st);
+// Lt: scratch for the transposed factor (l * Wc entries), or NULL.
+void launch_coarse_inverse(const double* L, int32_t l, int32_t b, int32_t Wc, double* Ginv, hipStream_t st,
+                           double* Lt);
 
 // ---- subdomain solves -----------------------------------------------------
 template <typename T>
