@@ -324,6 +324,54 @@ def run_leg(name, w, args, net, detail):
     return res
 
 
+def plate_run(args) -> int:
+    """The notched-plate benchmark (the box stand-in for the paper's Section 5
+    plate, Tables 2 and 3): both time discretizations, (a) one step and (b)
+    eight steps to t = 1/4, on the GPU.  One row per Newton iteration on
+    stderr (load step, iteration, PCGP iterations, plastic elements, the
+    increment criterion, relative residual, time) and one JSON line with the
+    totals; the two discretizations' final plastic zones are compared (the
+    paper finds them almost equal)."""
+    import torch
+
+    import workloads as W
+    from paper_1205_1926_amd import GpuSolver
+
+    opts = LEGS[args.plate_form]
+    out = {"metric": "notched plate: Newton iterations, PCGP iterations, plastic elements and wall time per "
+                     "time discretization", "form": args.plate_form, "level": args.plate,
+           "eps_newton": args.plate_eps[0], "eps_pcg": args.plate_eps[1]}
+    for disc, steps in (("a", 1), ("b", 8)):
+        w = W.plate_notch(args.plate, steps=steps, eps_newton=args.plate_eps[0], eps_pcg=args.plate_eps[1])
+        g = GpuSolver(w, tile=args.tile, **opts)
+        torch.cuda.synchronize()
+        sz = g.sizes
+        if disc == "a":
+            out["workload"] = (f"{w.name.rsplit('_n', 1)[0]}: {sz['n_sub']} box subdomains, {sz['n_elem']} "
+                               f"elements, {sz['n_torn']} torn DOF, {sz['m']} multipliers")
+        log(f"plate ({disc}): {steps} load steps; step  it  pcg  plastic_el  crit  relres  ms")
+        t0 = time.perf_counter()
+        newton = pcg = 0
+        for k in range(steps):
+            for r in g.load_step():
+                newton += 1
+                pcg += r["pcg_iters"]
+                log(f"plate ({disc}) {k + 1:2d} {r['iteration']:2d} {r['pcg_iters']:4d} {r['plastic_elements']:7d} "
+                    f"{r['crit']:.2e} {r['relres']:.2e} {r['ms_total']:.1f}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kappa = g.state()["kappa"].reshape(-1, 8)
+        plastic = int((kappa > 0).any(dim=1).sum().item())
+        umax = float(g.state()["u"].abs().max().item())
+        g.close()
+        out[disc] = {"steps": steps, "newton": newton, "pcg": pcg, "plastic_el": plastic, "u_max": rounded(umax),
+                     "seconds": rounded(elapsed)}
+    out["plastic_spread"] = rounded(abs(out["a"]["plastic_el"] - out["b"]["plastic_el"]) /
+                                    max(out["b"]["plastic_el"], 1))
+    print(json.dumps(out, separators=(",", ":")), flush=True)
+    return 0
+
+
 def rel(a, b):
     import numpy as np
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
@@ -361,6 +409,10 @@ def main() -> int:
     ap.add_argument("--counter-probe", action="store_true",
                     help="for hardware-counter runs: factorize once, run --fapply-reps F-applies and one "
                          "device copy of 1 GiB (the scale reference of the byte counters), print sizes")
+    ap.add_argument("--plate", type=int, default=None,
+                    help="run the notched-plate benchmark at this mesh level instead (both discretizations)")
+    ap.add_argument("--plate-form", default="fp64_graph_warm", help="leg options used by --plate")
+    ap.add_argument("--plate-eps", default="1e-9,1e-12", help="--plate: Newton and PCGP tolerances")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     ap.add_argument("--oracle-ref", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
@@ -376,6 +428,11 @@ def main() -> int:
     if not legs or any(l not in LEGS for l in legs):
         raise SystemExit(f"--legs: choose from {sorted(LEGS)}")
     args.warmup = max(1, args.warmup)
+    if args.plate is not None:
+        if args.plate_form not in LEGS or args.plate_form == "fp32_learned":
+            raise SystemExit(f"--plate-form: choose from {sorted(set(LEGS) - {'fp32_learned'})}")
+        args.plate_eps = [float(x) for x in args.plate_eps.split(",")]
+        return plate_run(args)
 
     import workloads as W
     w = W.config(args.config, load_seed=0)

@@ -23,8 +23,11 @@
  *  - A handle is not thread safe: calls on one handle must not overlap.
  *
  * Numbering (bit-exact with the test oracle):
- *  - global node (i,j,k) -> i + (Nx+1)*(j + (Ny+1)*k); subdomain (I,J,K) ->
- *    I + Sx*(J + Sy*K); local nodes and elements lexicographic, x fastest.
+ *  - global node (i,j,k) -> i + (Nx+1)*(j + (Ny+1)*k); subdomains are the
+ *    boxes (I,J,K) that are not absent, numbered in the order of
+ *    I + Sx*(J + Sy*K) (so p = I + Sx*(J + Sy*K) when none is absent); local
+ *    nodes and elements lexicographic, x fastest.  Untorn (global) DOF
+ *    vectors cover the nodes that belong to some subdomain, node ascending.
  *  - torn vectors (length n_torn) stack the subdomain vectors in subdomain
  *    order; the local DOF of (local node a, component c) is 3a + c.
  *  - Gauss-point state arrays are ordered subdomain, local element, Gauss
@@ -73,6 +76,10 @@ typedef struct {
   int32_t dirichlet[6][3];      /* [face][comp] != 0: u_comp = 0 on that face;
                                    faces x=0, x=X, y=0, y=Y, z=0, z=Z           */
   double traction[6][3];        /* traction vector on each face at load factor 1 */
+  const uint8_t* absent_host;   /* NULL, or S[0]*S[1]*S[2] flags at I + S[0]*(J +
+                                   S[1]*K): nonzero leaves box (I,J,K) out of the
+                                   body (a hole or notch through the box
+                                   decomposition); faces it exposes are free    */
 } tfeti_problem;
 
 /* ---- solver options (host struct) ------------------------------------- */
@@ -290,7 +297,8 @@ int tfeti_graph_status(const tfeti_handle* h);
 /* Host-only (no device work): build the model of prob and report its sizes
  * (factor_bytes and precision are not set) and, when the pointers are not
  * NULL, B in CSR like tfeti_get_B_host (host buffers of m+1, nnz, nnz).  Lets
- * the index maps be checked without a GPU.  tile: 0, 16, 32 or 64. */
+ * the index maps be checked without a GPU.  tile: 0, 16, 32 or 64.  Errors:
+ * TFETI_E_INVALID, the reason in tfeti_last_error(NULL). */
 int tfeti_model_host(const tfeti_problem* prob_host, int32_t tile, tfeti_sizes* sizes_host, int64_t* nnz_host,
                      int64_t* rowptr_host, int64_t* col_host, double* val_host);
 

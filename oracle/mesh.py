@@ -4,7 +4,10 @@ Oracle (test infrastructure).
 
 Numbering (fixed so that index maps can be compared bit for bit):
 * global node (i, j, k) -> i + (Nx+1) * (j + (Ny+1) * k);
-* subdomain (I, J, K) -> I + Sx * (J + Sy * K);
+* subdomain (I, J, K) -> I + Sx * (J + Sy * K) when every box of the
+  decomposition is present; boxes listed in the workload's ``absent`` are
+  left out of the body (a hole through the decomposition) and the others
+  keep that order;
 * local nodes and local elements of a subdomain: lexicographic, x fastest;
 * torn DOF of (subdomain p, local node a, component c): off_p + 3 a + c,
   subdomains stacked in order (Section 4.1: the torn vector stacks the
@@ -62,10 +65,14 @@ class Mesh:
         starts = [np.concatenate([[0], np.cumsum(a)[:-1]]).astype(int) for a in (w.nx, w.ny, w.nz)]
         self.subs: list[Subdomain] = []
         off = 0
+        absent = set(tuple(b) for b in getattr(w, "absent", []) or [])
+        p = -1
         for K in range(Sz):
             for J in range(Sy):
                 for I in range(Sx):
-                    p = I + Sx * (J + Sy * K)
+                    if (I, J, K) in absent:
+                        continue
+                    p += 1
                     n = (w.nx[I], w.ny[J], w.nz[K])
                     e0 = (starts[0][I], starts[1][J], starts[2][K])
                     ni, nj, nk = n[0] + 1, n[1] + 1, n[2] + 1
@@ -88,6 +95,10 @@ class Mesh:
             off += s.n_dofs
         self.n_torn = off
         self.n_elems = sum(len(s.elems) for s in self.subs)
+        # global nodes that belong to some subdomain (all, unless boxes are absent)
+        self.used = np.zeros(self.n_gnodes, dtype=bool)
+        for s in self.subs:
+            self.used[s.l2g] = True
         self._build_dirichlet()
         self._build_B()
 
@@ -185,13 +196,20 @@ class Mesh:
 
     # ------------------------------------------------------------------ torn/untorn maps
     def untorn_index(self) -> np.ndarray:
-        """For each global DOF 3g + c, the torn DOF of its lowest-p copy."""
+        """For each global DOF 3g + c of a node that belongs to some subdomain
+        (node ascending), the torn DOF of its lowest-p copy."""
         first = np.full(self.n_gnodes, -1, dtype=np.int64)
         for s in self.subs:
             sel = first[s.l2g] < 0
             first[s.l2g[sel]] = s.off + 3 * np.nonzero(sel)[0]
-        idx = (first[:, None] + np.arange(3)[None, :]).ravel()
+        idx = (first[self.used][:, None] + np.arange(3)[None, :]).ravel()
         return idx
+
+    def used_dofs(self) -> np.ndarray:
+        """Global DOF indices 3g + c of the nodes that belong to some subdomain,
+        in the order of untorn_index."""
+        g = np.nonzero(self.used)[0]
+        return (3 * g[:, None] + np.arange(3)[None, :]).ravel()
 
     def tear(self, u_global: np.ndarray) -> np.ndarray:
         out = np.zeros(self.n_torn)

@@ -55,7 +55,8 @@ class Solver:
         self.untorn = m.untorn_index()
         self.f1_torn = m.torn_load(1.0)
         self.n_global = 3 * m.n_gnodes
-        self.free = ~m.dir_mask.ravel()
+        # free global DOFs: not fixed, and of a node in some subdomain
+        self.free = ~m.dir_mask.ravel() & np.repeat(m.used, 3)
         if linear == "tfeti":
             self.tf = TFETI(m)
             self.u = np.zeros(m.n_torn)

@@ -45,7 +45,7 @@ def elastic_tangent_blocks(mesh, log=None) -> sp.csr_matrix:
         key = tuple(int(v) for v in s.n)
         if key not in cache:
             w1 = dataclasses.replace(mesh.w, name="one", S=(1, 1, 1), nx=[key[0]], ny=[key[1]], nz=[key[2]],
-                                     extent=tuple(key[d] * mesh.h[d] for d in range(3)))
+                                     extent=tuple(key[d] * mesh.h[d] for d in range(3)), absent=[])
             one = Mesh(w1)
             ed = assembly.element_dofs_torn(one)
             ne = one.n_elems
@@ -64,7 +64,7 @@ def assembled_norm(mesh, v: np.ndarray) -> float:
     rg = np.zeros(3 * mesh.n_gnodes)
     for s in mesh.subs:
         np.add.at(rg.reshape(-1, 3), s.l2g, v[s.off:s.off + s.n_dofs].reshape(-1, 3))
-    return float(np.linalg.norm(rg[~mesh.dir_mask.ravel()]))
+    return float(np.linalg.norm(rg[~mesh.dir_mask.ravel() & np.repeat(mesh.used, 3)]))
 
 
 def elastic_first_step(w, log=None, fapply_seed: int | None = None):

@@ -27,7 +27,8 @@ class Material(C.Structure):
 
 class Problem(C.Structure):
     _fields_ = [("S", C.c_int32 * 3), ("n_host", C.POINTER(C.c_int32) * 3), ("extent", C.c_double * 3),
-                ("mat", Material), ("dirichlet", (C.c_int32 * 3) * 6), ("traction", (C.c_double * 3) * 6)]
+                ("mat", Material), ("dirichlet", (C.c_int32 * 3) * 6), ("traction", (C.c_double * 3) * 6),
+                ("absent_host", C.POINTER(C.c_uint8))]
 
 
 class Options(C.Structure):
@@ -156,6 +157,16 @@ def make_problem(w):
         for c in range(3):
             prob.dirichlet[f][c] = int(w.dirichlet[f][c])
             prob.traction[f][c] = float(w.traction[f][c])
+    absent = getattr(w, "absent", None)
+    if absent:
+        S = [len(w.nx), len(w.ny), len(w.nz)]
+        flags = (C.c_uint8 * (S[0] * S[1] * S[2]))()
+        for (I, J, K) in absent:
+            if not (0 <= I < S[0] and 0 <= J < S[1] and 0 <= K < S[2]):
+                raise ValueError(f"absent box {(I, J, K)} outside the {S[0]} x {S[1]} x {S[2]} decomposition")
+            flags[I + S[0] * (J + S[1] * K)] = 1
+        keep.append(flags)
+        prob.absent_host = C.cast(flags, C.POINTER(C.c_uint8))
     return prob, keep
 
 

@@ -1327,6 +1327,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   if (h->opt.preconditioner < 0 || h->opt.preconditioner > 2)
     return fail(h, TFETI_E_INVALID, "preconditioner must be 0 (none), 1 (lumped) or 2 (Dirichlet)");
   h->dirichlet = h->opt.preconditioner == 2;
+  if (h->dirichlet && !M.interior_error.empty()) return fail(h, TFETI_E_INVALID, M.interior_error);
   if (h->dirichlet) {
     // interior problems: panels for the largest layout among the tiles in
     // use (assign_interior_panels leaves the current tile's layout set)
@@ -1561,7 +1562,7 @@ void tfeti_destroy(tfeti_handle* h) {
 
 const char* tfeti_last_error(const tfeti_handle* h) {
   if (h) return h->err.c_str();
-  const char* e = noalloc_error();
+  const char* e = call_error();
   return e ? e : "null handle";
 }
 
@@ -1921,12 +1922,22 @@ int return_map(const tfeti_material* mat, int64_t npts, const double* sigma_k, c
 
 extern "C" int tfeti_model_host(const tfeti_problem* prob, int32_t tile, tfeti_sizes* sizes, int64_t* nnz,
                                 int64_t* rowptr, int64_t* col, double* val) {
-  if (!prob || !sizes) return TFETI_E_INVALID;
+  set_call_error("");
+  if (!prob || !sizes) {
+    set_call_error("tfeti_model_host: null problem or sizes");
+    return TFETI_E_INVALID;
+  }
   if (tile == 0) tile = 32;
-  if (tile != 16 && tile != 32 && tile != 64) return TFETI_E_INVALID;
+  if (tile != 16 && tile != 32 && tile != 64) {
+    set_call_error("tfeti_model_host: tile must be 0, 16, 32 or 64");
+    return TFETI_E_INVALID;
+  }
   HostModel M;
   std::string msg = build_model(*prob, M);
-  if (!msg.empty()) return TFETI_E_INVALID;
+  if (!msg.empty()) {
+    set_call_error("tfeti_model_host: " + msg);
+    return TFETI_E_INVALID;
+  }
   int64_t pe = assign_panels(M, tile);
   sizes->n_sub = M.n_sub;
   sizes->n_torn = M.n_torn;

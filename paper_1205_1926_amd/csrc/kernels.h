@@ -243,8 +243,10 @@ void launch_dirichlet_c(const DualMaps& M, const NbGroups& kti, const SubDev* is
                         const double* sint, const TV* ktiv, double* out, const int32_t* done, hipStream_t st);
 
 int reduction_blocks(int64_t n);
-// message of the last failed allocation-free call on this thread (or nullptr)
-const char* noalloc_error();
+// message of the last failed handle-less call on this thread (or nullptr):
+// tfeti_mlp_forward_noalloc and tfeti_model_host record theirs here
+const char* call_error();
+void set_call_error(const std::string& msg);
 // scalar finalizers (single thread); see dual.hip
 void launch_finalize(int kind, PcgScalars* S, const double* partials, int nparts, hipStream_t st);
 enum FinalizeKind { FIN_WW = 0, FIN_YW = 1, FIN_PQ = 2, FIN_RREF = 3, FIN_SUM_TMP0 = 4 };

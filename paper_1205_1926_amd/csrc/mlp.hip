@@ -322,7 +322,9 @@ static void* scratch_ptr(int dev) {
   return g_scratch_ptr[dev];
 }
 
-const char* noalloc_error() { return g_noalloc_err.empty() ? nullptr : g_noalloc_err.c_str(); }
+const char* call_error() { return g_noalloc_err.empty() ? nullptr : g_noalloc_err.c_str(); }
+
+void set_call_error(const std::string& msg) { g_noalloc_err = msg; }
 
 }  // namespace tfeti
 

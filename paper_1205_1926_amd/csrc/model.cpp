@@ -96,8 +96,11 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   const int64_t Nx1 = M.N[0] + 1, Ny1 = M.N[1] + 1, Nz1 = M.N[2] + 1;
   M.n_gnodes = Nx1 * Ny1 * Nz1;
   M.n_gdof = 3 * M.n_gnodes;
-  M.n_sub = (int64_t)M.S[0] * M.S[1] * M.S[2];
-  if (M.n_sub > (1 << 20)) return "too many subdomains";
+  const int64_t n_box = (int64_t)M.S[0] * M.S[1] * M.S[2];
+  if (n_box > (1 << 20)) return "too many subdomains";
+  M.n_sub = 0;
+  for (int64_t q = 0; q < n_box; ++q) M.n_sub += (P.absent_host && P.absent_host[q]) ? 0 : 1;
+  if (M.n_sub == 0) return "every box of the decomposition is absent";
 
   // ---- subdomains ----
   std::vector<int32_t> start[3];
@@ -112,10 +115,12 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   M.subs.resize(M.n_sub);
   M.sub_e0.resize(3 * M.n_sub);
   int64_t dof_off = 0, elem_off = 0, band_off = 0;
+  int64_t p = -1;
   for (int K = 0; K < M.S[2]; ++K)
     for (int J = 0; J < M.S[1]; ++J)
       for (int I = 0; I < M.S[0]; ++I) {
-        int64_t p = I + (int64_t)M.S[0] * (J + (int64_t)M.S[1] * K);
+        if (P.absent_host && P.absent_host[I + (int64_t)M.S[0] * (J + (int64_t)M.S[1] * K)]) continue;
+        ++p;
         SubDev& s = M.subs[p];
         std::memset(&s, 0, sizeof(SubDev));
         s.n[0] = M.slab[0][I];
@@ -222,12 +227,12 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   std::vector<Ent> eG, eU;
   std::vector<int64_t> rnodeG, rnodeU;   // global node of each row
   std::vector<int8_t> rslotG, rslotU;    // slot 7 c + index within the node
-  M.g_free.assign(M.n_gdof, 1);
+  std::vector<uint8_t> gfree_full(M.n_gdof, 1);
   for (int64_t g = 0; g < M.n_gnodes; ++g) {
     int32_t k = cnt[g + 1] - cnt[g];
     for (int c = 0; c < 3; ++c) {
       if (dirichlet(g, c)) {
-        M.g_free[3 * g + c] = 0;
+        gfree_full[3 * g + c] = 0;
         for (int32_t t = 0; t < k; ++t) {
           eU.push_back({cp_sub[cnt[g] + t], cp_loc[cnt[g] + t], c, 1.0});
           rpU.push_back((int64_t)eU.size());
@@ -466,7 +471,13 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
       if (cnt_in == 0) continue;
       int64_t box = 1;
       for (int d = 0; d < 3; ++d) box *= hi[d] - lo[d] + 1;
-      if (box != cnt_in) return "the interior nodes of a subdomain do not form a box";
+      if (box != cnt_in) {
+        // a hole's edge or corner leaves interface nodes between free faces:
+        // the lumped preconditioner still applies, the Dirichlet one is refused
+        M.interior_error = "the interior nodes of subdomain " + std::to_string(p) +
+                           " do not form a box (Dirichlet preconditioner unavailable)";
+        break;
+      }
       for (int d = 0; d < 3; ++d) {
         M.ilo[3 * p + d] = lo[d];
         si.N[d] = hi[d] - lo[d] + 1;
@@ -488,6 +499,11 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
       si.band_off = iband;
       ioff += si.ndof;
       iband += (int64_t)si.npad * si.Wb;
+    }
+    if (!M.interior_error.empty()) {
+      M.isubs.assign(M.n_sub, SubDev{});
+      M.ilo.assign(3 * M.n_sub, 0);
+      ioff = iband = 0;
     }
     M.n_int = ioff;
     M.iband_entries = iband;
@@ -544,6 +560,7 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
       }
     };
     auto interior = [&](int64_t p, int32_t a) { return M.isubs[p].ndof > 0 && !node_touched[M.subs[p].dof_off / 3 + a]; };
+    if (M.interior_error.empty()) {
     // K_it: every DOF of an interior node (rows without a touched neighbour
     // too, so that every interior entry is written); output at its interior DOF
     build(M.kit, true,
@@ -570,22 +587,32 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
             }
           },
           interior);
+    }
     if (M.n_int >= (int64_t)1 << 31) return "too many interior DOFs for 32-bit indices";
   }
 
-  // ---- untorn maps ----
+  // ---- untorn maps: the global DOFs of the nodes in some subdomain (all of
+  //      them unless boxes are absent), node ascending ----
+  int64_t used_nodes = 0;
+  for (int64_t g = 0; g < M.n_gnodes; ++g) used_nodes += cnt[g + 1] > cnt[g] ? 1 : 0;
+  M.n_gdof = 3 * used_nodes;
   M.g_first.resize(M.n_gdof);
   M.g_rp.assign(M.n_gdof + 1, 0);
+  M.g_free.assign(M.n_gdof, 1);
   M.g_copies.clear();
   M.g_copies.reserve(3 * cp_sub.size());
-  for (int64_t g = 0; g < M.n_gnodes; ++g)
+  for (int64_t g = 0, gu = 0; g < M.n_gnodes; ++g) {
+    if (cnt[g + 1] == cnt[g]) continue;
     for (int c = 0; c < 3; ++c) {
-      int64_t gd = 3 * g + c;
+      const int64_t gd = 3 * gu + c;
       for (int32_t t = cnt[g]; t < cnt[g + 1]; ++t)
         M.g_copies.push_back(M.subs[cp_sub[t]].dof_off + 3 * cp_loc[t] + c);
       M.g_first[gd] = M.subs[cp_sub[cnt[g]]].dof_off + 3 * cp_loc[cnt[g]] + c;
       M.g_rp[gd + 1] = (int32_t)M.g_copies.size();
+      M.g_free[gd] = gfree_full[3 * g + c];
     }
+    ++gu;
+  }
 
   // ---- colouring of elements ----
   M.elem_sub.resize(M.n_elem);

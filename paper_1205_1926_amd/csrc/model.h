@@ -101,6 +101,7 @@ struct HostModel {
   std::vector<SubDev> isubs;            // n_sub; ndof 0 where no node is interior
   std::vector<int32_t> ilo;             // 3 per subdomain: first interior node per local axis
   int64_t n_int = 0;                    // interior DOFs of all subdomains
+  std::string interior_error;           // non-empty: some interior is not a box
   int64_t iband_entries = 0;            // sum npad * Wb of the interior problems
   NbGroupsHost kit;                     // K_it: interior rows x touched neighbour nodes
   NbGroupsHost kti;                     // K_ti: touched rows x interior neighbour nodes

@@ -249,7 +249,7 @@ def model_host(workload, tile: int = 0):
     nnz = C.c_int64()
     rc = lib.tfeti_model_host(C.byref(prob), tile, C.byref(s), C.byref(nnz), None, None, None)
     if rc < 0:
-        raise A.TfetiError(f"tfeti_model_host: {rc}")
+        raise A.TfetiError(f"tfeti_model_host: {rc}: {lib.tfeti_last_error(None).decode()}")
     sizes = A.struct_dict(s)
     rp = np.zeros(sizes["m"] + 1, dtype=np.int64)
     col = np.zeros(nnz.value, dtype=np.int64)
@@ -257,7 +257,7 @@ def model_host(workload, tile: int = 0):
     rc = lib.tfeti_model_host(C.byref(prob), tile, C.byref(s), C.byref(nnz), rp.ctypes.data_as(C.c_void_p),
                               col.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p))
     if rc < 0:
-        raise A.TfetiError(f"tfeti_model_host: {rc}")
+        raise A.TfetiError(f"tfeti_model_host: {rc}: {lib.tfeti_last_error(None).decode()}")
     return sizes, rp, col, val
 
 

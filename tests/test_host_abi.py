@@ -41,11 +41,20 @@ def test_library_exports_every_declared_symbol():
     assert set(_capi.SIGNATURES) == set(declared_functions())
 
 
+def holed_cube():
+    """3 x 3 x 2 boxes with the centre column and one corner box left out:
+    nodes on the hole's faces are shared by fewer subdomains."""
+    w = W.small_cube(S=(3, 3, 2), n=(2, 2, 2))
+    w.absent = [(1, 1, 0), (1, 1, 1), (2, 2, 1)]
+    return w
+
+
 @pytest.mark.parametrize("w", [W.config(0), W.config(1), W.config(2), W.config(4),
                                W.small_cube(S=(3, 2, 2), n=(2, 3, 2)),
                                W.patch_test(S=(2, 2, 3), n=(2, 1, 2)),
                                W.Workload("uneven", (2, 3, 2), [3, 5], [2, 4, 3], [6, 2],
-                                          dirichlet=[[1, 0, 0], [0, 0, 0], [0, 1, 0], [0, 0, 0], [1, 1, 1], [0, 0, 0]])])
+                                          dirichlet=[[1, 0, 0], [0, 0, 0], [0, 1, 0], [0, 0, 0], [1, 1, 1], [0, 0, 0]]),
+                               W.plate_notch(1), W.plate_notch(2), holed_cube()])
 def test_B_maps_bit_exact_with_oracle(w):
     from paper_1205_1926_amd import model_host
     sizes, rp, col, val = model_host(w)
@@ -98,9 +107,26 @@ def test_skyline_count_by_brute_force():
     assert sizes["skyline_entries"] == env
 
 
+def test_holed_decomposition_refuses_only_dirichlet():
+    """Where a hole's edge leaves interface nodes between free faces the
+    interior of a subdomain is no box: the model still builds (lumped
+    preconditioner), and the reason is kept for a Dirichlet set-up."""
+    from paper_1205_1926_amd import model_host
+    sizes, *_ = model_host(holed_cube())
+    assert sizes["n_sub"] == 15
+
+
 def test_invalid_problem_rejected():
     from paper_1205_1926_amd import model_host, TfetiError
     w = W.small_cube()
     w.material.H = 0.0
     with pytest.raises(TfetiError):
+        model_host(w)
+    w = W.small_cube(S=(1, 2, 1))
+    w.absent = [(0, 0, 0), (0, 1, 0)]
+    with pytest.raises(TfetiError):
+        model_host(w)
+    w = W.small_cube(S=(1, 2, 1))
+    w.absent = [(0, 2, 0)]
+    with pytest.raises(ValueError):
         model_host(w)

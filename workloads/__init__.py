@@ -17,6 +17,7 @@ sigma_y = 450, H_m = 10000.
 
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 from typing import List, Tuple
 
@@ -76,13 +77,22 @@ class Workload:
     eps_newton: float = 1e-10
     eps_pcg: float = 1e-8
     precision: str = "fp64"                 # "fp64" or "fp32" (factor precision)
+    # boxes (I, J, K) of the decomposition left out of the body (a hole or
+    # notch through it); their exposed faces carry no load and no constraint
+    absent: List[Tuple[int, int, int]] = field(default_factory=list)
+    # load path: "ramp" k/N, or "sine": sin(pi/2 k/N), the amplitude
+    # 400 sin(2 pi t) of the paper's benchmark at t_k = k (1/4) / N
+    load_kind: str = "ramp"
 
     @property
     def n_elements(self) -> int:
         return sum(self.nx) * sum(self.ny) * sum(self.nz)
 
     def load_factor(self, k: int) -> float:
-        """Linear ramp: factor k/N at the end of step k (k = 1..N)."""
+        """Load factor at the end of step k (k = 1..N): k/N on the linear
+        ramp, sin(pi/2 k/N) on the quarter sine."""
+        if self.load_kind == "sine":
+            return math.sin(0.5 * math.pi * k / self.steps)
         return k / self.steps
 
 
@@ -156,6 +166,38 @@ def small_cube(S=(2, 2, 2), n=(2, 2, 2), amp: float = 400.0, steps: int = 1,
                  [n[0]] * S[0], [n[1]] * S[1], [n[2]] * S[2],
                  dirichlet=_clamped_bottom(), steps=steps)
     w.traction[FACE_Z1] = [shear, 0.0, -amp]
+    return w
+
+
+def plate_notch(level: int = 1, steps: int = 1, amp: float = 400.0, eps_newton: float = 1e-9,
+                eps_pcg: float = 1e-12) -> Workload:
+    """Stand-in for the paper's benchmark (Section 5): an eighth of a
+    20 x 20 x 2 plate, x, y in [0, 10], z in [0, 1], with symmetry rollers on
+    x = 0 (u_x), y = 0 (u_y) and z = 0 (u_z), loaded in tension by the
+    traction (0, g(t), 0) on y = 10 with g(t) = amp sin(2 pi t), t in
+    [0, 1/4], in `steps` equal time steps (the paper's discretizations (a)
+    steps = 1 and (b) steps = 8).  The paper's hole of radius 1 and its
+    tetrahedral meshes are not available; the hole here is the square
+    [0, 1] x [0, 1] through the thickness, boxes of the decomposition left
+    out, so that every subdomain stays a box.  Elements of 1 / (4 level).
+    Level 1: boxes 1, 3, 3, 3 units wide in x and y, one in z (15
+    subdomains, 6 336 elements).  Level >= 2: cubic boxes of at most 8
+    elements per axis, k per unit length (level 2: 99 subdomains of 8^3,
+    50 688 elements; level 4: 792 subdomains of 8^3, 405 504 elements)."""
+    e = 4 * level                              # elements per unit length
+    if level == 1:
+        k, bx, bz = 1, [e, 3 * e, 3 * e, 3 * e], [e]
+    else:
+        k = next(k for k in range(1, e + 1) if e % k == 0 and e // k <= 8)
+        bx, bz = [e // k] * (10 * k), [e // k] * k
+    w = Workload(f"plate_notch_l{level}_n{steps}", (len(bx), len(bx), len(bz)), bx, list(bx), bz,
+                 extent=(10.0, 10.0, 1.0), steps=steps, eps_newton=eps_newton, eps_pcg=eps_pcg,
+                 load_kind="sine")
+    w.dirichlet[FACE_X0] = [1, 0, 0]
+    w.dirichlet[FACE_Y0] = [0, 1, 0]
+    w.dirichlet[FACE_Z0] = [0, 0, 1]
+    w.traction[FACE_Y1] = [0.0, amp, 0.0]
+    w.absent = [(i, j, m) for m in range(len(bz)) for j in range(k) for i in range(k)]
     return w
 
 
