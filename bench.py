@@ -37,6 +37,13 @@ mesh; plus the oracle's full-size single-core timings of load step 1.
 
 One compact JSON line goes to stdout; progress and per-iteration detail go
 to stderr (and, with --detail PATH, to a JSON file).
+
+--plate LEVEL runs the notched-plate benchmark instead (the box stand-in for
+the paper's Section 5 plate with a hole): time discretizations (a) one step
+and (b) eight steps to t = 1/4, one stderr row per Newton iteration (PCGP
+iterations, plastic elements, increment criterion, relative residual, time)
+and one JSON line with the totals and the two discretizations' final plastic
+element counts.
 """
 
 from __future__ import annotations
@@ -336,6 +343,7 @@ def plate_run(args) -> int:
 
     import workloads as W
     from paper_1205_1926_amd import GpuSolver
+    from paper_1205_1926_amd import _capi as A
 
     opts = LEGS[args.plate_form]
     out = {"metric": "notched plate: Newton iterations, PCGP iterations, plastic elements and wall time per "
@@ -353,11 +361,20 @@ def plate_run(args) -> int:
         t0 = time.perf_counter()
         newton = pcg = 0
         for k in range(steps):
-            for r in g.load_step():
+            # Newton iterations one call at a time, each reported as it ends
+            g.begin_load_step()
+            while True:
+                rc, r = g.newton_step()
+                if rc == A.TFETI_CONVERGED:
+                    break
                 newton += 1
                 pcg += r["pcg_iters"]
                 log(f"plate ({disc}) {k + 1:2d} {r['iteration']:2d} {r['pcg_iters']:4d} {r['plastic_elements']:7d} "
                     f"{r['crit']:.2e} {r['relres']:.2e} {r['ms_total']:.1f}")
+                if rc == A.TFETI_W_NEWTON_MAXIT:
+                    log(f"plate ({disc}): load step {k + 1} stopped at the Newton iteration limit")
+                    break
+            g.commit()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         kappa = g.state()["kappa"].reshape(-1, 8)

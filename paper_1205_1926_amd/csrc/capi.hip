@@ -1274,6 +1274,9 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     h->max_ndof = std::max(h->max_ndof, s.ndof);
     h->bmax = std::max(h->bmax, s.b);
   }
+  if (band_cholesky_nb(h->bmax, sizeof(double)) == 0)
+    return fail(h, TFETI_E_INVALID,
+                "a subdomain's half bandwidth (" + std::to_string(h->bmax) + ") does not fit the factorization kernel's LDS");
   {
     int dev = 0, lds = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -1345,6 +1348,8 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
         h->ipad_max = std::max(h->ipad_max, M.isubs[p].npad);
         h->ibmax = std::max(h->ibmax, M.isubs[p].b);
       }
+    if (h->ibmax > 0 && band_cholesky_nb(h->ibmax, sizeof(double)) == 0)
+      return fail(h, TFETI_E_INVALID, "an interior block's half bandwidth does not fit the factorization kernel's LDS");
     std::stable_sort(iorder.begin(), iorder.end(),
                      [&](int32_t a, int32_t b) { return M.isubs[a].npad > M.isubs[b].npad; });
     h->n_iorder = (int64_t)iorder.size();
@@ -1528,12 +1533,19 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     std::vector<SubDev> csv{cs};
     SubDev* d_cs = nullptr;
     RC(upload(h, &d_cs, csv));
+    std::vector<int32_t> cidx(M.lc);
+    for (int64_t g = 0; g < M.lc; ++g) cidx[g] = 6 * M.cpos[g / 6] + (int32_t)(g % 6);
+    int32_t* d_cidx = nullptr;
+    RC(upload(h, &d_cidx, cidx));
     HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int32_t), h->st));
-    launch_band_cholesky<double>(d_cs, 1, nullptr, d_cb, h->d_fail, M.bc, 0, h->st);
+    if (launch_band_cholesky<double>(d_cs, 1, nullptr, d_cb, h->d_fail, M.bc, 0, h->st) != 0)
+      return fail(h, TFETI_E_INVALID,
+                  "the band of the coarse matrix G G^T (half bandwidth " + std::to_string(M.bc) +
+                      ") does not fit the factorization kernel's LDS");
     double* d_ct = nullptr;  // transposed factor (setup scratch)
     RC(dalloc(h, &d_ct, (int64_t)M.lc_pad * (M.bc + 1)));
     launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st, d_ct);
-    launch_coarse_pack(M.lc, h->d_Ginv, h->d_Gpk, h->st);
+    launch_coarse_pack(M.lc, h->d_Ginv, d_cidx, h->d_Gpk, h->st);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));

@@ -16,8 +16,8 @@
 //     (initialized with the panel's entries) and streams its rows of L from
 //     memory 16 columns at a time, the next chunk's loads in flight;
 //  F. the accumulators become the LDS panel;
-//  D. the panel is factored column by column, each row in a thread's
-//     registers, one barrier per column;
+//  D. the diagonal tile is factored by one wavefront (one row per lane, no
+//     workgroup barrier), then the rows below are solved against it;
 //  W. the panel is written back.
 // Finished columns are only read, so the band is written once per entry
 // and no store waits on the matrix-core chain.
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
                                                             const int32_t* __restrict__ list,
                                                             double* __restrict__ W, int32_t* __restrict__ fail,
                                                             int LB) {
-  static_assert(NB % 16 == 0, "tile of whole 16 x 16 blocks");
+  static_assert(NB % 16 == 0 && NB <= 64, "tile of whole 16 x 16 blocks, one row per lane of a wavefront");
   extern __shared__ __align__(16) unsigned char smem[];
   // phase U: the tile rows' negated L over the update columns (NB x LB);
   // phases F..W: the panel (rows x LS), whose diagonal tile's rows hold L in
@@ -201,35 +201,37 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
       }
     }
     __syncthreads();
-    // ---- D. panel factorization, column by column: thread r keeps row r
-    //      of the panel in registers (rows past the first 256 follow once
-    //      the tile is done); at column j every row below j takes
-    //      L[r][j] = (x_r[j] - x_r[0:j] . L[j][0:j]) / L[j][j] with row j
-    //      read from LDS (one address for all lanes) and 1 / L[j][j] from
-    //      the pivot, and row j+1 completes its diagonal entry and publishes
-    //      itself and the reciprocal for the next column; one barrier per
-    //      column.  Dot products run as two interleaved partial sums. ----
-    {
-      const int r = tid;
+    // ---- D. the diagonal tile by wavefront 0, one row per lane: at column j
+    //      lane j completes its diagonal entry (its sum of squares is kept
+    //      as the row is finished) and publishes the reciprocal, then every
+    //      lane r > j forms L[r][j] = (x_r[j] - x_r[0:j] . L[j][0:j]) / L[j][j]
+    //      with row j read from LDS (one address for all lanes) and stores it
+    //      for the columns to come.  The lanes of one wavefront see each
+    //      other's LDS stores in program order, so the tile needs no
+    //      workgroup barrier; lanes jb..63 finish rows jb..63 of the panel on
+    //      the way.  Dot products run as two interleaved partial sums. ----
+    if (wave == 0) {
+      const int r = lane;
       const bool have = r < nr;
       double x[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = have ? P[r * LS + j] : 0.0;
+      for (int j = 0; j < NB; ++j) x[j] = have ? P[(have ? r : 0) * LS + j] : 0.0;
+      double sa = 0.0, sb = 0.0;
       bool bad = false;
-      if (r == 0 && jb > 0) {
-        double d = x[0];
-        if (!(d > 0.0)) {
-          bad = true;
-          d = 1.0;
-        }
-        x[0] = sqrt(d);
-        P[0] = x[0];
-        s_rcp[0] = 1.0 / x[0];
-      }
-      __syncthreads();
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         if (j < jb) {
+          if (r == j) {
+            double d = x[j] - (sa + sb);
+            if (!(d > 0.0)) {
+              bad = true;
+              d = 1.0;
+            }
+            x[j] = sqrt(d);
+            P[j * LS + j] = x[j];
+            s_rcp[j] = 1.0 / x[j];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           if (have && r > j) {
             double v0 = x[j], v1 = 0.0;
 #pragma unroll
@@ -240,39 +242,21 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
                 v0 -= x[k] * P[j * LS + k];
             }
             x[j] = (v0 + v1) * s_rcp[j];
-            if (r == j + 1 && j + 1 < jb) {
-              double d0 = x[j + 1], d1 = 0.0;
-#pragma unroll
-              for (int k = 0; k <= j; ++k) {
-                if (k & 1)
-                  d1 -= x[k] * x[k];
-                else
-                  d0 -= x[k] * x[k];
-              }
-              double d = d0 + d1;
-              if (!(d > 0.0)) {
-                bad = true;
-                d = 1.0;
-              }
-              x[j + 1] = sqrt(d);
-              s_rcp[j + 1] = 1.0 / x[j + 1];
-#pragma unroll
-              for (int k = 0; k <= j + 1; ++k) P[r * LS + k] = x[k];
-            }
+            P[r * LS + j] = x[j];
+            if (j & 1)
+              sb += x[j] * x[j];
+            else
+              sa += x[j] * x[j];
           }
-          __syncthreads();
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
       }
       if (bad) s_fail = 1;
-      if (have) {
-#pragma unroll
-        for (int j = 0; j < NB; ++j) P[r * LS + j] = x[j];
-      }
     }
     __syncthreads();
-    // ---- rows past the first 256: solved against the finished diagonal
+    // ---- rows 64.. of the panel: solved against the finished diagonal
     //      tile, independently ----
-    for (int r = 256 + tid; r < nr; r += 256) {
+    for (int r = 64 + tid; r < nr; r += 256) {
       double x[NB];
 #pragma unroll
       for (int j = 0; j < NB; ++j) x[j] = P[r * LS + j];

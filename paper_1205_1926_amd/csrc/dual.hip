@@ -210,14 +210,16 @@ __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
 }
 }  // namespace
 
+// G is the inverse in the coarse numbering; cidx maps a subdomain-order
+// coarse unknown to its coarse position
 __global__ __launch_bounds__(256) void coarse_pack_kernel(int64_t l, const double* __restrict__ G,
-                                                          double* __restrict__ P) {
+                                                          const int32_t* __restrict__ cidx, double* __restrict__ P) {
   int I, J;
   tile_ij(blockIdx.x, I, J);
   double* out = P + (int64_t)blockIdx.x * CT * CT;
   for (int q = threadIdx.x; q < CT * CT; q += 256) {
     const int64_t gi = (int64_t)I * CT + q / CT, gj = (int64_t)J * CT + q % CT;
-    out[q] = (gi < l && gj < l) ? G[gi * l + gj] : 0.0;
+    out[q] = (gi < l && gj < l) ? G[(int64_t)cidx[gi] * l + cidx[gj]] : 0.0;
   }
 }
 
@@ -294,9 +296,9 @@ int64_t coarse_tiles(int64_t l) {
   return nT * (nT + 1) / 2;
 }
 
-void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream_t st) {
+void launch_coarse_pack(int64_t l, const double* Ginv, const int32_t* cidx, double* packed, hipStream_t st) {
   const int64_t nt = coarse_tiles(l);
-  if (nt > 0) coarse_pack_kernel<<<dim3((unsigned)nt), dim3(256), 0, st>>>(l, Ginv, packed);
+  if (nt > 0) coarse_pack_kernel<<<dim3((unsigned)nt), dim3(256), 0, st>>>(l, Ginv, cidx, packed);
 }
 
 void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double scale, const int32_t* done,

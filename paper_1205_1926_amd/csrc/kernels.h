@@ -195,7 +195,9 @@ void launch_coarse_gemv(const DualMaps& M, const double* c, double* a, double sc
                         hipStream_t st);
 // tiles of the packed lower triangle of an l x l symmetric matrix (64 x 64)
 int64_t coarse_tiles(int64_t l);
-void launch_coarse_pack(int64_t l, const double* Ginv, double* packed, hipStream_t st);
+// Ginv in the coarse numbering; cidx (l entries) maps subdomain-order unknowns
+// to coarse positions
+void launch_coarse_pack(int64_t l, const double* Ginv, const int32_t* cidx, double* packed, hipStream_t st);
 // out = (x ? x : 0) - sign * G^T a; optional partial sums of out.out, or of
 // out.dotv when dotv is given
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,

@@ -663,12 +663,39 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   }
 
   // ---- coarse matrix G G^T (G = R^T B^T), lower row-band ----
+  // The coarse unknowns are numbered by the boxes in lexicographic order with
+  // the axis of fewest boxes fastest, which keeps the band of G G^T narrow on
+  // flat decompositions (20 x 20 x 2 boxes: neighbours 43 positions apart
+  // instead of 421); the inverse is gathered back to subdomain order.
   M.lc = (int32_t)(6 * M.n_sub);
+  {
+    int ax[3] = {0, 1, 2};
+    std::stable_sort(ax, ax + 3, [&](int x, int y) { return M.S[x] < M.S[y]; });
+    std::vector<int32_t> box_p((size_t)n_box, -1);
+    {
+      int64_t q = 0;
+      for (int K = 0; K < M.S[2]; ++K)
+        for (int J = 0; J < M.S[1]; ++J)
+          for (int I = 0; I < M.S[0]; ++I) {
+            const int64_t bi = I + (int64_t)M.S[0] * (J + (int64_t)M.S[1] * K);
+            if (!(P.absent_host && P.absent_host[bi])) box_p[bi] = (int32_t)q++;
+          }
+    }
+    M.cpos.assign(M.n_sub, 0);
+    int32_t pos = 0;
+    int c[3];
+    for (c[ax[2]] = 0; c[ax[2]] < M.S[ax[2]]; ++c[ax[2]])
+      for (c[ax[1]] = 0; c[ax[1]] < M.S[ax[1]]; ++c[ax[1]])
+        for (c[ax[0]] = 0; c[ax[0]] < M.S[ax[0]]; ++c[ax[0]]) {
+          const int32_t q = box_p[c[0] + (int64_t)M.S[0] * (c[1] + (int64_t)M.S[1] * c[2])];
+          if (q >= 0) M.cpos[q] = pos++;
+        }
+  }
   int64_t maxdp = 0;
   for (int64_t r = 0; r < M.m; ++r)
     for (int64_t e = M.b_rowptr[r]; e < M.b_rowptr[r + 1]; ++e)
       for (int64_t e2 = M.b_rowptr[r]; e2 < M.b_rowptr[r + 1]; ++e2)
-        maxdp = std::max<int64_t>(maxdp, std::abs((int64_t)e_sub[e] - e_sub[e2]));
+        maxdp = std::max<int64_t>(maxdp, std::abs((int64_t)M.cpos[e_sub[e]] - M.cpos[e_sub[e2]]));
   M.bc = (int32_t)(6 * maxdp + 5);
   M.lc_pad = (M.lc + kPadRows - 1) / kPadRows * kPadRows;
   const int64_t Wc = M.bc + 1;
@@ -678,7 +705,7 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
     int64_t e0 = M.b_rowptr[r], e1 = M.b_rowptr[r + 1];
     for (int64_t e = e0; e < e1; ++e)
       for (int64_t e2 = e0; e2 < e1; ++e2) {
-        int64_t pa = e_sub[e], pb = e_sub[e2];
+        const int64_t pa = M.cpos[e_sub[e]], pb = M.cpos[e_sub[e2]];
         if (pa < pb) continue;
         const double* Ra = &M.R_full[6 * M.b_col[e]];
         const double* Rb = &M.R_full[6 * M.b_col[e2]];

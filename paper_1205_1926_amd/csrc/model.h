@@ -86,6 +86,8 @@ struct HostModel {
   std::vector<double> f1;
   // coarse matrix G G^T in lower row-band form
   int32_t lc = 0, bc = 0, lc_pad = 0;
+  std::vector<int32_t> cpos;            // coarse position of each subdomain: boxes in
+                                        // lexicographic order, fewest boxes fastest
   std::vector<double> GGt_band;         // lc_pad rows of (bc + 1)
   // interface nodes of the learned warm start: nodes carrying multiplier rows
   int64_t n_wnodes = 0;
