@@ -88,6 +88,9 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   T* part0 = xs0 + NR * A.vec_stride;
   int32_t* fcr = reinterpret_cast<int32_t*>(part0 + NR * NT);
   const int VS = A.vec_stride;
+  // the diagonal tile of the block row being solved, for tiles too large to
+  // hold in wavefront 0's registers (after the envelope table, 16-byte aligned)
+  T* dg = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(fcr) + ((size_t)VS * sizeof(T) / 4 + 15) / 16 * 16);
 
   if (A.done && *A.done) return;
   const int tid = threadIdx.x;
@@ -154,6 +157,11 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   // every lane's first batch of chunks of the next block row (before the
   // second barrier, while wave 0 solves the diagonal block).
   constexpr bool DIAG_PRE = TS / V <= 8;
+  // larger tiles: every lane fetches DGU vectors of the diagonal tile (a
+  // contiguous TS x TS block of the panel) with the off-diagonal chunks and
+  // stores them in LDS before the first barrier, so that wavefront 0's
+  // diagonal step reads LDS instead of waiting on memory
+  constexpr int DGV = TS * TS / V, DGU = DIAG_PRE ? 1 : (DGV + NT - 1) / NT;
 
   // ---- forward substitution L y = x (in place) ----
   {
@@ -188,6 +196,17 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
 #pragma unroll
       for (int u = 0; u < UNR; ++u) Lp[u] = __builtin_nontemporal_load(chunk(off, cc0 + u * RPT));
     for (int I = 0; I < nb; ++I) {
+      VT dgv[DGU];
+      if constexpr (!DIAG_PRE) {
+        // chunk q = dc TS + row, needed where dc V <= row (the inverse of a
+        // lower triangle is lower); the others are never read
+        const VT* dsrc = reinterpret_cast<const VT*>(P + off + (int64_t)nco * TS * V);
+#pragma unroll
+        for (int u = 0; u < DGU; ++u) {
+          const int q = tid + u * NT;
+          if (q < DGV && (q / TS) * V <= q % TS) dgv[u] = __builtin_nontemporal_load(dsrc + q);
+        }
+      }
       T acc[NR];
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[k] = T(0);
@@ -218,11 +237,21 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           acc[k] += vdot<VT, V>(L, y);
         }
       }
+      if constexpr (!DIAG_PRE) {
+#pragma unroll
+        for (int u = 0; u < DGU; ++u) {
+          const int q = tid + u * NT;
+          if (q < DGV && (q / TS) * V <= q % TS) *reinterpret_cast<VT*>(dg + (int64_t)q * V) = dgv[u];
+        }
+      }
       // the inverse of a lower triangle is lower: lane tid < TS needs the
       // diagonal chunks dc with dc V <= tid
       auto diag = [&](int dc) -> VT {
-        return (tid < TS && dc * V <= tid) ? *reinterpret_cast<const VT*>(P + off + ((int64_t)(nco + dc) * TS + tid) * V)
-                                           : VT(T(0));
+        if constexpr (DIAG_PRE)
+          return (tid < TS && dc * V <= tid) ? *reinterpret_cast<const VT*>(P + off + ((int64_t)(nco + dc) * TS + tid) * V)
+                                             : VT(T(0));
+        else
+          return (tid < TS && dc * V <= tid) ? *reinterpret_cast<const VT*>(dg + ((int64_t)dc * TS + tid) * V) : VT(T(0));
       };
       VT Ld[DIAG_PRE ? TS / V : 1];
       if (DIAG_PRE && tid < 64)
@@ -319,6 +348,16 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
       for (int u = 0; u < UNR; ++u) Lp[u] = __builtin_nontemporal_load(src(off, nb - 1, rr0 + u * RPT));
     for (int I = nb - 1; I >= 0; --I) {
       const int rbase = (I + 1) * TS;
+      VT dgv[DGU];
+      if constexpr (!DIAG_PRE) {
+        // chunk q = dc TS + row, needed where dc V + V - 1 >= row
+        const VT* dsrc = reinterpret_cast<const VT*>(P + off);
+#pragma unroll
+        for (int u = 0; u < DGU; ++u) {
+          const int q = tid + u * NT;
+          if (q < DGV && (q / TS) * V + V - 1 >= q % TS) dgv[u] = __builtin_nontemporal_load(dsrc + q);
+        }
+      }
       T acc[NR];
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[k] = T(0);
@@ -349,12 +388,23 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           acc[k] += vdot<VT, V>(L, z);
         }
       }
+      if constexpr (!DIAG_PRE) {
+#pragma unroll
+        for (int u = 0; u < DGU; ++u) {
+          const int q = tid + u * NT;
+          if (q < DGV && (q / TS) * V + V - 1 >= q % TS) *reinterpret_cast<VT*>(dg + (int64_t)q * V) = dgv[u];
+        }
+      }
       // the inverse transpose is upper: lane tid < TS needs the diagonal
       // chunks dc with dc V + V - 1 >= tid
       auto diag = [&](int dc) -> VT {
-        return (tid < TS && dc * V + V - 1 >= tid)
-                   ? *reinterpret_cast<const VT*>(P + off + ((int64_t)dc * TS + tid) * V)
-                   : VT(T(0));
+        if constexpr (DIAG_PRE)
+          return (tid < TS && dc * V + V - 1 >= tid)
+                     ? *reinterpret_cast<const VT*>(P + off + ((int64_t)dc * TS + tid) * V)
+                     : VT(T(0));
+        else
+          return (tid < TS && dc * V + V - 1 >= tid) ? *reinterpret_cast<const VT*>(dg + ((int64_t)dc * TS + tid) * V)
+                                                     : VT(T(0));
       };
       VT Ld[DIAG_PRE ? TS / V : 1];
       if (DIAG_PRE && tid < 64)
@@ -435,6 +485,8 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
 template <typename T, int NT, int NR>
 static void launch_ts(const KsolveArgs<T>& b, int TS, size_t shm, hipStream_t st) {
   dim3 grid((unsigned)b.nsub), block(NT);
+  // the diagonal tile's LDS copy of the tiles wider than 8 vectors of 16 bytes
+  if ((size_t)TS * sizeof(T) > 128) shm += (size_t)TS * TS * sizeof(T);
   if (TS == 16) {
     if (shm > 65536)
       (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 16, NT, NR>,
@@ -456,14 +508,15 @@ static void launch_ts(const KsolveArgs<T>& b, int TS, size_t shm, hipStream_t st
 template <typename T>
 void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st) {
   // shared memory: NR vectors (npad_max entries each, rounded to 16 bytes)
-  // + NR partial sums per thread + one envelope column per chunk of rows;
-  // a second right-hand side when lam2 is set
+  // + NR partial sums per thread + one envelope column per chunk of rows
+  // (16-byte aligned) + the diagonal tile for the wide tiles; a second
+  // right-hand side when lam2 is set
   // 1024 threads only with tiles of 16 or 32 rows (the 64-row kernel needs
   // more registers than 16 waves per compute unit leave)
   const int NT = (threads == 1024 && TS <= 32) ? 1024 : (threads == 512 ? 512 : 256);
   const int NR = a.lam2 ? 2 : 1;
   const size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
-  const size_t shm = NR * (vec + (size_t)NT * sizeof(T)) + (size_t)npad_max / (16 / sizeof(T)) * sizeof(int32_t);
+  const size_t shm = NR * (vec + (size_t)NT * sizeof(T)) + (vec / 4 + 15) / 16 * 16;
   KsolveArgs<T> b = a;
   b.vec_stride = (int32_t)(vec / sizeof(T));
   if (NR == 2) {
