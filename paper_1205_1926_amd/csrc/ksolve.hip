@@ -27,7 +27,10 @@
 // some lane needs.
 // Panel loads are non-temporal (each factor entry is read once per apply)
 // and issued four chunks at a time per lane (a sweep of 2..16 on MI355X put
-// the optimum at 4 for both precisions).
+// the optimum at 4 for both precisions on the cube benchmark; the FP64
+// 64-row tiles of large subdomains take 8), a lane's last chunks of a block
+// row in one batch as well except in the FP64 narrow-tile and two-right-hand-
+// side kernels.
 #include "kernels.h"
 
 namespace tfeti {
@@ -79,7 +82,10 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   using VT = typename Vec<T>::type;
   constexpr int V = Vec<T>::V;
   constexpr int RPT = NT / TS;           // threads per tile row
-  constexpr int UNR = 4;                 // panel chunks loaded back to back per lane
+  // panel chunks loaded back to back per lane: 4 (a sweep of 2..16 on the
+  // cube benchmark), 8 for the FP64 64-row tiles, whose lanes stream about 25
+  // chunks per block row and still run two wavefronts per SIMD with 8
+  constexpr int UNR = (sizeof(T) == 8 && TS == 64) ? 8 : 4;
   extern __shared__ __align__(16) unsigned char smem[];
   // NR right-hand sides, each a vector of vec_stride entries in LDS, one
   // partial sum per thread and right-hand side, then the first envelope
@@ -167,6 +173,7 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   {
     const T* P = A.Fp + s.panel_off;
     const int r = tid % TS;
+    const VT* zsrc = reinterpret_cast<const VT*>(g_zero_chunks) + (tid & 63);
     // block row I: chunk count, first column, and this lane's first chunk
     // (the 8 rows of a 128-byte line, lanes 8k .. 8k+7 of the tile row,
     // start at their earliest envelope chunk together, so every line is
@@ -229,12 +236,33 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           for (int k = 0; k < NR; ++k)
             acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + (cc + u * RPT) * V));
       }
-      for (; cc < nco; cc += RPT) {
-        VT L = *chunk(off, cc);
+      if constexpr (DIAG_PRE && (NR > 1 || sizeof(T) == 8)) {
+        for (; cc < nco; cc += RPT) {
+          VT L = *chunk(off, cc);
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          VT y = *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + cc * V);
-          acc[k] += vdot<VT, V>(L, y);
+          for (int k = 0; k < NR; ++k) {
+            VT y = *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + cc * V);
+            acc[k] += vdot<VT, V>(L, y);
+          }
+        }
+      } else if (cc < nco) {
+        // this lane's last chunks as one batch, the loads past the end
+        // reading zeros with the vector index held at a valid entry (the
+        // wide tiles and the single-right-hand-side FP32 kernels; the others
+        // measured as fast or faster one chunk at a time, or ran out of
+        // registers)
+        VT L[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int c = cc + u * RPT;
+          L[u] = __builtin_nontemporal_load(c < nco ? chunk(off, c) : zsrc);
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int c = cc + u * RPT < nco ? cc + u * RPT : cc;
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + c0 + c * V));
         }
       }
       if constexpr (!DIAG_PRE) {
@@ -380,12 +408,29 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
           for (int k = 0; k < NR; ++k)
             acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + (rr + u * RPT) * V));
       }
-      for (; rr < rend; rr += RPT) {
-        VT L = *src(off, I, rr);
+      if constexpr (DIAG_PRE && (NR > 1 || sizeof(T) == 8)) {
+        for (; rr < rend; rr += RPT) {
+          VT L = *src(off, I, rr);
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          VT z = *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + rr * V);
-          acc[k] += vdot<VT, V>(L, z);
+          for (int k = 0; k < NR; ++k) {
+            VT z = *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + rr * V);
+            acc[k] += vdot<VT, V>(L, z);
+          }
+        }
+      } else if (rr < rend) {
+        // this lane's last chunks as one batch (zeros past the end)
+        VT L[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int r = rr + u * RPT;
+          L[u] = __builtin_nontemporal_load(r < rend ? src(off, I, r) : zsrc);
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int r = rr + u * RPT < rend ? rr + u * RPT : rr;
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            acc[k] += vdot<VT, V>(L[u], *reinterpret_cast<const VT*>(xs0 + k * VS + rbase + r * V));
         }
       }
       if constexpr (!DIAG_PRE) {
