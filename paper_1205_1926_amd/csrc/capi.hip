@@ -1529,7 +1529,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     cs.npad = M.lc_pad;
     cs.ndof = M.lc;
     cs.b = M.bc;
-    cs.Wb = M.bc + 1;
+    cs.Wb = M.Wc;
     std::vector<SubDev> csv{cs};
     SubDev* d_cs = nullptr;
     RC(upload(h, &d_cs, csv));
@@ -1543,8 +1543,8 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
                   "the band of the coarse matrix G G^T (half bandwidth " + std::to_string(M.bc) +
                       ") does not fit the factorization kernel's LDS");
     double* d_ct = nullptr;  // transposed factor (setup scratch)
-    RC(dalloc(h, &d_ct, (int64_t)M.lc_pad * (M.bc + 1)));
-    launch_coarse_inverse(d_cb, M.lc, M.bc, M.bc + 1, h->d_Ginv, h->st, d_ct);
+    RC(dalloc(h, &d_ct, (int64_t)M.lc_pad * M.Wc));
+    launch_coarse_inverse(d_cb, M.lc, M.bc, M.Wc, h->d_Ginv, h->st, d_ct);
     launch_coarse_pack(M.lc, h->d_Ginv, d_cidx, h->d_Gpk, h->st);
     int32_t bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, h->d_fail, sizeof(bad), hipMemcpyDeviceToHost, h->st));

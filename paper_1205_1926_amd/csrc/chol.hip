@@ -2,8 +2,9 @@
 // once regularized, each block is factorized by a standard Cholesky method
 // for nonsingular matrices).
 //
-// Storage: row-band, row r holds columns r-b..r (entry (r, k) is column
-// r-b+k, k = b the diagonal); rows are the subdomain DOFs in the factor
+// Storage: row-band, row r holds columns r-b..r (entry (r, k) at
+// r Wb + k - r + b, k = r the diagonal) with the row stride Wb one more than
+// a multiple of 16 (band_stride); rows are the subdomain DOFs in the factor
 // ordering, padded with identity rows to a multiple of 64.
 //
 // One workgroup (256 threads) per band matrix, left-looking by block columns
@@ -13,11 +14,16 @@
 //     A_panel - L_panel,k L_tile,k^T over k in [J - b, J), on the FP64
 //     matrix cores: the tile rows' L (negated) are staged in LDS, each
 //     wavefront keeps the accumulators of its row blocks in registers
-//     (initialized with the panel's entries) and streams its rows of L from
-//     memory 16 columns at a time, the next chunk's loads in flight;
+//     (initialized with the panel's entries) and streams the 16 x 16 tiles
+//     of its rows of L that meet the band, slot by slot, a ring of DT tiles
+//     in flight; the 16-column chunks start where every row's chunk is one
+//     aligned 128-byte line;
 //  F. the accumulators become the LDS panel;
-//  D. the diagonal tile is factored by one wavefront (one row per lane, no
-//     workgroup barrier), then the rows below are solved against it;
+//  D. the diagonal tile is factored by one wavefront in registers
+//     (right-looking, one row per lane, cross-lane reads instead of LDS
+//     round trips), which also carries panel rows NB..63 along; the same
+//     wavefront forms the tile's inverse X, and the rows from 64 on are
+//     L_below = A_below X^T on the matrix cores;
 //  W. the panel is written back.
 // Finished columns are only read, so the band is written once per entry
 // and no store waits on the matrix-core chain.
@@ -29,6 +35,27 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// a copy of v that the compiler cannot identify with v (no common
+// subexpression, so values derived from v earlier need not stay live)
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// v, for the compiler computed only once dep is (orders independent work)
+template <typename V>
+__device__ __forceinline__ V after(V v, double dep) {
+  asm volatile("" : "+v"(v) : "v"(dep));
+  return v;
+}
+
+// lane l's v, for a lane index l known at compile time
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, l), hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -39,12 +66,13 @@ __host__ __device__ inline int tile_stride(int bmax) { return ((bmax + 15) / 16 
 
 }  // namespace
 
-template <int NB, int G>
+template <int NB, int G, int DT>
 __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __restrict__ subs, int64_t count,
                                                             const int32_t* __restrict__ list,
                                                             double* __restrict__ W, int32_t* __restrict__ fail,
                                                             int LB) {
   static_assert(NB % 16 == 0 && NB <= 64, "tile of whole 16 x 16 blocks, one row per lane of a wavefront");
+  static_assert(kPadRows % NB == 0, "whole block columns: the diagonal tile is always NB x NB");
   extern __shared__ __align__(16) unsigned char smem[];
   // phase U: the tile rows' negated L over the update columns (NB x LB);
   // phases F..W: the panel (rows x LS), whose diagonal tile's rows hold L in
@@ -60,7 +88,9 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
   const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
   const int b = subs[p].b, Wb = subs[p].Wb, n = subs[p].npad;
   double* A = W + subs[p].band_off;
-  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, lk = lane / 16;
+  const unsigned char* Abytes = reinterpret_cast<const unsigned char*>(A);
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64, li = lane % 16,
+            lk = lane / 16;
   if (tid == 0) s_fail = 0;
 
   for (int J = 0; J < n; J += NB) {
@@ -70,28 +100,38 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
     const int nr = rend - J;                      // panel rows (>= jb)
     const int nbr = (nr + 15) / 16;               // panel row blocks
     const int kbeg = J > b ? J - b : 0;           // first update column
-    const int nq = (J - kbeg + 15) / 16;          // 16-column update chunks
+    // 16-column chunks of the update columns start at kq0 <= kbeg, chosen
+    // with kq0 + b a multiple of 16: with the band's row stride one more
+    // than a multiple of 16 every row's chunk is then one aligned 128-byte
+    // line (chunk entries before kbeg are masked)
+    const int kq0 = kbeg - ((kbeg + b) & 15);
+    const int nq = (J - kq0 + 15) / 16;           // chunks
     const bool multi = nbr > 4 * G;               // row blocks in several passes
-    // ---- U. updates from the finished columns ----
-    for (int q0 = tid; q0 < NB * 16 * nq; q0 += 8 * 256) {
-      double v[8];
+    // entry (r, k) of the band, as a byte offset from its (uniform) start;
+    // rows J - 1 .. n - 1 and columns kq0 .. J + 14 stay inside the storage
+    auto eoff = [&](int r, int k) { return 8u * (uint32_t)(r * (Wb - 1) + k + b); };
+    // ---- U. updates from the finished columns: the tile rows' L over the
+    //      chunks, negated, to LDS (16-byte loads, all of a round in flight) ----
+    constexpr int SU = 10;
+    const int npair = NB * 8 * nq;
+    for (int q0 = tid; q0 < npair; q0 += SU * 256) {
+      double2 v[SU];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = q0 + u * 256;
-        const int c = q / (16 * nq), kk = q - c * (16 * nq);
-        const int row = J + c, k = kbeg + kk;
-        const int rc = row < rend ? row : rend - 1;
-        int kc = k > rc - b ? k : rc - b;
-        kc = kc < rc ? kc : rc;
-        v[u] = A[(int64_t)rc * Wb + (kc - rc + b)];
+      for (int u = 0; u < SU; ++u) {
+        int q = q0 + u * 256;
+        q = q < npair ? q : npair - 1;
+        const int c = q / (8 * nq), kk = 2 * (q - c * (8 * nq));
+        v[u] = *reinterpret_cast<const double2*>(Abytes + eoff(J + c, kq0 + kk));
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < SU; ++u) {
         const int q = q0 + u * 256;
-        const int c = q / (16 * nq), kk = q - c * (16 * nq);
-        const int row = J + c, k = kbeg + kk;
-        const bool in = c < jb && k < J && k >= row - b;
-        if (q < NB * 16 * nq) Bt[c * LB + kk] = in ? -v[u] : 0.0;
+        const int c = q / (8 * nq), kk = 2 * (q - c * (8 * nq));
+        const int row = J + c, k = kq0 + kk;
+        if (q < npair) {
+          Bt[c * LB + kk] = (c < jb && k >= kbeg && k < J && k >= row - b) ? -v[u].x : 0.0;
+          Bt[c * LB + kk + 1] = (c < jb && k + 1 >= kbeg && k + 1 < J && k + 1 >= row - b) ? -v[u].y : 0.0;
+        }
       }
     }
     __syncthreads();
@@ -112,60 +152,101 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
             const int rc = row < rend ? row : rend - 1;
             int cc = col > rc - b ? col : rc - b;
             cc = cc < rc ? cc : rc;
-            const double v = A[(int64_t)rc * Wb + (cc - rc + b)];
+            const double v =
+                *reinterpret_cast<const double*>(Abytes + 8u * (uint32_t)(rc * Wb + (cc - rc + b)));
             acc[g][jc][r] = in ? v : 0.0;
           }
-      // one chunk: the next chunk's L rows are requested (clamped addresses,
-      // so unconditionally), this chunk's rows (copied from the previous
-      // request) meet the staged tile rows, and the request is copied over
-      // at the end, when the matrix-core chain has been issued
-      auto load_chunk = [&](int q, double (&a)[G][4]) {
+      // The wavefront's tiles (16 rows x 16 update columns) that meet the
+      // band, slot by slot: slot g's row block takes the chunks from the
+      // first one its first row reaches (lo_of) to the last.  Each slot's
+      // run is padded to whole turns of a ring of DT tiles (padding tiles
+      // load the panel's first row and add zero), so that a slot always
+      // starts at ring position 0 and its accumulators are updated in a
+      // plain loop; loads run DT tiles ahead of the matrix cores across
+      // slot boundaries.  All cursors are wavefront-uniform.
+      auto lo_of = [&](int g) {
+        const int R = row_block(pass, g);
+        if (R >= nbr) return nq;
+        const int x = J + 16 * R - b - kq0 - 15;
+        const int lo = x <= 0 ? 0 : (x + 15) / 16;
+        return lo < nq ? lo : nq;
+      };
+      auto run_of = [&](int g) { return (nq - lo_of(g) + DT - 1) / DT * DT; };
+      auto next_slot = [&](int g) {  // first slot after g with a nonempty run (G: none)
+        ++g;
+        while (g < G && run_of(g) == 0) ++g;
+        return g;
+      };
+      // One turn of requests: entries i0 .. i0 + DT - 1 of slot sl's run
+      // into the ring (sl == G or entries past the run: the panel's first
+      // row).  Lane (li, lk) fetches columns 4 lk .. 4 lk + 3 of row li as
+      // two 16-byte loads; rows past the panel read its last row (their
+      // products are never stored).  The loader always runs one turn ahead
+      // of the matrix cores.
+      const uint32_t edummy = eoff(J, kq0);
+      auto load_turn = [&](int sl, int i0, double2 (&ring)[DT][2]) {
+        int q0 = nq, row = J;
+        if (sl < G) {
+          q0 = lo_of(sl) + i0;
+          row = J + 16 * row_block(pass, sl) + li;
+        }
+        const uint32_t e0 = eoff(row < rend ? row : rend - 1, kq0 + 4 * lk);
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const int R = row_block(pass, g);
-          const int row = J + 16 * R + li;
-          const int rc = row < rend ? row : rend - 1;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int k = kbeg + 16 * q + 4 * lk + s;
-            int kc = k > rc - b ? k : rc - b;
-            kc = kc < rc ? kc : rc;
-            a[g][s] = A[(int64_t)rc * Wb + (kc - rc + b)];
-          }
+        for (int d = 0; d < DT; ++d) {
+          const uint32_t e = q0 + d < nq ? e0 + 128u * (uint32_t)(q0 + d) : edummy;
+          ring[d][0] = *reinterpret_cast<const double2*>(Abytes + e);
+          ring[d][1] = *reinterpret_cast<const double2*>(Abytes + e + 16u);
         }
       };
-      double a[G][4], an[G][4];
-      load_chunk(0, a);
-      for (int q = 0; q < nq; ++q) {
-        load_chunk(q + 1, an);
-        double bq[NJ][4];
+      double2 ring[DT][2];
+      load_turn(next_slot(-1), 0, ring);
 #pragma unroll
-        for (int jc = 0; jc < NJ; ++jc)
+      for (int g = 0; g < G; ++g) {
+        const int lo = lo_of(g), n = nq - lo, run = run_of(g), nx = next_slot(g);
+        const int R = row_block(pass, g);
+        for (int i0 = 0; i0 < run; i0 += DT) {
+          const bool same = i0 + DT < run;
+          const int ns = same ? g : nx, ni = same ? i0 + DT : 0;
+          int nq0 = nq, nrow = J;
+          if (ns < G) {
+            nq0 = lo_of(ns) + ni;
+            nrow = J + 16 * row_block(pass, ns) + li;
+          }
+          const uint32_t ne0 = eoff(nrow < rend ? nrow : rend - 1, kq0 + 4 * lk);
 #pragma unroll
-          for (int s = 0; s < 4; ++s) bq[jc][s] = Bt[(16 * jc + li) * LB + 16 * q + 4 * lk + s];
+          for (int d = 0; d < DT; ++d) {
+            const int i = i0 + d;
+            const int q = lo + (i < n ? i : n - 1);
+            double bq[NJ][4];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const int R = row_block(pass, g);
-          // rows of block R meet this chunk's columns inside the band?
-          if (R < nbr && kbeg + 16 * q + 15 >= J + 16 * R - b) {
-            const int row = J + 16 * R + li;
+            for (int jc = 0; jc < NJ; ++jc)
+#pragma unroll
+              for (int s = 0; s < 4; ++s) bq[jc][s] = Bt[(16 * jc + li) * LB + 16 * q + 4 * lk + s];
+            // lane (li, lk) holds column k = kq0 + 16 q + 4 lk + s of row
+            // J + 16 R + li; its band starts at k = row - b, i.e. the entry
+            // counts when li - 4 lk - s <= ub.  The tile rows in LDS are zero
+            // outside kbeg .. J - 1, so no other column needs a mask, and
+            // rows past the panel are never stored.
+            const int ub = i < n ? kq0 + 16 * q + b - J - 16 * R : -64;
+            const double a[4] = {ring[d][0].x, ring[d][0].y, ring[d][1].x, ring[d][1].y};
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-              const int k = kbeg + 16 * q + 4 * lk + s;
-              const double av = (row < rend && k < J && k >= row - b) ? a[g][s] : 0.0;
+              const double av = (li - 4 * lk - s <= ub) ? a[s] : 0.0;
 #pragma unroll
               for (int jc = 0; jc < NJ; ++jc) acc[g][jc] = mfma4(av, bq[jc][s], acc[g][jc]);
             }
+            // the next turn's entry d into the freed ring position
+            const uint32_t e = nq0 + d < nq ? ne0 + 128u * (uint32_t)(nq0 + d) : edummy;
+            ring[d][0] = *reinterpret_cast<const double2*>(Abytes + e);
+            ring[d][1] = *reinterpret_cast<const double2*>(Abytes + e + 16u);
           }
         }
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) a[g][s] = an[g][s];
       }
       if (multi) {
         // several passes: this pass's panel rows go back to memory and are
-        // staged with the others below
+        // staged with the others below (lane indices re-derived, so that
+        // nothing of the accumulators' set-up stays live across the loop)
+        const int li2 = opaque(li), lk2 = opaque(lk);
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -173,7 +254,7 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int R = row_block(pass, g);
-              const int row = J + 16 * R + lk + 4 * r, col = J + 16 * jc + li;
+              const int row = J + 16 * R + lk2 + 4 * r, col = J + 16 * jc + li2;
               if (R < nbr && row < rend && col < J + jb && col <= row && row - col <= b)
                 A[(int64_t)row * Wb + (col - row + b)] = acc[g][jc][r];
             }
@@ -182,6 +263,7 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
     __syncthreads();
     // ---- F. the LDS panel (zero outside the band and past jb) ----
     if (!multi) {
+      const int li2 = opaque(li), lk2 = opaque(lk);
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
@@ -189,7 +271,7 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int R = row_block(0, g);
-            const int i = 16 * R + lk + 4 * r, j = 16 * jc + li;
+            const int i = 16 * R + lk2 + 4 * r, j = 16 * jc + li2;
             if (R < nbr && i < nr) P[i * LS + j] = acc[g][jc][r];
           }
     } else {
@@ -201,81 +283,112 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
       }
     }
     __syncthreads();
-    // ---- D. the diagonal tile by wavefront 0, one row per lane: at column j
-    //      lane j completes its diagonal entry (its sum of squares is kept
-    //      as the row is finished) and publishes the reciprocal, then every
-    //      lane r > j forms L[r][j] = (x_r[j] - x_r[0:j] . L[j][0:j]) / L[j][j]
-    //      with row j read from LDS (one address for all lanes) and stores it
-    //      for the columns to come.  The lanes of one wavefront see each
-    //      other's LDS stores in program order, so the tile needs no
-    //      workgroup barrier; lanes jb..63 finish rows jb..63 of the panel on
-    //      the way.  Dot products run as two interleaved partial sums. ----
+    // ---- D. the diagonal tile by wavefront 0, right-looking, one row per
+    //      lane (lanes NB..63 carry panel rows NB..63 along): at column j the
+    //      pivot is lane j's entry, 1/sqrt of it comes from the reciprocal
+    //      square root refined by two Newton steps, and every later column k
+    //      takes lane k's L[k][j] by a cross-lane read, so the chain has no
+    //      LDS round trip.  Then lane c < NB forms column c of X = L^{-1}
+    //      (forward substitution over the tile in LDS) and stores its strict
+    //      lower part transposed in the tile's upper triangle; s_rcp holds
+    //      X's diagonal. ----
     if (wave == 0) {
-      const int r = lane;
+      // lane index re-derived here: nothing lane-dependent of this phase is
+      // computed ahead of the block-column loop and kept live across it
+      const int r = opaque(lane);
       const bool have = r < nr;
       double x[NB];
 #pragma unroll
       for (int j = 0; j < NB; ++j) x[j] = have ? P[(have ? r : 0) * LS + j] : 0.0;
-      double sa = 0.0, sb = 0.0;
       bool bad = false;
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        if (j < jb) {
-          if (r == j) {
-            double d = x[j] - (sa + sb);
-            if (!(d > 0.0)) {
-              bad = true;
-              d = 1.0;
-            }
-            x[j] = sqrt(d);
-            P[j * LS + j] = x[j];
-            s_rcp[j] = 1.0 / x[j];
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          if (have && r > j) {
-            double v0 = x[j], v1 = 0.0;
+        double d = readlane_f64(x[j], j);
+        if (!(d > 0.0)) {
+          bad = true;
+          d = 1.0;
+        }
+        double y = __builtin_amdgcn_rsq(d);
+        y = y * fma(-0.5 * d * y, y, 1.5);
+        y = y * fma(-0.5 * d * y, y, 1.5);
+        x[j] = r == j ? d * y : x[j] * y;
+        if (r == 0) s_rcp[j] = y;
+        // the cross-lane reads go in groups of four, each group ordered
+        // after the previous one's updates, so that few scalar registers
+        // hold read values at a time
+        double xj = x[j];
 #pragma unroll
-            for (int k = 0; k < j; ++k) {
-              if (k & 1)
-                v1 -= x[k] * P[j * LS + k];
-              else
-                v0 -= x[k] * P[j * LS + k];
-            }
-            x[j] = (v0 + v1) * s_rcp[j];
-            P[r * LS + j] = x[j];
-            if (j & 1)
-              sb += x[j] * x[j];
-            else
-              sa += x[j] * x[j];
-          }
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int k0 = j + 1; k0 < NB; k0 += 4) {
+#pragma unroll
+          for (int k = k0; k < k0 + 4 && k < NB; ++k) x[k] = fma(-xj, readlane_f64(xj, k), x[k]);
+          xj = after(xj, x[k0 + 3 < NB ? k0 + 3 : NB - 1]);
         }
       }
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (have && j <= r) P[r * LS + j] = x[j];
       if (bad) s_fail = 1;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (r < NB) {
+        const int c = r;
+        double z[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          // row i of the tile is read once z[i - 1] is known: one row in
+          // flight, not the whole tile at once
+          const int base = i >= 1 ? after(i * LS, z[i - 1]) : 0;
+          double s0 = i == c ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+          for (int k = 0; k < i; ++k) {
+            if (k & 1)
+              s1 = fma(-P[base + k], z[k], s1);
+            else
+              s0 = fma(-P[base + k], z[k], s0);
+          }
+          z[i] = (s0 + s1) * s_rcp[i];
+        }
+#pragma unroll
+        for (int i = 1; i < NB; ++i)
+          if (i > c) P[c * LS + i] = z[i];
+      }
     }
     __syncthreads();
-    // ---- rows 64.. of the panel: solved against the finished diagonal
-    //      tile, independently ----
-    for (int r = 64 + tid; r < nr; r += 256) {
-      double x[NB];
+    // ---- rows 64.. of the panel: L_below = A_below X^T on the matrix cores
+    //      (B[k][n] = X[n][k], zero for k > n), one 16-row block at a time ----
+    {
+      const int nb2 = nr > 64 ? (nr - 64 + 15) / 16 : 0;
+      if (nb2 > wave) {
+        const int mi = opaque(li), mk = opaque(lk);
+        double xb[NJ][KS];
 #pragma unroll
-      for (int j = 0; j < NB; ++j) x[j] = P[r * LS + j];
+        for (int jc = 0; jc < NJ; ++jc)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < jb) {
-          double v0 = x[j], v1 = 0.0;
-#pragma unroll
-          for (int k = 0; k < j; ++k) {
-            if (k & 1)
-              v1 -= x[k] * P[j * LS + k];
-            else
-              v0 -= x[k] * P[j * LS + k];
+          for (int t = 0; t < KS; ++t) {
+            const int n = 16 * jc + mi, k = 4 * t + mk;
+            xb[jc][t] = k < n ? P[k * LS + n] : (k == n ? s_rcp[n] : 0.0);
           }
-          x[j] = (v0 + v1) * s_rcp[j];
+        for (int rb = wave; rb < nb2; rb += 4) {
+          const int row0 = 64 + 16 * rb;
+          const int ra = row0 + mi < nr ? row0 + mi : nr - 1;
+          d4 y[NJ];
+#pragma unroll
+          for (int jc = 0; jc < NJ; ++jc) y[jc] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int t = 0; t < KS; ++t) {
+            const double av = P[ra * LS + 4 * t + mk];
+#pragma unroll
+            for (int jc = 0; jc < NJ; ++jc)
+              if (4 * t <= 16 * jc + 15) y[jc] = mfma4(av, xb[jc][t], y[jc]);
+          }
+#pragma unroll
+          for (int jc = 0; jc < NJ; ++jc)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = row0 + mk + 4 * q;
+              if (row < nr) P[row * LS + 16 * jc + mi] = y[jc][q];
+            }
         }
       }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) P[r * LS + j] = x[j];
     }
     __syncthreads();
     // ---- W. write the panel back ----
@@ -311,19 +424,22 @@ int band_cholesky_nb(int bmax, size_t elem) {
   return 0;
 }
 
-template <int NB, int G>
+template <int NB, int G, int DT>
 static int launch_nb(const SubDev* subs, int64_t nsub, const int32_t* list, double* band, int32_t* fail, int bmax,
                      hipStream_t st) {
   const size_t shm = chol_lds(NB, bmax);
   if (shm > 65536)
-    (void)hipFuncSetAttribute((const void*)band_cholesky_kernel<NB, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)band_cholesky_kernel<NB, G, DT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)shm);
   if (nsub > 0)
-    band_cholesky_kernel<NB, G><<<dim3((unsigned)nsub), dim3(256), shm, st>>>(subs, nsub, list, band, fail,
+    band_cholesky_kernel<NB, G, DT><<<dim3((unsigned)nsub), dim3(256), shm, st>>>(subs, nsub, list, band, fail,
                                                                              tile_stride(bmax));
   return 0;
 }
 
+#ifndef CHOL_DT
+#define CHOL_DT 2
+#endif
 template <typename T>
 int launch_band_cholesky(const SubDev* subs, int64_t nsub, const int32_t* list, T* band, int32_t* fail, int bmax,
                          int nb, hipStream_t st) {
@@ -331,9 +447,9 @@ int launch_band_cholesky(const SubDev* subs, int64_t nsub, const int32_t* list, 
   if (nb <= 0) nb = band_cholesky_nb(bmax, sizeof(T));
   switch (nb) {
     case 32:
-      return launch_nb<32, 5>(subs, nsub, list, band, fail, bmax, st);
+      return launch_nb<32, 5, CHOL_DT>(subs, nsub, list, band, fail, bmax, st);
     case 16:
-      return launch_nb<16, 5>(subs, nsub, list, band, fail, bmax, st);
+      return launch_nb<16, 5, CHOL_DT>(subs, nsub, list, band, fail, bmax, st);
     default:
       return -1;
   }

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void gather_interior_band_kernel(const SubDev*
     double v = 0.0;
     if (r >= si.ndof)
       v = k == si.b ? 1.0 : 0.0;
-    else if (c >= 0)
+    else if (c >= 0 && k <= si.b)
       v = band_entry(A, s, interior_to_sub(si, s, lo, r), interior_to_sub(si, s, lo, c));
     D[q] = v;
   }

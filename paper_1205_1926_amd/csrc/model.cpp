@@ -143,7 +143,7 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
         s.npad = (s.ndof + kPadRows - 1) / kPadRows * kPadRows;
         int32_t N0 = s.N[s.perm[0]], N1 = s.N[s.perm[1]], N2 = s.N[s.perm[2]];
         s.b = 3 * (N0 * N1 + N0 + 1) + 2;
-        s.Wb = s.b + 1;
+        s.Wb = band_stride(s.b);
         s.bo = (s.b + 3) / 4 * 4;
         s.n_elem = s.n[0] * s.n[1] * s.n[2];
         s.dof_off = dof_off;
@@ -493,7 +493,7 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
       si.npad = (si.ndof + kPadRows - 1) / kPadRows * kPadRows;
       const int32_t N0 = si.N[si.perm[0]], N1 = si.N[si.perm[1]];
       si.b = std::min(3 * (N0 * N1 + N0 + 1) + 2, si.npad - 1);
-      si.Wb = si.b + 1;
+      si.Wb = band_stride(si.b);
       si.bo = (si.b + 3) / 4 * 4;
       si.dof_off = ioff;
       si.band_off = iband;
@@ -698,7 +698,8 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
         maxdp = std::max<int64_t>(maxdp, std::abs((int64_t)M.cpos[e_sub[e]] - M.cpos[e_sub[e2]]));
   M.bc = (int32_t)(6 * maxdp + 5);
   M.lc_pad = (M.lc + kPadRows - 1) / kPadRows * kPadRows;
-  const int64_t Wc = M.bc + 1;
+  M.Wc = band_stride(M.bc);
+  const int64_t Wc = M.Wc;
   M.GGt_band.assign((int64_t)M.lc_pad * Wc, 0.0);
   for (int64_t r = 0; r < M.m; ++r) {
     // column r of G: for entry (p, ldof, v): v * R_p[ldof, :] at rows 6p..6p+5

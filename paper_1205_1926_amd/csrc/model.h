@@ -85,10 +85,10 @@ struct HostModel {
   // load at factor 1, torn
   std::vector<double> f1;
   // coarse matrix G G^T in lower row-band form
-  int32_t lc = 0, bc = 0, lc_pad = 0;
+  int32_t lc = 0, bc = 0, lc_pad = 0, Wc = 0;  // Wc: row stride of GGt_band
   std::vector<int32_t> cpos;            // coarse position of each subdomain: boxes in
                                         // lexicographic order, fewest boxes fastest
-  std::vector<double> GGt_band;         // lc_pad rows of (bc + 1)
+  std::vector<double> GGt_band;         // lc_pad rows of Wc
   // interface nodes of the learned warm start: nodes carrying multiplier rows
   int64_t n_wnodes = 0;
   std::vector<int32_t> wn_rows;         // n_wnodes * 21: row in slot 7 c + j, or -1

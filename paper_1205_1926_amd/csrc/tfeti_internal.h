@@ -13,6 +13,12 @@ namespace tfeti {
 
 constexpr int kThreads = 256;     // threads per workgroup of the subdomain kernels
 constexpr int kPadRows = 64;      // subdomain factors are padded to a multiple of this
+// Row stride of a row-band matrix of half bandwidth b: b rounded up to a
+// multiple of 16, plus one.  Entry (r, k) sits at r (stride - 1) + k + b, so
+// with the band 16-entry aligned a column k that is a multiple of 16 minus b
+// starts a 128-byte line in every row (the factorization streams 16-column
+// chunks of many rows).
+inline int32_t band_stride(int32_t b) { return (b + 15) / 16 * 16 + 1; }
 
 // Per-subdomain description, identical on host and device.
 struct SubDev {
@@ -23,7 +29,7 @@ struct SubDev {
   int32_t ndof;        // 3 * nodes
   int32_t npad;        // ndof rounded up to kPadRows
   int32_t b;           // half bandwidth in the factor ordering
-  int32_t Wb;          // row-band width b + 1
+  int32_t Wb;          // row stride of the band, band_stride(b)
   int32_t bo;          // off-diagonal panel width (b rounded up to 4)
   int32_t n_iface;     // B-touched local DOFs
   int32_t n_elem;
