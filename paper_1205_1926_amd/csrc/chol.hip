@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
   const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
   const int b = subs[p].b, Wb = subs[p].Wb, n = subs[p].npad;
   double* A = W + subs[p].band_off;
-  const unsigned char* Abytes = reinterpret_cast<const unsigned char*>(A);
+  unsigned char* Abytes = reinterpret_cast<unsigned char*>(A);
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64, li = lane % 16,
             lk = lane / 16;
   if (tid == 0) s_fail = 0;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
     auto eoff = [&](int r, int k) { return 8u * (uint32_t)(r * (Wb - 1) + k + b); };
     // ---- U. updates from the finished columns: the tile rows' L over the
     //      chunks, negated, to LDS (16-byte loads, all of a round in flight) ----
-    constexpr int SU = 10;
+    constexpr int SU = 20;
     const int npair = NB * 8 * nq;
     for (int q0 = tid; q0 < npair; q0 += SU * 256) {
       double2 v[SU];
@@ -329,27 +329,79 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
         if (have && j <= r) P[r * LS + j] = x[j];
       if (bad) s_fail = 1;
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (r < NB) {
-        const int c = r;
-        double z[NB];
+      if constexpr (NB == 32) {
+        // X in 16 x 16 blocks: lanes 0..15 form the columns of X11 = L11^{-1}
+        // and lanes 16..31 those of X22 = L22^{-1} (two 16-row chains at
+        // once), then X21 = -X22 (L21 X11) on the matrix cores
+        if (r < NB) {
+          const int o = r & 16, c = r - o;
+          double z[16];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          // row i of the tile is read once z[i - 1] is known: one row in
-          // flight, not the whole tile at once
-          const int base = i >= 1 ? after(i * LS, z[i - 1]) : 0;
-          double s0 = i == c ? 1.0 : 0.0, s1 = 0.0;
+          for (int i = 0; i < 16; ++i) {
+            // row i of the block is read once z[i - 1] is known
+            const int base = i >= 1 ? after((o + i) * LS + o, z[i - 1]) : o * LS + o;
+            double s0 = i == c ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-          for (int k = 0; k < i; ++k) {
-            if (k & 1)
-              s1 = fma(-P[base + k], z[k], s1);
-            else
-              s0 = fma(-P[base + k], z[k], s0);
+            for (int k = 0; k < i; ++k) {
+              if (k & 1)
+                s1 = fma(-P[base + k], z[k], s1);
+              else
+                s0 = fma(-P[base + k], z[k], s0);
+            }
+            z[i] = (s0 + s1) * s_rcp[o + i];
           }
-          z[i] = (s0 + s1) * s_rcp[i];
-        }
 #pragma unroll
-        for (int i = 1; i < NB; ++i)
-          if (i > c) P[c * LS + i] = z[i];
+          for (int i = 1; i < 16; ++i)
+            if (i > c) P[(o + c) * LS + o + i] = z[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int mi = opaque(li), mk = opaque(lk);
+        // T = L21 X11 (X11[k][n] is P[n][k] below its diagonal, s_rcp on it)
+        d4 t = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = 4 * st + mk;
+          const double bb = kk > mi ? P[mi * LS + kk] : (kk == mi ? s_rcp[mi] : 0.0);
+          t = mfma4(P[(16 + mi) * LS + kk], bb, t);
+        }
+        // parked in the tile's upper right block, P[m][16 + n] = T[m][n]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) P[(mk + 4 * q) * LS + 16 + mi] = t[q];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        d4 x = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = 4 * st + mk;
+          const double aa = mi > kk ? P[(16 + kk) * LS + 16 + mi] : (mi == kk ? s_rcp[16 + mi] : 0.0);
+          x = mfma4(aa, P[kk * LS + 16 + mi], x);
+        }
+        // X21[m][n] = -x, stored transposed: P[n][16 + m] (over T, whose
+        // reads are done)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) P[mi * LS + 16 + mk + 4 * q] = -x[q];
+      } else {
+        if (r < NB) {
+          const int c = r;
+          double z[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            // row i of the tile is read once z[i - 1] is known: one row in
+            // flight, not the whole tile at once
+            const int base = i >= 1 ? after(i * LS, z[i - 1]) : 0;
+            double s0 = i == c ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) {
+              if (k & 1)
+                s1 = fma(-P[base + k], z[k], s1);
+              else
+                s0 = fma(-P[base + k], z[k], s0);
+            }
+            z[i] = (s0 + s1) * s_rcp[i];
+          }
+#pragma unroll
+          for (int i = 1; i < NB; ++i)
+            if (i > c) P[c * LS + i] = z[i];
+        }
       }
     }
     __syncthreads();
@@ -392,9 +444,24 @@ __global__ __launch_bounds__(256, 2) void band_cholesky_kernel(const SubDev* __r
     }
     __syncthreads();
     // ---- W. write the panel back ----
-    for (int q = tid; q < nr * NB; q += blockDim.x) {
-      const int r = q / NB, j = q - (q / NB) * NB;
-      if (j < jb && j <= r && r - j <= b) A[(int64_t)(J + r) * Wb + (j - r + b)] = P[r * LS + j];
+    {
+      // eight LDS reads in flight per thread before the stores
+      constexpr int WU = 8;
+      const int nw = nr * NB;
+      for (int q0 = tid; q0 < nw; q0 += WU * 256) {
+        double v[WU];
+#pragma unroll
+        for (int u = 0; u < WU; ++u) {
+          const int q = q0 + u * 256 < nw ? q0 + u * 256 : nw - 1;
+          v[u] = P[(q / NB) * LS + q % NB];
+        }
+#pragma unroll
+        for (int u = 0; u < WU; ++u) {
+          const int q = q0 + u * 256, r = q / NB, j = q % NB;
+          if (q < nw && j < jb && j <= r && r - j <= b)
+            *reinterpret_cast<double*>(Abytes + eoff(J + r, J + j)) = v[u];
+        }
+      }
     }
     __syncthreads();
   }
