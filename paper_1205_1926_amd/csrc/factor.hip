@@ -28,7 +28,6 @@ void launch_copy_band(const SubDev* subs, int64_t count, const int32_t* list, co
 
 // Panels (layout in kernels.h): tile rows TS, vector width V = 16 bytes /
 // sizeof(T).  Each workgroup takes block rows of one subdomain.
-constexpr int PB = 8;  // band entries in flight per thread while packing
 
 template <typename TW, typename T, int TS>
 __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restrict__ subs, int64_t count,
@@ -82,41 +81,58 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
       }
     }
     // off-diagonal part of the forward panel, columns I TS - wF .. I TS - 1,
-    // and of the backward panel, rows (I+1) TS .. + wB - 1: PB band entries
-    // requested per thread before any is stored, so that the loads overlap
-    // (one at a time, every entry paid a full memory latency)
-    const int nF = TS * wF, nB = TS * wB;
-    for (int q0 = tid; q0 < nF; q0 += PB * (int)blockDim.x) {
-      T v[PB];
+    // and of the backward panel, rows (I+1) TS .. + wB - 1, in items of CH =
+    // 4 consecutive columns (forward) or rows (backward) of one row (column):
+    // a thread stores whole 16-byte chunks (CH / V of them, and one FP32
+    // chunk of the second copy), consecutive threads consecutive chunks;
+    // IU items' band entries are requested before any is stored.  wF and wB
+    // are multiples of 4 (bo is, and so are TS and n).
+    constexpr int CH = 4, IU = 4;
+    static_assert(CH % V == 0 && CH == V2, "an item is whole chunks of both layouts");
+    auto put = [](T* dst, const T* v) {
+      if constexpr (V == 2)
+        *reinterpret_cast<double2*>(dst) = double2{(double)v[0], (double)v[1]};
+      else
+        *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    };
+    auto put32 = [](float* dst, const T* v) {
+      *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    };
+    const int nF = TS * (wF / CH), nB = TS * (wB / CH);
+    for (int q0 = tid; q0 < nF; q0 += IU * (int)blockDim.x) {
+      T v[IU][CH];
 #pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const int q = q0 + u * (int)blockDim.x;
-        v[u] = q < nF ? L(I * TS + q % TS, I * TS - wF + q / TS) : T(0);
+      for (int u = 0; u < IU; ++u) {
+        const int q = q0 + u * (int)blockDim.x, r = q % TS, c0 = CH * (q / TS);
+#pragma unroll
+        for (int t = 0; t < CH; ++t) v[u][t] = q < nF ? L(I * TS + r, I * TS - wF + c0 + t) : T(0);
       }
 #pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const int q = q0 + u * (int)blockDim.x;
+      for (int u = 0; u < IU; ++u) {
+        const int q = q0 + u * (int)blockDim.x, r = q % TS, c0 = CH * (q / TS);
         if (q < nF) {
-          const int r = q % TS, cc = q / TS;
-          F[offF + ((int64_t)(cc / V) * TS + r) * V + (cc % V)] = v[u];
-          if (F2) F2[offF + ((int64_t)(cc / V2) * TS + r) * V2 + (cc % V2)] = (float)v[u];
+#pragma unroll
+          for (int h = 0; h < CH / V; ++h) put(F + offF + ((int64_t)((c0 + V * h) / V) * TS + r) * V, &v[u][V * h]);
+          if (F2) put32(F2 + offF + ((int64_t)(c0 / V2) * TS + r) * V2, v[u]);
         }
       }
     }
-    for (int q0 = tid; q0 < nB; q0 += PB * (int)blockDim.x) {
-      T v[PB];
+    for (int q0 = tid; q0 < nB; q0 += IU * (int)blockDim.x) {
+      T v[IU][CH];
 #pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const int q = q0 + u * (int)blockDim.x;
-        v[u] = q < nB ? L((I + 1) * TS + q / TS, I * TS + q % TS) : T(0);
+      for (int u = 0; u < IU; ++u) {
+        const int q = q0 + u * (int)blockDim.x, c = q % TS, r0 = CH * (q / TS);
+#pragma unroll
+        for (int t = 0; t < CH; ++t) v[u][t] = q < nB ? L((I + 1) * TS + r0 + t, I * TS + c) : T(0);
       }
 #pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const int q = q0 + u * (int)blockDim.x;
+      for (int u = 0; u < IU; ++u) {
+        const int q = q0 + u * (int)blockDim.x, c = q % TS, r0 = CH * (q / TS);
         if (q < nB) {
-          const int c = q % TS, rr = q / TS;
-          Bk[offB + ((int64_t)((TS + rr) / V) * TS + c) * V + ((TS + rr) % V)] = v[u];
-          if (B2) B2[offB + ((int64_t)((TS + rr) / V2) * TS + c) * V2 + ((TS + rr) % V2)] = (float)v[u];
+#pragma unroll
+          for (int h = 0; h < CH / V; ++h)
+            put(Bk + offB + ((int64_t)((TS + r0 + V * h) / V) * TS + c) * V, &v[u][V * h]);
+          if (B2) put32(B2 + offB + ((int64_t)((TS + r0) / V2) * TS + c) * V2, v[u]);
         }
       }
     }
