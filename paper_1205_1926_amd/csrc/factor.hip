@@ -54,16 +54,44 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
   const int b = s.b, Wb = s.Wb, n = s.npad, nb = n / TS;
   const int tid = threadIdx.x;
   auto L = [&](int r, int c) -> T { return (c <= r && r - c <= b && c >= 0) ? (T)A[(int64_t)r * Wb + (c - r + b)] : T(0); };
-  // block rows I = blockIdx.x, blockIdx.x + gridDim.x, ...
-  for (int I = blockIdx.x; I < nb; I += gridDim.x) {
-    const int64_t offF = panel_fwd_offset(I, TS, s.bo), offB = panel_bwd_offset(I, TS, s.bo, n);
-    const int wF = I * TS < s.bo ? I * TS : s.bo;
-    const int rem = n - (I + 1) * TS;
+  auto put = [](T* dst, const double* v) {
+    if constexpr (V == 2)
+      *reinterpret_cast<double2*>(dst) = double2{v[0], v[1]};
+    else
+      *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+  };
+  auto put32 = [](float* dst, const double* v) {
+    *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+  };
+  // entries of a TS x TS tile per thread, loaded one tile ahead
+  constexpr int TPT = (TS * TS + 255) / 256;
+  // block columns J = blockIdx.x, blockIdx.x + gridDim.x, ...: the diagonal
+  // tile (inverted, into block row J's forward panel and block column J's
+  // backward panel), then the tiles (I, J) below it inside the backward
+  // window, each read once and written as one contiguous block of block
+  // column J's backward panel and one of block row I's forward panel
+  for (int J = blockIdx.x; J < nb; J += gridDim.x) {
+    const int64_t offF = panel_fwd_offset(J, TS, s.bo), offB = panel_bwd_offset(J, TS, s.bo, n);
+    const int wF = J * TS < s.bo ? J * TS : s.bo;
+    const int rem = n - (J + 1) * TS;
     const int wB = rem < s.bo ? rem : s.bo;
+    // the first tile below the diagonal is requested before the diagonal
+    // tile's inversion, so that its loads are in flight meanwhile
+    const int nI = (wB + TS - 1) / TS;
+    double nx[TPT];
+    auto fetch = [&](int I, double (&v)[TPT]) {
+#pragma unroll
+      for (int u = 0; u < TPT; ++u) {
+        const int q = tid + 256 * u;
+        v[u] = q < TS * TS ? (double)L(I * TS + q / TS, J * TS + q % TS) : 0.0;
+      }
+    };
+    __syncthreads();
     for (int q = tid; q < TS * TS; q += blockDim.x) {
       int i = q / TS, j = q % TS;
-      sD[i][j] = (i >= j) ? (double)L(I * TS + i, I * TS + j) : 0.0;
+      sD[i][j] = (i >= j) ? (double)L(J * TS + i, J * TS + j) : 0.0;
     }
+    if (nI > 0) fetch(J + 1, nx);
     __syncthreads();
     // inverse of the lower-triangular diagonal tile, one column per thread
     if (tid < TS) tile_inverse_column(&sD[0][0], TS + 1, TS, tid, sXd);
@@ -80,63 +108,64 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(const SubDev* __restri
         B2[offB + ((int64_t)(r / V2) * TS + c) * V2 + (r % V2)] = (float)x;
       }
     }
-    // off-diagonal part of the forward panel, columns I TS - wF .. I TS - 1,
-    // and of the backward panel, rows (I+1) TS .. + wB - 1, in items of CH =
-    // 4 consecutive columns (forward) or rows (backward) of one row (column):
-    // a thread stores whole 16-byte chunks (CH / V of them, and one FP32
-    // chunk of the second copy), consecutive threads consecutive chunks;
-    // IU items' band entries are requested before any is stored.  wF and wB
-    // are multiples of 4 (bo is, and so are TS and n).
-    constexpr int CH = 4, IU = 4;
-    static_assert(CH % V == 0 && CH == V2, "an item is whole chunks of both layouts");
-    auto put = [](T* dst, const T* v) {
-      if constexpr (V == 2)
-        *reinterpret_cast<double2*>(dst) = double2{(double)v[0], (double)v[1]};
-      else
-        *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
-    };
-    auto put32 = [](float* dst, const T* v) {
-      *reinterpret_cast<float4*>(dst) = float4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
-    };
-    const int nF = TS * (wF / CH), nB = TS * (wB / CH);
-    for (int q0 = tid; q0 < nF; q0 += IU * (int)blockDim.x) {
-      T v[IU][CH];
+    // tiles below the diagonal: block rows I = J + 1 .. while the block row
+    // starts inside the backward window (wB and the forward windows are
+    // multiples of 4, so every 16-byte chunk is wholly in or out)
+    for (int t = 0; t < nI; ++t) {
+      const int I = J + 1 + t;
+      __syncthreads();  // the previous tile (or the diagonal) is written out
 #pragma unroll
-      for (int u = 0; u < IU; ++u) {
-        const int q = q0 + u * (int)blockDim.x, r = q % TS, c0 = CH * (q / TS);
-#pragma unroll
-        for (int t = 0; t < CH; ++t) v[u][t] = q < nF ? L(I * TS + r, I * TS - wF + c0 + t) : T(0);
+      for (int u = 0; u < TPT; ++u) {
+        const int q = tid + 256 * u;
+        if (q < TS * TS) sD[q / TS][q % TS] = nx[u];
       }
+      if (t + 1 < nI) fetch(I + 1, nx);
+      __syncthreads();
+      // backward panel of block column J: rows rr0 + i, chunks of V rows
+      const int rr0 = t * TS;
+      for (int q = tid; q < TS * TS / V; q += blockDim.x) {
+        const int rl = q / TS, c = q % TS;
+        if (rr0 + rl * V < wB) {
+          double v[V];
 #pragma unroll
-      for (int u = 0; u < IU; ++u) {
-        const int q = q0 + u * (int)blockDim.x, r = q % TS, c0 = CH * (q / TS);
-        if (q < nF) {
-#pragma unroll
-          for (int h = 0; h < CH / V; ++h) put(F + offF + ((int64_t)((c0 + V * h) / V) * TS + r) * V, &v[u][V * h]);
-          if (F2) put32(F2 + offF + ((int64_t)(c0 / V2) * TS + r) * V2, v[u]);
+          for (int k = 0; k < V; ++k) v[k] = sD[rl * V + k][c];
+          put(Bk + offB + ((int64_t)((TS + rr0) / V + rl) * TS + c) * V, v);
         }
       }
-    }
-    for (int q0 = tid; q0 < nB; q0 += IU * (int)blockDim.x) {
-      T v[IU][CH];
+      if (B2)
+        for (int q = tid; q < TS * TS / V2; q += blockDim.x) {
+          const int rl = q / TS, c = q % TS;
+          if (rr0 + rl * V2 < wB) {
+            double v[V2];
 #pragma unroll
-      for (int u = 0; u < IU; ++u) {
-        const int q = q0 + u * (int)blockDim.x, c = q % TS, r0 = CH * (q / TS);
+            for (int k = 0; k < V2; ++k) v[k] = sD[rl * V2 + k][c];
+            put32(B2 + offB + ((int64_t)((TS + rr0) / V2 + rl) * TS + c) * V2, v);
+          }
+        }
+      // forward panel of block row I: its columns cf0 + j (those >= 0)
+      const int wFI = I * TS < s.bo ? I * TS : s.bo;
+      const int cf0 = wFI - (I - J) * TS;
+      const int64_t offFI = panel_fwd_offset(I, TS, s.bo);
+      for (int q = tid; q < TS * TS / V; q += blockDim.x) {
+        const int cl = q / TS, i = q % TS;
+        if (cf0 + cl * V >= 0) {
+          double v[V];
 #pragma unroll
-        for (int t = 0; t < CH; ++t) v[u][t] = q < nB ? L((I + 1) * TS + r0 + t, I * TS + c) : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < IU; ++u) {
-        const int q = q0 + u * (int)blockDim.x, c = q % TS, r0 = CH * (q / TS);
-        if (q < nB) {
-#pragma unroll
-          for (int h = 0; h < CH / V; ++h)
-            put(Bk + offB + ((int64_t)((TS + r0 + V * h) / V) * TS + c) * V, &v[u][V * h]);
-          if (B2) put32(B2 + offB + ((int64_t)((TS + r0) / V2) * TS + c) * V2, v[u]);
+          for (int k = 0; k < V; ++k) v[k] = sD[i][cl * V + k];
+          put(F + offFI + ((int64_t)((cf0 + cl * V) / V) * TS + i) * V, v);
         }
       }
+      if (F2)
+        for (int q = tid; q < TS * TS / V2; q += blockDim.x) {
+          const int cl = q / TS, i = q % TS;
+          if (cf0 + cl * V2 >= 0) {
+            double v[V2];
+#pragma unroll
+            for (int k = 0; k < V2; ++k) v[k] = sD[i][cl * V2 + k];
+            put32(F2 + offFI + ((int64_t)((cf0 + cl * V2) / V2) * TS + i) * V2, v);
+          }
+        }
     }
-    __syncthreads();
   }
 }
 
