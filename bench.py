@@ -35,8 +35,9 @@ cpu_baseline: the oracle's F-apply on a sample of 8 subdomains of the same
 shape, run by one process per host core at once and scaled to the whole
 mesh; plus the oracle's full-size single-core timings of load step 1.
 
-One compact JSON line goes to stdout; progress and per-iteration detail go
-to stderr (and, with --detail PATH, to a JSON file).
+One compact JSON line goes to stdout; the full record, progress and
+per-iteration detail go to stderr (and, with --detail PATH, the detail to a
+JSON file).
 
 --plate LEVEL runs the notched-plate benchmark instead (the box stand-in for
 the paper's Section 5 plate with a hole): time discretizations (a) one step
@@ -194,6 +195,43 @@ def describe(w, sz) -> str:
     load = " + ".join(t for t, v in (("x shear", top[0]), ("y shear", top[1]), ("z traction", top[2])) if v)
     return (f"{w.name}: unit cube of Q1 hexahedra, {sz['n_sub']} box subdomains of {sub}, {sz['n_torn']} torn DOF, "
             f"{sz['m']} multipliers, clamped bottom, top face {load}, load ramp over {w.steps} steps")
+
+
+def compact(line: dict, head: str, sz: dict, w) -> dict:
+    """The stdout record: the full one's headline fields, short."""
+    out = {k: line[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    cfg = dict(line["config"])
+    cfg["workload"] = (f"{w.name}: {sz['n_sub']} box subdomains, {sz['n_torn']} torn DOF, {sz['m']} multipliers, "
+                       f"load ramp over {w.steps} steps")
+    out["config"] = cfg
+    for k in ("newton_step_ms", "pcg_iters_per_s", "fapply_isolated_ms"):
+        out[k] = line[k]
+    rf = line["roofline"]
+    out["roofline"] = {k: rf[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
+    out["legs"] = {n: [r["value"], r["newton_step_ms"]] for n, r in line["legs"].items()}
+    acc = line["rel_error_vs_oracle"]
+    if acc:
+        err = {"load_step": acc.get("load_step")}
+        for k in ("u", "lam"):
+            if isinstance(acc.get(k), dict) and acc[k]:
+                err[k] = acc[k].get(head)
+                err[k + "_max_legs"] = max(v for v in acc[k].values() if v is not None)
+        after = acc.get("u_after_timed_vs_fp64_plain")
+        if after:
+            err["u_after_timed_vs_fp64_plain"] = max(after.values())
+        out["rel_error_vs_oracle"] = err
+    cpu = line["cpu_baseline"]
+    if cpu:
+        c = {k: cpu[k] for k in ("value", "unit", "cores", "kind", "cpu", "nproc") if k in cpu}
+        c["sample"] = "oracle F-apply of 2x2x2 subdomains of 8^3 in each process, scaled to 1000 subdomains"
+        full = cpu.get("oracle_full_size_1core")
+        if full:
+            c["full_size_1core_s"] = {k: full[k] for k in ("fapply_s", "pcg_iter_s", "newton_step_s")}
+        out["cpu_baseline"] = c
+    if "newton_step_speedup_vs_fp64_plain" in line:
+        out["newton_step_speedup_vs_fp64_plain"] = line["newton_step_speedup_vs_fp64_plain"]
+    return out
 
 
 def measured_traffic(workload: str, precision: str, tile: int, threads: int):
@@ -560,7 +598,11 @@ def main() -> int:
     }
     if "fp64_plain" in results and legs[0] != "fp64_plain":
         line["newton_step_speedup_vs_fp64_plain"] = newton_ms["fp64_plain"] / newton_ms[legs[0]]
-    print(json.dumps(rounded(line), separators=(",", ":"), ensure_ascii=False), flush=True)
+    # everything on stderr; on stdout one short line with the same headline
+    # fields, the legs as [F-applies/s, Newton-step ms] and the errors as
+    # the headline leg's and the largest over the legs
+    log("full result: " + json.dumps(rounded(line), separators=(",", ":"), ensure_ascii=False))
+    print(json.dumps(rounded(compact(line, legs[0], sz, w)), separators=(",", ":"), ensure_ascii=False), flush=True)
     try:
         os.remove(ref_path)
         os.rmdir(tmp)
