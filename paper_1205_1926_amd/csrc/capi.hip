@@ -120,6 +120,8 @@ struct tfeti_handle {
   // factorization fails until the next assembly
   bool fact_failed = false;
   int64_t last_plastic = 0;
+  bool plcount_pending = false;  // d_plcount holds a count not yet read into last_plastic
+  bool subpl_fresh = true;       // subpl is sub_plastic of the current d_plastic
   // timing of the F-apply solve kernel
   bool timing = false;
   double t_ms = 0.0;
@@ -818,6 +820,7 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
   launch_sub_plastic(h->d_subs, M.n_sub, h->d_plastic, h->d_subpl, h->st);
   HIPCHK(hipMemcpyAsync(h->subpl.data(), h->d_subpl, M.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
+  h->subpl_fresh = true;
   std::vector<uint8_t> need(M.n_sub, 0);
   std::vector<int32_t> alist, rlist;
   for (int64_t p = 0; p < M.n_sub; ++p) {
@@ -876,12 +879,24 @@ int assemble_at(tfeti_handle* h, const double* du, double* fint) {
       }
     }
   }
-  unsigned long long cnt = 0;
-  HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
-  h->last_plastic = (int64_t)cnt;
+  // the plastic Gauss-point count is read with the next scalar the host needs
+  h->plcount_pending = true;
   h->factored = false;
   h->fact_failed = false;
+  return 0;
+}
+
+// The plastic Gauss points of the last assembly (one device read if the
+// count has not been fetched with another scalar yet).
+int plastic_gp_count(tfeti_handle* h, int64_t* out) {
+  if (h->plcount_pending) {
+    unsigned long long cnt = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    h->last_plastic = (int64_t)cnt;
+    h->plcount_pending = false;
+  }
+  *out = h->last_plastic;
   return 0;
 }
 
@@ -1116,9 +1131,14 @@ int factorize(tfeti_handle* h) {
   if (h->opt.refactor_all) {
     for (int64_t p = 0; p < M.n_sub; ++p) list.push_back((int32_t)p);
   } else {
-    launch_sub_plastic(h->d_subs, M.n_sub, h->d_plastic, h->d_subpl, h->st);
-    HIPCHK(hipMemcpyAsync(h->subpl.data(), h->d_subpl, M.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
+    // the plastic flags change only in assemble_at, which brings subpl up
+    // to date; otherwise it is fetched here
+    if (!h->subpl_fresh) {
+      launch_sub_plastic(h->d_subs, M.n_sub, h->d_plastic, h->d_subpl, h->st);
+      HIPCHK(hipMemcpyAsync(h->subpl.data(), h->d_subpl, M.n_sub * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
+      h->subpl_fresh = true;
+    }
     for (int64_t p = 0; p < M.n_sub; ++p) {
       if (h->subpl[p])
         list.push_back((int32_t)p);
@@ -1639,7 +1659,20 @@ int tfeti_newton_step(tfeti_handle* h, tfeti_newton_report* rep) {
   h->assembled_at_du = true;
   launch_copy(M.n_torn, h->d_df, h->d_f, h->st);
   launch_axpby(M.n_torn, -1.0, h->d_fint, 1.0, h->d_f, h->st);
-  double fn = assembled_norm(h, h->d_f);
+  // the residual norm and the assembly's plastic Gauss-point count in one read
+  double fn = 0.0;
+  {
+    launch_assembled_sq(M.n_gdof, h->d_g_rp, h->d_g_copies, h->d_g_free, h->d_f, h->d_partials, h->st);
+    launch_sum_partials(h->d_partials, reduction_blocks(M.n_gdof), h->d_scal, h->st);
+    double sq = 0.0;
+    unsigned long long cnt = 0;
+    HIPCHK(hipMemcpyAsync(&sq, h->d_scal, sizeof(sq), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipMemcpyAsync(&cnt, h->d_plcount, sizeof(cnt), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    fn = std::sqrt(sq);
+    h->last_plastic = (int64_t)cnt;
+    h->plcount_pending = false;
+  }
   r.relres = h->df_norm > 0 ? fn / h->df_norm : 0.0;
   r.plastic_gp = (int32_t)h->last_plastic;
   r.ms_assembly = ms_since(t0);
@@ -1693,25 +1726,28 @@ int tfeti_newton_step(tfeti_handle* h, tfeti_newton_report* rep) {
   r.pcg_iters = pr.iters;
   r.fapplies = pr.fapplies;
   r.warm_choice = pr.warm_choice;
-  // the paper's increment criterion, untorn norms
-  double nd = untorn_norm(h, h->d_delta);
-  double nold = untorn_norm(h, h->d_du);
-  launch_axpby(M.n_torn, 1.0, h->d_delta, 1.0, h->d_du, h->st);
-  h->assembled_at_du = false;
-  double nnew = untorn_norm(h, h->d_du);
-  r.crit = (nnew + nold) > 0 ? nd / (nnew + nold) : 0.0;
-  // plastic elements
+  // the paper's increment criterion (untorn norms of the correction and of
+  // the increment before and after it) and the plastic elements, reduced on
+  // the device into four scalars read back together
   {
-    std::vector<uint8_t> pl(M.n_gp);
-    HIPCHK(hipMemcpyAsync(pl.data(), h->d_plastic, M.n_gp, hipMemcpyDeviceToHost, h->st));
+    const int nbg = reduction_blocks(M.n_gdof);
+    double* sc = h->d_scal + 8;
+    launch_untorn_sq(M.n_gdof, h->d_g_first, h->d_delta, h->d_partials, h->st);
+    launch_sum_partials(h->d_partials, nbg, sc + 0, h->st);
+    launch_untorn_sq(M.n_gdof, h->d_g_first, h->d_du, h->d_partials, h->st);
+    launch_sum_partials(h->d_partials, nbg, sc + 1, h->st);
+    launch_axpby(M.n_torn, 1.0, h->d_delta, 1.0, h->d_du, h->st);
+    h->assembled_at_du = false;
+    launch_untorn_sq(M.n_gdof, h->d_g_first, h->d_du, h->d_partials, h->st);
+    launch_sum_partials(h->d_partials, nbg, sc + 2, h->st);
+    launch_plastic_elements(M.n_elem, h->d_plastic, h->d_partials, h->st);
+    launch_sum_partials(h->d_partials, reduction_blocks(M.n_elem), sc + 3, h->st);
+    double v[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(v, sc, sizeof(v), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
-    int64_t ne = 0;
-    for (int64_t e = 0; e < M.n_elem; ++e) {
-      bool any = false;
-      for (int g = 0; g < 8; ++g) any |= pl[8 * e + g] != 0;
-      ne += any;
-    }
-    r.plastic_elements = (int32_t)ne;
+    const double nd = std::sqrt(v[0]), nold = std::sqrt(v[1]), nnew = std::sqrt(v[2]);
+    r.crit = (nnew + nold) > 0 ? nd / (nnew + nold) : 0.0;
+    r.plastic_elements = (int32_t)std::llround(v[3]);
   }
   r.ms_total = ms_since(t0);
   if (rep) *rep = r;
@@ -1815,7 +1851,7 @@ int tfeti_assemble(tfeti_handle* h, const double* du, double* fint, int64_t* pla
   if (!h || !du || !fint) return TFETI_E_INVALID;
   RC(assemble_at(h, du, fint));
   h->assembled_at_du = false;
-  if (plastic_count) *plastic_count = h->last_plastic;
+  if (plastic_count) RC(plastic_gp_count(h, plastic_count));
   return TFETI_OK;
 }
 

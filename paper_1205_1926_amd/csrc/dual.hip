@@ -622,4 +622,22 @@ void launch_untorn_sq(int64_t n_gdof, const int64_t* g_first, const double* v, d
   untorn_sq_kernel<<<dim3(reduction_blocks(n_gdof)), dim3(RB), 0, st>>>(n_gdof, g_first, v, partials);
 }
 
+// Elements with a plastic Gauss point (the 8 flags of element e are bytes
+// 8e .. 8e + 7), per workgroup, as doubles for launch_sum_partials.
+__global__ __launch_bounds__(RB) void plastic_elements_kernel(int64_t n_elem, const uint8_t* __restrict__ pl,
+                                                              double* __restrict__ partials) {
+  __shared__ double sh[RB];
+  double c = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n_elem; e += (int64_t)gridDim.x * RB) {
+    const uint2 v = *reinterpret_cast<const uint2*>(pl + 8 * e);
+    c += (v.x | v.y) != 0u ? 1.0 : 0.0;
+  }
+  double s = block_sum(c, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+void launch_plastic_elements(int64_t n_elem, const uint8_t* plastic, double* partials, hipStream_t st) {
+  plastic_elements_kernel<<<dim3(reduction_blocks(n_elem)), dim3(RB), 0, st>>>(n_elem, plastic, partials);
+}
+
 }  // namespace tfeti

@@ -266,6 +266,8 @@ void launch_assembled_sq(int64_t n_gdof, const int32_t* g_rp, const int64_t* g_c
 // partial sums of v[g_first[i]]^2 and (v + w)[g_first]^2 etc. (kind selects)
 void launch_untorn_sq(int64_t n_gdof, const int64_t* g_first, const double* v, double* partials, hipStream_t st);
 void launch_sum_partials(const double* partials, int n, double* out, hipStream_t st);
+// per-workgroup counts of the elements with a plastic Gauss point (reduction_blocks(n_elem) partials)
+void launch_plastic_elements(int64_t n_elem, const uint8_t* plastic, double* partials, hipStream_t st);
 
 // ---- learned warm start ---------------------------------------------------------
 struct WarmMaps {
