@@ -128,7 +128,24 @@ typedef struct {
   int32_t refactor_all;         /* 1: factorize every subdomain each Newton
                                    iteration; 0: keep the factor of a subdomain
                                    whose tangent is and was the elastic one      */
+  int32_t fapply_format;        /* F-applies inside the PCGP loop (and
+                                   tfeti_fapply) through
+                                   TFETI_FAPPLY_FACTORS or
+                                   TFETI_FAPPLY_EXPLICIT                        */
+  int32_t pad;
 } tfeti_options;
+#define TFETI_FAPPLY_FACTORS 0  /* forward and backward substitution with the
+                                   packed Cholesky factors (Remark 1 in Section
+                                   4.2)                                         */
+#define TFETI_FAPPLY_EXPLICIT 1 /* explicit local dual operators: per subdomain
+                                   the block of K_reg^{-1} on the DOFs that
+                                   carry rows of B, formed on the matrix cores
+                                   from the FP64 factor whenever the subdomain
+                                   is factorized (or its elastic factor is
+                                   copied back), stored as the lower triangle in
+                                   the F-apply's precision and applied as one
+                                   symmetric product; d, lambda_Im, the FP32
+                                   outer refinement and u keep the factors      */
 
 /* ---- reports (host structs) ------------------------------------------- */
 typedef struct {
@@ -180,6 +197,8 @@ typedef struct {
                                    them faster: few or uneven subdomains per
                                    compute unit)                                 */
   int32_t pad;
+  int64_t explicit_bytes;       /* bytes one explicit F-apply reads of the local
+                                   operators (0 unless TFETI_FAPPLY_EXPLICIT)    */
 } tfeti_sizes;
 
 typedef struct tfeti_handle tfeti_handle;

@@ -19,6 +19,8 @@ TFETI_E_OOM = -3
 TFETI_E_NOT_SPD = -4
 PREC_FP64 = 0
 PREC_FP32 = 1
+FAPPLY_FACTORS = 0
+FAPPLY_EXPLICIT = 1
 
 
 class Material(C.Structure):
@@ -35,7 +37,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("preconditioner", C.c_int32), ("eps_pcg", C.c_double),
                 ("eps_newton", C.c_double), ("max_pcg", C.c_int32), ("max_newton", C.c_int32),
                 ("warm_start", C.c_int32), ("use_graph", C.c_int32), ("tile", C.c_int32),
-                ("refine_eps", C.c_double), ("check_every", C.c_int32), ("refactor_all", C.c_int32)]
+                ("refine_eps", C.c_double), ("check_every", C.c_int32), ("refactor_all", C.c_int32),
+                ("fapply_format", C.c_int32), ("pad", C.c_int32)]
 
 
 class PcgReport(C.Structure):
@@ -57,7 +60,8 @@ class Sizes(C.Structure):
                 ("m_U", C.c_int64), ("l", C.c_int64), ("n_elem", C.c_int64), ("n_gp", C.c_int64),
                 ("n_gdof", C.c_int64), ("skyline_entries", C.c_int64), ("factor_entries", C.c_int64),
                 ("factor_bytes", C.c_int64), ("tile", C.c_int32), ("precision", C.c_int32),
-                ("schedule", C.c_int32), ("autotuned", C.c_int32), ("threads", C.c_int32), ("pad", C.c_int32)]
+                ("schedule", C.c_int32), ("autotuned", C.c_int32), ("threads", C.c_int32), ("pad", C.c_int32),
+                ("explicit_bytes", C.c_int64)]
 
 
 class Mlp(C.Structure):
@@ -172,7 +176,7 @@ def make_problem(w):
 
 def make_options(w=None, precision=None, eps_pcg=None, eps_newton=None, preconditioner=1, max_pcg=5000,
                  max_newton=50, warm_start=1, use_graph=0, tile=0, refine_eps=0.0, check_every=8,
-                 refactor_all=0):
+                 refactor_all=0, fapply_format=0):
     o = Options()
     prec = precision if precision is not None else (w.precision if w is not None else "fp64")
     o.precision = PREC_FP32 if prec in ("fp32", PREC_FP32) else PREC_FP64
@@ -187,4 +191,5 @@ def make_options(w=None, precision=None, eps_pcg=None, eps_newton=None, precondi
     o.refine_eps = refine_eps
     o.check_every = check_every
     o.refactor_all = refactor_all
+    o.fapply_format = FAPPLY_EXPLICIT if fapply_format in ("explicit", FAPPLY_EXPLICIT) else FAPPLY_FACTORS
     return o

@@ -81,6 +81,17 @@ struct tfeti_handle {
   void* d_B = nullptr;          // backward panels (factor precision)
   double* d_F64 = nullptr;      // FP32 mode: FP64 panels of the same factor (outer refinement)
   double* d_B64 = nullptr;
+  // explicit local dual operators (options.fapply_format = TFETI_FAPPLY_EXPLICIT)
+  bool exf = false;
+  void* d_fx = nullptr;         // lower-triangle tiles (F-apply precision)
+  double* d_dinv = nullptr;     // diagonal-block inverses of the factors
+  double* d_zs = nullptr;       // forming scratch: ex_slots items of ex_zstride entries
+  int64_t *d_ex_foff = nullptr, *d_ex_doff = nullptr;
+  int32_t *d_ex_sfidx = nullptr, *d_ex_sit = nullptr, *d_ex_pos = nullptr;
+  int32_t *d_ex_items[2] = {};  // (subdomain, column block) of the copied-back and the factorized subdomains
+  std::vector<int32_t> ex_items[2];
+  int64_t ex_slots = 0, ex_zstride = 0, ex_bytes = 0;
+  int ex_ring = 0;
   // state
   double *d_sigma = nullptr, *d_kappa = nullptr, *d_dsigma = nullptr, *d_dkappa = nullptr;
   uint8_t* d_plastic = nullptr;
@@ -263,14 +274,43 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
   }
 }
 
+// out_iface = Ft B^T lam at the touched DOFs (explicit local operators in
+// the F-apply's precision)
+void explicit_apply(tfeti_handle* h, const double* lam, double* out_iface, const int32_t* done,
+                    const PcgFold& fold = PcgFold{}) {
+  ExplicitApply a{};
+  a.subs = h->d_subs;
+  a.order = h->d_order;
+  a.nsub = h->M.n_sub;
+  a.F = h->d_fx;
+  a.foff = h->d_ex_foff;
+  a.sit = h->d_ex_sit;
+  a.lam = lam;
+  a.lam_sign = 1.0;
+  a.out_iface = out_iface;
+  a.if_rp = h->d_if_rp;
+  a.if_row = h->d_if_row;
+  a.if_coef = h->d_if_coef;
+  a.done = done;
+  a.fold = fold;
+  if (h->prec == TFETI_PREC_FP64)
+    launch_explicit_apply<double>(a, h->max_iface, h->st);
+  else
+    launch_explicit_apply<float>(a, h->max_iface, h->st);
+}
+
 // q = F lam; optional partial sums of q.dotv
 // timed: bracket the solve kernel with timing events (loop F-applies only);
-// use64: in FP32 mode apply the FP64 factor instead.
+// use64: in FP32 mode apply the FP64 factor instead; factors: the factor
+// path also where explicit operators are in use.
 void fapply(tfeti_handle* h, const double* lam, double* q, const double* dotv, double* partials,
-            const int32_t* done, bool timed = false, bool use64 = false) {
+            const int32_t* done, bool timed = false, bool use64 = false, bool factors = false) {
   const bool rec = timed && h->timing && 2 * h->ev_used + 1 < (int)h->ev.size();
   if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], h->st);
-  ksolve(h, nullptr, lam, 1.0, h->d_iface, nullptr, nullptr, done, use64);
+  if (h->exf && !use64 && !factors)
+    explicit_apply(h, lam, h->d_iface, done);
+  else
+    ksolve(h, nullptr, lam, 1.0, h->d_iface, nullptr, nullptr, done, use64);
   if (rec) {
     (void)hipEventRecord(h->ev[2 * h->ev_used + 1], h->st);
     h->ev_used++;
@@ -417,7 +457,10 @@ void enqueue_iteration_b(tfeti_handle* h, const int32_t* done) {
 
 // The subdomain-solve kernel of one iteration's F-apply, on p = y + beta p.
 void iteration_ksolve(tfeti_handle* h, const int32_t* done) {
-  ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done, false, nullptr, nullptr, fold_direction(h));
+  if (h->exf)
+    explicit_apply(h, h->d_p, h->d_iface, done, fold_direction(h));
+  else
+    ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done, false, nullptr, nullptr, fold_direction(h));
 }
 
 // The F-apply's subdomain-solve kernel of one iteration (timed if asked).
@@ -913,6 +956,105 @@ void pack(tfeti_handle* h, int64_t count, const int32_t* list, const double* ban
   }
 }
 
+// Form the explicit local operators of the listed subdomains (host list ps,
+// the same list on the device in dlist) from their FP64 factors in band;
+// k selects the item buffer (0 copied-back, 1 factorized subdomains).
+int form_explicit(tfeti_handle* h, const std::vector<int32_t>& ps, const int32_t* dlist, const double* band, int k) {
+  if (!h->exf || ps.empty()) return 0;
+  launch_diag_inverse(h->d_subs, (int64_t)ps.size(), dlist, band, h->d_ex_doff, h->d_dinv, h->st);
+  std::vector<int32_t>& it = h->ex_items[k];
+  it.clear();
+  for (int32_t p : ps)
+    for (int32_t cb = 0; cb < (h->M.subs[p].n_iface + 15) / 16; ++cb) {
+      it.push_back(p);
+      it.push_back(cb);
+    }
+  const int64_t n = (int64_t)it.size() / 2;
+  if (n == 0) return 0;
+  HIPCHK(hipMemcpyAsync(h->d_ex_items[k], it.data(), it.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
+  ExplicitForm a{};
+  a.subs = h->d_subs;
+  a.band = band;
+  a.dinv = h->d_dinv;
+  a.doff = h->d_ex_doff;
+  a.sfidx = h->d_ex_sfidx;
+  a.pos = h->d_ex_pos;
+  a.foff = h->d_ex_foff;
+  a.items = h->d_ex_items[k];
+  a.zs = h->d_zs;
+  a.zstride = h->ex_zstride;
+  a.ring = h->ex_ring;
+  a.F = h->d_fx;
+  for (int64_t i0 = 0; i0 < n; i0 += h->ex_slots) {
+    const int64_t cnt = std::min(h->ex_slots, n - i0);
+    if (h->prec == TFETI_PREC_FP64)
+      launch_explicit_form<double>(a, i0, cnt, h->st);
+    else
+      launch_explicit_form<float>(a, i0, cnt, h->st);
+  }
+  return 0;
+}
+
+// Maps and storage of the explicit local operators: touched DOFs in
+// ascending factor index per subdomain, tile and diagonal-block offsets, the
+// operators (zero: padding entries are never written) and the forming
+// scratch (at most 2 GiB, a launch forms that many column blocks).
+int setup_explicit(tfeti_handle* h) {
+  const HostModel& M = h->M;
+  std::vector<int32_t> sfidx(M.n_iface), sit(M.n_iface), pos(M.n_torn, -1);
+  std::vector<int64_t> foff(M.n_sub), doff(M.n_sub);
+  int64_t nf = 0, nd = 0, items = 0;
+  int nbr_max = 0;
+  for (int64_t p = 0; p < M.n_sub; ++p) {
+    const SubDev& s = M.subs[p];
+    std::vector<int32_t> t(s.n_iface);
+    std::iota(t.begin(), t.end(), 0);
+    std::sort(t.begin(), t.end(), [&](int32_t x, int32_t y) {
+      return M.if_fidx[s.iface_off + x] < M.if_fidx[s.iface_off + y];
+    });
+    for (int32_t i = 0; i < s.n_iface; ++i) {
+      const int32_t f = M.if_fidx[s.iface_off + t[i]];
+      sfidx[s.iface_off + i] = f;
+      sit[s.iface_off + i] = (int32_t)(s.iface_off + t[i]);
+      pos[s.dof_off + f] = i;
+    }
+    foff[p] = nf;
+    doff[p] = nd;
+    nf += explicit_tiles(s.n_iface) * 256;
+    nd += (int64_t)(s.ndof + 15) / 16 * 512;
+    items += (s.n_iface + 15) / 16;
+    nbr_max = std::max(nbr_max, (s.ndof + 15) / 16);
+  }
+  const size_t esz = h->prec == TFETI_PREC_FP64 ? sizeof(double) : sizeof(float);
+  h->ex_bytes = nf * (int64_t)esz;
+  h->ex_ring = (h->bmax + 15) / 16 + 1;
+  // LDS of the forming (ring of 16 x 16 blocks) and apply (x and two
+  // partial results) kernels, within the 64 KiB a launch gets by default
+  if ((int64_t)h->ex_ring * 256 * 8 > 65536)
+    return fail(h, TFETI_E_INVALID, "a subdomain's half bandwidth (" + std::to_string(h->bmax) +
+                                        ") is too wide for the explicit operators' forming kernel");
+  if ((int64_t)3 * ((h->max_iface + 15) / 16 * 16) * 8 > 65536)
+    return fail(h, TFETI_E_INVALID, "a subdomain has too many touched DOFs (" + std::to_string(h->max_iface) +
+                                        ") for the explicit operators' apply kernel");
+  h->ex_zstride = (int64_t)nbr_max * 256;
+  h->ex_slots = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t(1) << 31) / (h->ex_zstride * 8)));
+  RC(upload(h, &h->d_ex_sfidx, sfidx));
+  RC(upload(h, &h->d_ex_sit, sit));
+  RC(upload(h, &h->d_ex_pos, pos));
+  RC(upload(h, &h->d_ex_foff, foff));
+  RC(upload(h, &h->d_ex_doff, doff));
+  RC(dalloc(h, &h->d_ex_items[0], 2 * items));
+  RC(dalloc(h, &h->d_ex_items[1], 2 * items));
+  RC(dalloc(h, &h->d_dinv, nd));
+  RC(dalloc(h, &h->d_zs, h->ex_slots * h->ex_zstride));
+  if (h->prec == TFETI_PREC_FP64)
+    RC(dalloc(h, (double**)&h->d_fx, nf));
+  else
+    RC(dalloc(h, (float**)&h->d_fx, nf));
+  HIPCHK(hipMemset(h->d_fx, 0, (size_t)nf * esz));
+  return 0;
+}
+
 // Subdomain schedule: longest panel first (stable), or natural order.
 std::vector<int32_t> schedule(const HostModel& M, int natural) {
   std::vector<int32_t> order(M.n_sub);
@@ -966,7 +1108,7 @@ double time_fapply(tfeti_handle* h, int reps) {
   std::vector<float> t;
   for (int r = 0; r < reps + 2; ++r) {
     (void)hipEventRecord(e0, h->st);
-    fapply(h, h->d_lam, h->d_q, nullptr, nullptr, nullptr);
+    fapply(h, h->d_lam, h->d_q, nullptr, nullptr, nullptr, false, false, /*factors=*/true);
     (void)hipEventRecord(e1, h->st);
     (void)hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1152,6 +1294,7 @@ int factorize(tfeti_handle* h) {
     HIPCHK(hipMemcpyAsync(h->d_rlist, restore.data(), restore.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           h->st));
     pack(h, (int64_t)restore.size(), h->d_rlist, h->d_eband);
+    RC(form_explicit(h, restore, h->d_rlist, h->d_eband, 0));
     if (h->dirichlet) {
       const int64_t ni = interior_list(h, restore.data(), (int64_t)restore.size(), h->ilist_keep[1], h->d_ilist_r);
       pack_interior(h, ni, h->d_ilist_r, h->d_eiband);
@@ -1182,6 +1325,9 @@ int factorize(tfeti_handle* h) {
           launch_band_cholesky<double>(h->d_isubs, ni, h->d_ilist_f, h->d_iband, h->d_fail, h->ibmax, 0, h->st);
       }
     }
+    // a subdomain packed again keeps its explicit operator (formed from
+    // the same factor)
+    if (!fresh.empty()) RC(form_explicit(h, fresh, h->d_flist, h->d_band, 1));
     HIPCHK(hipMemcpyAsync(h->d_flist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
     const int64_t cnt = (int64_t)list.size();
     pack(h, cnt, h->d_flist);
@@ -1274,6 +1420,9 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   if (h->opt.precision != TFETI_PREC_FP64 && h->opt.precision != TFETI_PREC_FP32)
     return fail(h, TFETI_E_INVALID, "precision must be TFETI_PREC_FP64 or TFETI_PREC_FP32");
   h->prec = h->opt.precision;
+  if (h->opt.fapply_format != TFETI_FAPPLY_FACTORS && h->opt.fapply_format != TFETI_FAPPLY_EXPLICIT)
+    return fail(h, TFETI_E_INVALID, "fapply_format must be TFETI_FAPPLY_FACTORS or TFETI_FAPPLY_EXPLICIT");
+  h->exf = h->opt.fapply_format == TFETI_FAPPLY_EXPLICIT;
   int TS = h->opt.tile;
   h->tune_pending = TS == 0;
   if (TS == 0) TS = 32;
@@ -1451,6 +1600,7 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
     h->allocs.push_back(q);
     h->d_B = q;
   }
+  if (h->exf) RC(setup_explicit(h));
   // state
   RC(dalloc(h, &h->d_sigma, 6 * M.n_gp));
   RC(dalloc(h, &h->d_kappa, M.n_gp));
@@ -1618,6 +1768,8 @@ int tfeti_get_sizes(const tfeti_handle* h, tfeti_sizes* o) {
   o->schedule = h->natural;
   o->autotuned = h->tuned;
   o->threads = h->nt;
+  o->pad = 0;
+  o->explicit_bytes = h->exf ? h->ex_bytes : 0;
   return TFETI_OK;
 }
 
@@ -2004,6 +2156,8 @@ extern "C" int tfeti_model_host(const tfeti_problem* prob, int32_t tile, tfeti_s
   sizes->schedule = 0;
   sizes->autotuned = 0;
   sizes->threads = 256;
+  sizes->pad = 0;
+  sizes->explicit_bytes = 0;
   if (nnz) *nnz = (int64_t)M.b_col.size();
   if (rowptr) std::memcpy(rowptr, M.b_rowptr.data(), M.b_rowptr.size() * sizeof(int64_t));
   if (col) std::memcpy(col, M.b_col.data(), M.b_col.size() * sizeof(int64_t));

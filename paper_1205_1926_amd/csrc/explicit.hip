@@ -1,0 +1,452 @@
+// Explicit local dual operators (cheaper F-apply format).
+//
+// F = B K^+ B^T (Section 4.2) sums, over the subdomains, B_p K_p^+ B_p^T,
+// and B_p only touches the DOFs of subdomain p that carry rows of B.  With
+// K_p^+ the inverse of the regularized block (Remark 1: fixing nodes, then
+// a Cholesky factor L L^T), the touched block of that inverse,
+//
+//   Ft_p = S_p^T K_reg,p^{-1} S_p     (S_p: the columns of I at the touched DOFs),
+//
+// is a dense symmetric m_p x m_p matrix, and one F-apply needs only
+// Ft_p (B_p^T lambda)_touched per subdomain.  Stored as its lower triangle
+// in 16 x 16 tiles it holds about 5.4 MB in FP64 for an interior 8^3
+// subdomain (1158 touched DOFs), against the 8.6 MB of factor panels that
+// the two triangular sweeps of a subdomain solve read.
+//
+// Touched DOFs are taken in ascending factor index ("sorted position"), so
+// that column c of S_p has no entry before row f_c of the factor ordering:
+// L^{-1} S_p is zero above f_c and its solves can start there.
+//
+// Forming (once per factorization of the subdomain, on the FP64 matrix
+// cores, v_mfma_f64_16x16x4f64): each wavefront takes 16 consecutive sorted
+// columns C and computes W = L^{-T} L^{-1} S_C by block forward and backward
+// substitution over 16-row blocks of the band factor:
+//   forward  Z_I = D_I (S_I - sum_K L_IK Z_K),        K in [I - kb, I)
+//   backward W_I = D_I^T (Z_I - sum_K L_KI^T W_K),     K in (I, I + kb]
+// with D_I the inverse of the diagonal 16 x 16 block (diag_inverse_kernel)
+// and kb = ceil(b / 16).  The last kb + 1 blocks of Z (then W) stay in LDS
+// for the updates; Z goes to a scratch buffer for the backward sweep.  The
+// rows of W at touched DOFs of sorted position >= the first of C are the
+// lower-triangle entries of columns C of Ft_p.
+//
+// Applying (once per F-apply, HBM bound): one workgroup per subdomain;
+// each wavefront walks whole tile columns J and uses every off-diagonal
+// tile (I, J) twice, y_I += T x_J and y_J += T^T x_I, so the lower triangle
+// is read once.  Each wavefront accumulates into its own copy of y in LDS
+// and the copies are summed in a fixed order: the result does not depend on
+// scheduling.
+#include "kernels.h"
+
+namespace tfeti {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// tile (I, J), I >= J, of the lower triangle of an mt x mt tile grid, tiles
+// of one tile column contiguous
+__host__ __device__ inline int64_t tile_index(int64_t I, int64_t J, int64_t mt) {
+  return J * mt - J * (J - 1) / 2 + (I - J);
+}
+
+// Inverse X of each 16 x 16 diagonal block of the factor, in two orders
+// that put a lane's four matrix-core operands next to each other:
+//   block + 0:   X[i][g + 4 s]  at i * 16 + 4 g + s   (forward: X Z)
+//   block + 256: X[g + 4 s][i]  at i * 16 + 4 g + s   (backward: X^T W)
+// Rows past the last DOF are identity rows.  16 lanes per block, lane j
+// computes column j by forward substitution.
+__global__ __launch_bounds__(256) void diag_inverse_kernel(const SubDev* __restrict__ subs, int64_t count,
+                                                           const int32_t* __restrict__ list,
+                                                           const double* __restrict__ band,
+                                                           const int64_t* __restrict__ doff,
+                                                           double* __restrict__ dinv) {
+  if ((int64_t)blockIdx.x >= count) return;
+  const int64_t p = list ? list[blockIdx.x] : blockIdx.x;
+  const int ndof = subs[p].ndof, b = subs[p].b, Wm = subs[p].Wb - 1;
+  const double* A = band + subs[p].band_off;
+  double* D = dinv + doff[p];
+  const int nbr = (ndof + 15) / 16, j = threadIdx.x % 16;
+  for (int I = threadIdx.x / 16; I < nbr; I += 16) {
+    const int R0 = 16 * I;
+    double x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int R = R0 + i;
+      double acc = i == j ? 1.0 : 0.0;
+      if (R < ndof) {
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+          if (R0 + k >= R - b) acc -= A[(int64_t)R * Wm + R0 + k + b] * x[k];
+        acc /= A[(int64_t)R * Wm + R + b];
+      }
+      x[i] = acc;
+    }
+    double* X = D + (int64_t)I * 512;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      X[i * 16 + 4 * (j % 4) + j / 4] = x[i];
+      X[256 + j * 16 + 4 * (i % 4) + i / 4] = x[i];
+    }
+  }
+}
+
+// One wavefront per work item (subdomain p, column block cb of 16 sorted
+// touched DOFs).  The sweeps are flattened into a sequence of elements of
+// four values per lane (a factor tile, a diagonal inverse, or a block of Z
+// to start a backward row), fetched PD elements ahead into a ring of
+// registers, so that the fetches of the next tiles overlap the matrix-core
+// work of the current ones.
+//
+// MFMA operand order: in step s of a 16 x 16 x 4 product, lane l (row or
+// column l % 16, group g = l / 16) supplies contraction index 4 g + s for
+// factor tiles (four consecutive band entries of a row in forward, four
+// rows of a column in backward) and g + 4 s for the diagonal inverses,
+// whose B operand is then register s of the accumulator (rows g + 4 r).
+// Blocks of Z and W are kept in LDS row-major (16 x 16 per slot).
+template <typename T, int PD>
+__global__ __launch_bounds__(64) void explicit_form_kernel(ExplicitForm a, int64_t item0, int64_t n) {
+  extern __shared__ double ring[];
+  // consecutive items (of one subdomain) on one XCD: workgroups are dealt
+  // to the eight XCDs in turn
+  const int64_t per = (n + 7) / 8;
+  const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= n) return;
+  const int lane = threadIdx.x, li = lane % 16, g = lane / 16;
+  const int p = uniform(a.items[2 * (item0 + t)]), cb = uniform(a.items[2 * (item0 + t) + 1]);
+  const int ndof = uniform(a.subs[p].ndof), b = uniform(a.subs[p].b), Wm = uniform(a.subs[p].Wb - 1);
+  const int m = uniform(a.subs[p].n_iface);
+  const int64_t ioff = a.subs[p].iface_off, doff_t = a.subs[p].dof_off;
+  const double* A = a.band + a.subs[p].band_off;
+  const double* D = a.dinv + a.doff[p];
+  double* Zs = a.zs + t * a.zstride;
+  const int nbr = (ndof + 15) / 16, kb = (b + 15) / 16, RW = a.ring;
+  const int mt = (m + 15) / 16;
+  const int c = 16 * cb + li;
+  const int fj = c < m ? a.sfidx[ioff + c] : -1;
+  const int I0 = uniform(a.sfidx[ioff + 16 * cb]) / 16;
+  T* F = reinterpret_cast<T*>(a.F) + a.foff[p];
+
+  double rg[PD][4];
+  d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+
+  // ---- forward: elements (I, K), K in [max(I0, I - kb), I) factor tiles,
+  // K == I the diagonal inverse; I from I0 to nbr - 1
+  {
+    int lI = I0, lK = I0;  // fetch cursor
+    int cI = I0, cK = I0;  // consume cursor
+    auto advance = [&](int& I, int& K) {
+      if (K < I) {
+        ++K;
+      } else {
+        ++I;
+        K = I - kb > I0 ? I - kb : I0;
+      }
+    };
+    auto fetch = [&](int I, int K, double* d) {
+      if (I >= nbr) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d[s] = 0.0;
+      } else if (K < I) {
+        const int R = 16 * I + li;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int col = 16 * K + 4 * g + s, cc = col > R - b ? col : R - b;
+          d[s] = A[R * Wm + cc + b];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d[s] = D[(int64_t)I * 512 + li * 16 + 4 * g + s];
+      }
+    };
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      fetch(lI, lK, rg[u]);
+      advance(lI, lK);
+    }
+    bool end = false;
+    while (!end) {
+#pragma unroll
+      for (int u = 0; u < PD; ++u) {
+        if (!end) {
+          if (cK < cI) {
+            const int R = 16 * cI + li;
+            const double* Zk = ring + (cK % RW) * 256;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int col = 16 * cK + 4 * g + s;
+              const double va = (R < ndof && col >= R - b) ? -rg[u][s] : 0.0;
+              if (u & 1)
+                acc1 = mfma4(va, Zk[(4 * g + s) * 16 + li], acc1);
+              else
+                acc0 = mfma4(va, Zk[(4 * g + s) * 16 + li], acc0);
+            }
+          } else {
+            d4 tv = acc0 + acc1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tv[r] += (16 * cI + g + 4 * r == fj) ? 1.0 : 0.0;
+            d4 z = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) z = mfma4(rg[u][s], tv[s], z);
+            double* Zi = ring + (cI % RW) * 256;
+            double* Zg = Zs + (int64_t)(cI - I0) * 256;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              Zi[(g + 4 * r) * 16 + li] = z[r];
+              Zg[r * 64 + lane] = z[r];
+            }
+            acc0 = d4{0, 0, 0, 0};
+            acc1 = d4{0, 0, 0, 0};
+          }
+          advance(cI, cK);
+          fetch(lI, lK, rg[u]);
+          advance(lI, lK);
+          end = cI >= nbr;
+        }
+      }
+    }
+  }
+
+  // ---- backward: per row I from nbr - 1 down to I0: ph 0 the block Z_I,
+  // ph 1 factor tiles K in (I, min(nbr - 1, I + kb)], ph 2 the transposed
+  // diagonal inverse
+  {
+    auto khi = [&](int I) { return I + kb < nbr - 1 ? I + kb : nbr - 1; };
+    auto advance = [&](int& I, int& K, int& ph) {
+      if (ph == 0) {
+        if (I + 1 <= khi(I)) {
+          ph = 1;
+          K = I + 1;
+        } else {
+          ph = 2;
+        }
+      } else if (ph == 1) {
+        if (K < khi(I))
+          ++K;
+        else
+          ph = 2;
+      } else {
+        --I;
+        ph = 0;
+      }
+    };
+    auto fetch = [&](int I, int K, int ph, double* d) {
+      if (I < I0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d[s] = 0.0;
+      } else if (ph == 0) {
+        const double* Zg = Zs + (int64_t)(I - I0) * 256;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d[s] = Zg[s * 64 + lane];
+      } else if (ph == 1) {
+        const int col = 16 * I + li;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int R = 16 * K + 4 * g + s, cc = col > R - b ? col : R - b;
+          d[s] = A[R * Wm + cc + b];
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) d[s] = D[(int64_t)I * 512 + 256 + li * 16 + 4 * g + s];
+      }
+    };
+    int lI = nbr - 1, lK = 0, lph = 0;
+    int cI = nbr - 1, cK = 0, cph = 0;
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+      fetch(lI, lK, lph, rg[u]);
+      advance(lI, lK, lph);
+    }
+    bool end = false;
+    while (!end) {
+#pragma unroll
+      for (int u = 0; u < PD; ++u) {
+        if (!end) {
+          if (cph == 0) {
+            acc0 = d4{rg[u][0], rg[u][1], rg[u][2], rg[u][3]};
+            acc1 = d4{0, 0, 0, 0};
+          } else if (cph == 1) {
+            const int col = 16 * cI + li;
+            const double* Wk = ring + (cK % RW) * 256;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int R = 16 * cK + 4 * g + s;
+              const double va = (R < ndof && col >= R - b) ? -rg[u][s] : 0.0;
+              if (u & 1)
+                acc1 = mfma4(va, Wk[(4 * g + s) * 16 + li], acc1);
+              else
+                acc0 = mfma4(va, Wk[(4 * g + s) * 16 + li], acc0);
+            }
+          } else {
+            const d4 tv = acc0 + acc1;
+            d4 w = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) w = mfma4(rg[u][s], tv[s], w);
+            double* Wi = ring + (cI % RW) * 256;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              Wi[(g + 4 * r) * 16 + li] = w[r];
+              const int R = 16 * cI + g + 4 * r;
+              if (R < ndof) {
+                const int q = a.pos[doff_t + R];
+                if (q >= 0 && (q >> 4) >= cb)
+                  F[tile_index(q >> 4, cb, mt) * 256 + (q & 15) * 16 + li] = (T)w[r];
+              }
+            }
+          }
+          advance(cI, cK, cph);
+          fetch(lI, lK, lph, rg[u]);
+          advance(lI, lK, lph);
+          end = cI < I0;
+        }
+      }
+    }
+  }
+}
+
+// y = Ft_p x per subdomain (x = lam_sign B^T lam at the touched DOFs), the
+// result at the touched DOFs.  NW wavefronts per workgroup; lane l holds
+// row l / 4 and columns 4 (l % 4) .. + 3 of a tile; U tiles of a column are
+// fetched together.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void explicit_apply_kernel(ExplicitApply a) {
+  if (a.done && *a.done) return;
+  extern __shared__ double sh[];
+  constexpr int CH = (int)sizeof(T) * 256 / 16 / 64;  // 16-byte chunks per lane per tile
+  constexpr int U = 16 / CH;                          // tiles in flight per lane
+  typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type VT;
+  const int p = a.order ? a.order[blockIdx.x] : blockIdx.x;
+  const int m = a.subs[p].n_iface;
+  const int mt = (m + 15) / 16, mp = 16 * mt;
+  const int64_t ioff = a.subs[p].iface_off;
+  const T* F = reinterpret_cast<const T*>(a.F) + a.foff[p];
+  double* x = sh;
+  double* y = sh + mp;  // NW copies
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, rr = lane / 4, cq = lane % 4;
+
+  const double beta = a.fold.S ? a.fold.S->beta : 0.0;
+  for (int i = tid; i < mp; i += 64 * NW) {
+    double v = 0.0;
+    if (i < m) {
+      const int64_t it = a.sit[ioff + i];
+      v = a.lam_sign * seg_dot<4>(a.if_rp[it], a.if_rp[it + 1], a.if_row, a.if_coef, [&](int32_t row) {
+            return a.fold.S ? fma(beta, a.lam[row], a.fold.y[row]) : a.lam[row];
+          });
+    }
+    x[i] = v;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) y[w * mp + i] = 0.0;
+  }
+  __syncthreads();
+
+  double* yw = y + wave * mp;
+  for (int J = wave; J < mt; J += NW) {
+    double xj[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xj[c] = x[16 * J + 4 * cq + c];
+    double cp[4] = {0.0, 0.0, 0.0, 0.0};
+    const T* col = F + tile_index(J, J, mt) * 256 + rr * 16 + 4 * cq;
+    // tiles I = J .. mt - 1 of column J, U at a time (the diagonal tile
+    // contributes its rows only: it is stored whole)
+    for (int I0 = J; I0 < mt; I0 += U) {
+      VT v[U][CH];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int I = I0 + u < mt ? I0 + u : mt - 1;
+#pragma unroll
+        for (int h = 0; h < CH; ++h) v[u][h] = reinterpret_cast<const VT*>(col + (int64_t)(I - J) * 256)[h];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int I = I0 + u;
+        if (I < mt) {
+          double e[4];
+#pragma unroll
+          for (int h = 0; h < CH; ++h) {
+            if constexpr (sizeof(T) == 8) {
+              e[2 * h] = v[u][h].x;
+              e[2 * h + 1] = v[u][h].y;
+            } else {
+              e[0] = v[u][h].x;
+              e[1] = v[u][h].y;
+              e[2] = v[u][h].z;
+              e[3] = v[u][h].w;
+            }
+          }
+          double rp = e[0] * xj[0];
+#pragma unroll
+          for (int c = 1; c < 4; ++c) rp = fma(e[c], xj[c], rp);
+          rp += __shfl_xor(rp, 1);
+          rp += __shfl_xor(rp, 2);
+          if (cq == 0) yw[16 * I + rr] += rp;
+          if (I > J) {
+            const double xi = x[16 * I + rr];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cp[c] = fma(e[c], xi, cp[c]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double v = cp[c];
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      cp[c] = v;
+    }
+    if (rr == 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) yw[16 * J + 4 * cq + c] += cp[c];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += 64 * NW) {
+    double v = y[i];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += y[w * mp + i];
+    a.out_iface[a.sit[ioff + i]] = v;
+  }
+}
+
+}  // namespace
+
+int64_t explicit_tiles(int64_t m) {
+  const int64_t mt = (m + 15) / 16;
+  return mt * (mt + 1) / 2;
+}
+
+void launch_diag_inverse(const SubDev* subs, int64_t count, const int32_t* list, const double* band,
+                         const int64_t* doff, double* dinv, hipStream_t st) {
+  if (count > 0)
+    diag_inverse_kernel<<<dim3((unsigned)count), dim3(256), 0, st>>>(subs, count, list, band, doff, dinv);
+}
+
+template <typename T>
+void launch_explicit_form(const ExplicitForm& a, int64_t item0, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int64_t per = (n + 7) / 8;
+  const size_t lds = (size_t)a.ring * 256 * sizeof(double);
+  explicit_form_kernel<T, 8><<<dim3((unsigned)(8 * per)), dim3(64), lds, st>>>(a, item0, n);
+}
+
+template <typename T>
+void launch_explicit_apply(const ExplicitApply& a, int max_iface, hipStream_t st) {
+  constexpr int NW = 2;
+  const int mp = (max_iface + 15) / 16 * 16;
+  const size_t lds = (size_t)(NW + 1) * mp * sizeof(double);
+  explicit_apply_kernel<T, NW><<<dim3((unsigned)a.nsub), dim3(64 * NW), lds, st>>>(a);
+}
+
+template void launch_explicit_form<double>(const ExplicitForm&, int64_t, int64_t, hipStream_t);
+template void launch_explicit_form<float>(const ExplicitForm&, int64_t, int64_t, hipStream_t);
+template void launch_explicit_apply<double>(const ExplicitApply&, int, hipStream_t);
+template void launch_explicit_apply<float>(const ExplicitApply&, int, hipStream_t);
+
+}  // namespace tfeti

@@ -198,6 +198,53 @@ int64_t coarse_tiles(int64_t l);
 // Ginv in the coarse numbering; cidx (l entries) maps subdomain-order unknowns
 // to coarse positions
 void launch_coarse_pack(int64_t l, const double* Ginv, const int32_t* cidx, double* packed, hipStream_t st);
+
+// ---- explicit local dual operators (touched block of K_reg^{-1}) -----------
+// Touched DOFs of a subdomain in ascending factor index: sorted position i
+// of subdomain p is global touched index sit[iface_off + i], factor index
+// sfidx[iface_off + i]; pos[dof_off + r] is the sorted position of factor
+// row r, or -1.  Ft_p: lower-triangle 16 x 16 tiles (row-major), tile (I, J)
+// at foff[p] + 256 (J mt - J (J - 1) / 2 + I - J), mt = ceil(m_p / 16);
+// diagonal tiles whole, padding rows and columns zero.
+struct ExplicitForm {
+  const SubDev* subs;
+  const double* band;         // FP64 band factors
+  const double* dinv;         // diagonal-block inverses (512 entries per 16-row block)
+  const int64_t* doff;        // their offset per subdomain
+  const int32_t* sfidx;
+  const int32_t* pos;
+  const int64_t* foff;
+  const int32_t* items;       // (subdomain, column block) pairs
+  double* zs;                 // scratch: zstride entries per item of a launch
+  int64_t zstride;
+  int32_t ring;               // LDS blocks per wavefront (>= ceil(bmax / 16) + 1)
+  void* F;                    // Ft storage (double or float)
+};
+struct ExplicitApply {
+  const SubDev* subs;
+  const int32_t* order;       // workgroup -> subdomain, or nullptr
+  int64_t nsub;
+  const void* F;
+  const int64_t* foff;
+  const int32_t* sit;
+  const double* lam;
+  double lam_sign;
+  double* out_iface;          // z at the touched DOFs (global touched numbering)
+  const int32_t* if_rp;
+  const int32_t* if_row;
+  const double* if_coef;
+  const int32_t* done;
+  PcgFold fold;               // as in KsolveArgs
+};
+// tiles of the lower triangle of an m x m operator
+int64_t explicit_tiles(int64_t m);
+void launch_diag_inverse(const SubDev* subs, int64_t count, const int32_t* list, const double* band,
+                         const int64_t* doff, double* dinv, hipStream_t st);
+// items [item0, item0 + n) of a.items; n <= the scratch's item capacity
+template <typename T>
+void launch_explicit_form(const ExplicitForm& a, int64_t item0, int64_t n, hipStream_t st);
+template <typename T>
+void launch_explicit_apply(const ExplicitApply& a, int max_iface, hipStream_t st);
 // out = (x ? x : 0) - sign * G^T a; optional partial sums of out.out, or of
 // out.dotv when dotv is given
 void launch_gt_apply(const DualMaps& M, const double* x, const double* a, double sign, double* out,

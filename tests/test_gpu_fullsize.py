@@ -5,7 +5,7 @@ replay on):
 * the 10x10x10-subdomain cube and the uneven 8x8x8-subdomain mesh against
   the FP64 oracle at full size on the first (elastic) tangent: F-applies
   entry by entry and load step 1 (displacements and multipliers), FP64 and
-  FP32 panels on the same oracle reference;
+  FP32 panels and explicit local operators on the same oracle reference;
 * the 4x4x4-subdomain cube (139 968 torn DOFs): the first load steps against
   the FP64 oracle, displacement bar 1e-6;
 * the 10x10x10-subdomain cube (2 187 000 torn DOFs): K^+ on sampled
@@ -70,7 +70,8 @@ def ref_uneven8(dev):
 @pytest.mark.timeout(1200)
 @pytest.mark.parametrize("which", ["ref_cube10", "ref_uneven8"])
 def test_full_size_fapply_and_first_load_step_match_oracle(which, request, dev):
-    """Full-size oracle parity on the elastic tangent of load step 1.
+    """Full-size oracle parity on the elastic tangent of load step 1, with
+    the factor path and with the explicit local operators.
 
     F-apply: the cube's subdomains are cubes, whose fixing nodes are the
     oracle's, so F itself agrees entry by entry (FP64 panels to 1e-9 of the
@@ -86,23 +87,26 @@ def test_full_size_fapply_and_first_load_step_match_oracle(which, request, dev):
     cube = which == "ref_cube10"
     lam = ref["lam_F"] if cube else tf.project(ref["lam_F"])
     q_ref = ref["F_lam"] if cube else tf.project(tf.F(lam))
-    for precision, tol in (("fp64", 1e-9), ("fp32", 1e-5)):
-        g = GpuSolver(w, use_graph=1, precision=precision)
+    for precision, fmt, tol in (("fp64", "factors", 1e-9), ("fp32", "factors", 1e-5),
+                                ("fp64", "explicit", 1e-9), ("fp32", "explicit", 1e-5)):
+        _log(f"{w.name} {precision} {fmt}: F-apply")
+        g = GpuSolver(w, use_graph=1, precision=precision, fapply_format=fmt)
         g.begin_load_step()
         g.assemble(g.zeros(g.sizes["n_torn"]))
         g.factorize()
         q = g.fapply(T(lam, dev)).cpu().numpy()
         e_f = emax(q if cube else tf.project(q), q_ref)
         g.close()
-        g = GpuSolver(w, use_graph=1, precision=precision)
+        _log(f"{w.name} {precision} {fmt}: load step 1")
+        g = GpuSolver(w, use_graph=1, precision=precision, fapply_format=fmt)
         hist = g.load_step()
         u = g.state()["u"].cpu().numpy()
         e_u = rel(u[idx], ref["du"][idx])
         e_l = rel(g.lam().cpu().numpy(), ref["lam"])
-        _log(f"{w.name} {precision}: F entry error {e_f:.2e}, load step 1: {len(hist)} solve(s), "
+        _log(f"{w.name} {precision} {fmt}: F entry error {e_f:.2e}, load step 1: {len(hist)} solve(s), "
              f"PCGP {[r['pcg_iters'] for r in hist]} (oracle {ref['iters']}), u {e_u:.2e}, lambda {e_l:.2e}")
         g.close()
-        assert e_f <= tol, (precision, e_f)
+        assert e_f <= tol, (precision, fmt, e_f)
         assert len(hist) == 1 and hist[0]["plastic_gp"] == 0
         assert e_u <= 1e-6, (precision, e_u)
         assert e_l <= 1e-5, (precision, e_l)

@@ -130,3 +130,40 @@ def test_invalid_problem_rejected():
     w.absent = [(0, 2, 0)]
     with pytest.raises(ValueError):
         model_host(w)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes mirrors of the header's host structs have the C
+    compiler's size and field offsets (a field added on one side only would
+    shift every later one)."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_1205_1926_amd import _capi
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"tfeti_options": _capi.Options, "tfeti_sizes": _capi.Sizes, "tfeti_pcg_report": _capi.PcgReport,
+               "tfeti_newton_report": _capi.NewtonReport, "tfeti_problem": _capi.Problem,
+               "tfeti_material": _capi.Material, "tfeti_mlp": _capi.Mlp}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "tfeti.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        cname, f, v = line.split()
+        py = structs[cname]
+        want = ctypes.sizeof(py) if f == "sizeof" else getattr(py, f).offset
+        assert int(v) == want, (cname, f, int(v), want)
+        seen += 1
+    assert seen == sum(len(p._fields_) + 1 for p in structs.values())
