@@ -70,6 +70,10 @@ LEGS = {
     "fp64_dirichlet": dict(precision="fp64", use_graph=1, warm_start=1, preconditioner=2),
     "fp32_dirichlet": dict(precision="fp32", use_graph=1, warm_start=1, preconditioner=2),
     "fp32_learned": dict(precision="fp32", use_graph=1, warm_start=1),
+    # explicit local dual operators in place of the factor sweeps (formed at
+    # every factorization of a subdomain)
+    "fp64_explicit": dict(precision="fp64", use_graph=1, warm_start=1, fapply_format="explicit"),
+    "fp32_explicit": dict(precision="fp32", use_graph=1, warm_start=1, fapply_format="explicit"),
 }
 # the learned candidate of the fp32_learned leg (and of fp32_all with --learned)
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_1205_1926_amd", "weights", "warmstart_cube8x8x8_uneven.safetensors")
@@ -350,7 +354,9 @@ def run_leg(name, w, args, net, detail):
     g.set_timing(False)
     g.close()
     fb = 8 if opts["precision"] == "fp64" else 4
-    alg = 2 * sz["skyline_entries"] * fb
+    # algorithmic bytes of one F-apply: both sweeps over the factor envelope,
+    # or the stored lower triangles of the explicit operators
+    alg = sz["explicit_bytes"] if opts.get("fapply_format") == "explicit" else 2 * sz["skyline_entries"] * fb
     iso_kernel_s = iso_ms / max(iso_cnt, 1) / 1e3
     if k_cnt > 0:
         kernel_s, src = k_ms / k_cnt / 1e3, "timed load steps"
@@ -450,7 +456,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed load steps before them (at least 1)")
     ap.add_argument("--learned", default=None, help="safetensors weights of the warm-start network (fp32_all leg)")
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--legs", default="fp32_all,fp64_plain,fp64_graph_warm,fp64_dirichlet,fp32_learned",
+    ap.add_argument("--legs", default="fp32_all,fp64_plain,fp64_graph_warm,fp64_dirichlet,fp32_learned,fp64_explicit",
                     help="comma-separated forms; the first is the headline line")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--refine-eps", type=float, default=0.0, help="FP32 mode: inner PCGP tolerance")

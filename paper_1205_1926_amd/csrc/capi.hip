@@ -84,14 +84,14 @@ struct tfeti_handle {
   // explicit local dual operators (options.fapply_format = TFETI_FAPPLY_EXPLICIT)
   bool exf = false;
   void* d_fx = nullptr;         // lower-triangle tiles (F-apply precision)
-  double* d_dinv = nullptr;     // diagonal-block inverses of the factors
-  double* d_zs = nullptr;       // forming scratch: ex_slots items of ex_zstride entries
+  double* d_dinv = nullptr;     // diagonal-block inverses of the factors, then the
+                                // forming scratch (ex_slots groups of kExplicitWaves x ex_zstride entries)
   int64_t *d_ex_foff = nullptr, *d_ex_doff = nullptr;
   int32_t *d_ex_sfidx = nullptr, *d_ex_sit = nullptr, *d_ex_pos = nullptr;
   int32_t *d_ex_items[2] = {};  // (subdomain, column block) of the copied-back and the factorized subdomains
   std::vector<int32_t> ex_items[2];
-  int64_t ex_slots = 0, ex_zstride = 0, ex_bytes = 0;
-  int ex_ring = 0;
+  int64_t ex_slots = 0, ex_zstride = 0, ex_zs_off = 0, ex_bytes = 0;
+  int ex_kb = 0;
   // state
   double *d_sigma = nullptr, *d_kappa = nullptr, *d_dsigma = nullptr, *d_dkappa = nullptr;
   uint8_t* d_plastic = nullptr;
@@ -964,11 +964,13 @@ int form_explicit(tfeti_handle* h, const std::vector<int32_t>& ps, const int32_t
   launch_diag_inverse(h->d_subs, (int64_t)ps.size(), dlist, band, h->d_ex_doff, h->d_dinv, h->st);
   std::vector<int32_t>& it = h->ex_items[k];
   it.clear();
-  for (int32_t p : ps)
-    for (int32_t cb = 0; cb < (h->M.subs[p].n_iface + 15) / 16; ++cb) {
+  for (int32_t p : ps) {
+    const int32_t mt = (h->M.subs[p].n_iface + 15) / 16;
+    for (int32_t grp = 0; grp < (mt + kExplicitWaves - 1) / kExplicitWaves; ++grp) {
       it.push_back(p);
-      it.push_back(cb);
+      it.push_back(grp);
     }
+  }
   const int64_t n = (int64_t)it.size() / 2;
   if (n == 0) return 0;
   HIPCHK(hipMemcpyAsync(h->d_ex_items[k], it.data(), it.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
@@ -981,9 +983,10 @@ int form_explicit(tfeti_handle* h, const std::vector<int32_t>& ps, const int32_t
   a.pos = h->d_ex_pos;
   a.foff = h->d_ex_foff;
   a.items = h->d_ex_items[k];
-  a.zs = h->d_zs;
+  a.zs_off = h->ex_zs_off;
   a.zstride = h->ex_zstride;
-  a.ring = h->ex_ring;
+  a.kb = h->ex_kb;
+  a.max_ndof = h->max_ndof;
   a.F = h->d_fx;
   for (int64_t i0 = 0; i0 < n; i0 += h->ex_slots) {
     const int64_t cnt = std::min(h->ex_slots, n - i0);
@@ -1022,22 +1025,22 @@ int setup_explicit(tfeti_handle* h) {
     doff[p] = nd;
     nf += explicit_tiles(s.n_iface) * 256;
     nd += (int64_t)(s.ndof + 15) / 16 * 512;
-    items += (s.n_iface + 15) / 16;
+    items += ((s.n_iface + 15) / 16 + kExplicitWaves - 1) / kExplicitWaves;
     nbr_max = std::max(nbr_max, (s.ndof + 15) / 16);
   }
   const size_t esz = h->prec == TFETI_PREC_FP64 ? sizeof(double) : sizeof(float);
   h->ex_bytes = nf * (int64_t)esz;
-  h->ex_ring = (h->bmax + 15) / 16 + 1;
-  // LDS of the forming (ring of 16 x 16 blocks) and apply (x and two
-  // partial results) kernels, within the 64 KiB a launch gets by default
-  if ((int64_t)h->ex_ring * 256 * 8 > 65536)
+  h->ex_kb = explicit_form_kb(h->bmax);
+  // the forming kernel's staged rows and the apply kernel's LDS (x and two
+  // partial results, within the 64 KiB a launch gets by default)
+  if (h->ex_kb == 0)
     return fail(h, TFETI_E_INVALID, "a subdomain's half bandwidth (" + std::to_string(h->bmax) +
                                         ") is too wide for the explicit operators' forming kernel");
   if ((int64_t)3 * ((h->max_iface + 15) / 16 * 16) * 8 > 65536)
     return fail(h, TFETI_E_INVALID, "a subdomain has too many touched DOFs (" + std::to_string(h->max_iface) +
                                         ") for the explicit operators' apply kernel");
   h->ex_zstride = (int64_t)nbr_max * 256;
-  h->ex_slots = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t(1) << 31) / (h->ex_zstride * 8)));
+  h->ex_slots = std::max<int64_t>(1, std::min<int64_t>(items, (int64_t(1) << 31) / (h->ex_zstride * 8 * kExplicitWaves)));
   RC(upload(h, &h->d_ex_sfidx, sfidx));
   RC(upload(h, &h->d_ex_sit, sit));
   RC(upload(h, &h->d_ex_pos, pos));
@@ -1045,8 +1048,9 @@ int setup_explicit(tfeti_handle* h) {
   RC(upload(h, &h->d_ex_doff, doff));
   RC(dalloc(h, &h->d_ex_items[0], 2 * items));
   RC(dalloc(h, &h->d_ex_items[1], 2 * items));
-  RC(dalloc(h, &h->d_dinv, nd));
-  RC(dalloc(h, &h->d_zs, h->ex_slots * h->ex_zstride));
+  // diagonal-block inverses, then the forming scratch, in one buffer
+  h->ex_zs_off = (nd + 63) / 64 * 64;
+  RC(dalloc(h, &h->d_dinv, h->ex_zs_off + h->ex_slots * kExplicitWaves * h->ex_zstride));
   if (h->prec == TFETI_PREC_FP64)
     RC(dalloc(h, (double**)&h->d_fx, nf));
   else

@@ -49,6 +49,13 @@ __device__ __forceinline__ d4 mfma4(double a, double b, d4 c) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// v, for the compiler computed only once dep is (keeps loads from being
+// hoisted far ahead of their use)
+__device__ __forceinline__ int after(int v, double dep) {
+  asm volatile("" : "+v"(v) : "v"(dep));
+  return v;
+}
+
 // tile (I, J), I >= J, of the lower triangle of an mt x mt tile grid, tiles
 // of one tile column contiguous
 __host__ __device__ inline int64_t tile_index(int64_t I, int64_t J, int64_t mt) {
@@ -96,213 +103,206 @@ __global__ __launch_bounds__(256) void diag_inverse_kernel(const SubDev* __restr
   }
 }
 
-// One wavefront per work item (subdomain p, column block cb of 16 sorted
-// touched DOFs).  The sweeps are flattened into a sequence of elements of
-// four values per lane (a factor tile, a diagonal inverse, or a block of Z
-// to start a backward row), fetched PD elements ahead into a ring of
-// registers, so that the fetches of the next tiles overlap the matrix-core
-// work of the current ones.
-//
-// MFMA operand order: in step s of a 16 x 16 x 4 product, lane l (row or
-// column l % 16, group g = l / 16) supplies contraction index 4 g + s for
-// factor tiles (four consecutive band entries of a row in forward, four
-// rows of a column in backward) and g + 4 s for the diagonal inverses,
-// whose B operand is then register s of the accumulator (rows g + 4 r).
-// Blocks of Z and W are kept in LDS row-major (16 x 16 per slot).
-template <typename T, int PD>
-__global__ __launch_bounds__(64) void explicit_form_kernel(ExplicitForm a, int64_t item0, int64_t n) {
-  extern __shared__ double ring[];
-  // consecutive items (of one subdomain) on one XCD: workgroups are dealt
+// One workgroup per (subdomain p, group of NW consecutive column blocks of
+// 16 sorted touched DOFs), one wavefront per column block; the wavefronts
+// walk the block rows together.  Per block row the KB factor tiles the
+// update needs (forward: row block I, columns of blocks I - KB .. I - 1;
+// backward: column block I, rows of blocks I + 1 .. I + KB) are read from
+// the band once per workgroup, masked to the band, and staged in LDS (two
+// buffers: the tiles of the next row are fetched into registers while the
+// current row is computed).  Each wavefront keeps the last KB blocks of its
+// Z (then W) in registers, a shift register advanced once per row, so that
+// block K is the B operand of the product with tile K without any move:
+// in step s of a 16 x 16 x 4 product lane l (row or column l % 16, group
+// g = l / 16) supplies contraction index g + 4 s, which is register s of an
+// accumulator (rows g + 4 r).  LDS holds tile k as [s][g][i] = T[i][g + 4 s],
+// so that the 64 lanes' operands of one step are 64 consecutive doubles
+// (no bank conflicts).  Rows a wavefront does not need
+// (before its first touched DOF) are skipped by that wavefront only.
+template <typename T, int KB, int NW>
+__global__ __launch_bounds__(64 * NW) void explicit_form_kernel(ExplicitForm a, int64_t item0, int64_t n) {
+  constexpr int NT = 64 * NW;
+  constexpr int SE = (KB * 256 + NT - 1) / NT;   // staged entries per thread and row
+  __shared__ __align__(16) double stage[2][KB * 256];
+  extern __shared__ int posl[];                   // sorted position of each factor row (-1: untouched)
+  // consecutive groups (of one subdomain) on one XCD: workgroups are dealt
   // to the eight XCDs in turn
   const int64_t per = (n + 7) / 8;
   const int64_t t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= n) return;
-  const int lane = threadIdx.x, li = lane % 16, g = lane / 16;
-  const int p = uniform(a.items[2 * (item0 + t)]), cb = uniform(a.items[2 * (item0 + t) + 1]);
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, li = lane % 16, g = lane / 16;
+  const int p = uniform(a.items[2 * (item0 + t)]), grp = uniform(a.items[2 * (item0 + t) + 1]);
   const int ndof = uniform(a.subs[p].ndof), b = uniform(a.subs[p].b), Wm = uniform(a.subs[p].Wb - 1);
   const int m = uniform(a.subs[p].n_iface);
   const int64_t ioff = a.subs[p].iface_off, doff_t = a.subs[p].dof_off;
   const double* A = a.band + a.subs[p].band_off;
   const double* D = a.dinv + a.doff[p];
-  double* Zs = a.zs + t * a.zstride;
-  const int nbr = (ndof + 15) / 16, kb = (b + 15) / 16, RW = a.ring;
+  const int nbr = (ndof + 15) / 16, kb = (b + 15) / 16;
   const int mt = (m + 15) / 16;
+  const int cb = NW * grp + wave;                // this wavefront's column block
+  const bool has = cb < mt;
   const int c = 16 * cb + li;
   const int fj = c < m ? a.sfidx[ioff + c] : -1;
-  const int I0 = uniform(a.sfidx[ioff + 16 * cb]) / 16;
+  const int Iw = has ? uniform(a.sfidx[ioff + 16 * cb]) / 16 : nbr;  // first row block of this wavefront
+  const int Ig = uniform(a.sfidx[ioff + 16 * NW * grp]) / 16;         // of the group (sorted: the first)
+  double* Zs = a.dinv + a.zs_off + (t * NW + wave) * a.zstride;
   T* F = reinterpret_cast<T*>(a.F) + a.foff[p];
 
-  double rg[PD][4];
-  d4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int r = tid; r < ndof; r += NT) posl[r] = a.pos[doff_t + r];
+  double zr[KB][4];
+#pragma unroll
+  for (int k = 0; k < KB; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) zr[k][s] = 0.0;
+  // staging: entry e = tid + NT q of a row's KB tiles is entry (i, c) =
+  // (e % 16, (e / 16) % 4 + 4 ((e / 64) % 4)) of tile e / 256 (forward: row
+  // i, column c; backward: row c, column i), stored at LDS position e, so
+  // that in step s lane l reads position 64 s + l: 64 consecutive doubles
+  double sv[SE];
+  double dv[4];
 
-  // ---- forward: elements (I, K), K in [max(I0, I - kb), I) factor tiles,
-  // K == I the diagonal inverse; I from I0 to nbr - 1
+  // ---- forward
   {
-    int lI = I0, lK = I0;  // fetch cursor
-    int cI = I0, cK = I0;  // consume cursor
-    auto advance = [&](int& I, int& K) {
-      if (K < I) {
-        ++K;
-      } else {
-        ++I;
-        K = I - kb > I0 ? I - kb : I0;
+    // tile k of row I: rows 16 I + i, columns 16 (I - KB + k) + c
+    auto fetch = [&](int I) {
+#pragma unroll
+      for (int q = 0; q < SE; ++q) {
+        const int e = tid + NT * q, k = e >> 8, i = e & 15, c = ((e >> 4) & 3) + 4 * ((e >> 6) & 3);
+        const int R = 16 * I + i, col = 16 * (I - KB + k) + c;
+        const int Rc = R < ndof ? R : ndof - 1, cc = col > Rc - b ? col : Rc - b;
+        const double v = A[Rc * Wm + cc + b];
+        sv[q] = (e < KB * 256 && R < ndof && col >= R - b && col >= 0) ? v : 0.0;
       }
     };
-    auto fetch = [&](int I, int K, double* d) {
-      if (I >= nbr) {
+    auto put = [&](int buf) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) d[s] = 0.0;
-      } else if (K < I) {
-        const int R = 16 * I + li;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int col = 16 * K + 4 * g + s, cc = col > R - b ? col : R - b;
-          d[s] = A[R * Wm + cc + b];
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) d[s] = D[(int64_t)I * 512 + li * 16 + 4 * g + s];
+      for (int q = 0; q < SE; ++q) {
+        const int e = tid + NT * q;
+        if (e < KB * 256) stage[buf][e] = sv[q];
       }
     };
+    auto fetch_d = [&](int I) {
 #pragma unroll
-    for (int u = 0; u < PD; ++u) {
-      fetch(lI, lK, rg[u]);
-      advance(lI, lK);
-    }
-    bool end = false;
-    while (!end) {
+      for (int s = 0; s < 4; ++s) dv[s] = D[(int64_t)(I < nbr ? I : 0) * 512 + li * 16 + 4 * g + s];
+    };
+    fetch(Ig);
+    fetch_d(Ig);
+    // rows in rounds of KB: block K lives in ring slot K mod KB, a
+    // compile-time index within the round
+    for (int I0r = Ig / KB * KB; I0r < nbr; I0r += KB) {
 #pragma unroll
-      for (int u = 0; u < PD; ++u) {
-        if (!end) {
-          if (cK < cI) {
-            const int R = 16 * cI + li;
-            const double* Zk = ring + (cK % RW) * 256;
+      for (int u = 0; u < KB; ++u) {
+        const int I = I0r + u;
+        if (I >= Ig && I < nbr) {
+          const int buf = I & 1;
+          put(buf);
+          if (I + 1 < nbr) fetch(I + 1);
+          __syncthreads();
+          if (I >= Iw) {
+            d4 acc = {0, 0, 0, 0};
+            const int tb = buf * KB * 256 + lane;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-              const int col = 16 * cK + 4 * g + s;
-              const double va = (R < ndof && col >= R - b) ? -rg[u][s] : 0.0;
-              if (u & 1)
-                acc1 = mfma4(va, Zk[(4 * g + s) * 16 + li], acc1);
-              else
-                acc0 = mfma4(va, Zk[(4 * g + s) * 16 + li], acc0);
+            for (int k = 0; k < KB; ++k) {
+              const int K = I - KB + k;
+              if (K >= Iw && K >= I - kb) {
+                // read once the products of tile k - 1 are issued
+                const double* tk = &stage[0][after(tb + k * 256, acc[0])];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = mfma4(-tk[64 * s], zr[(u + k) % KB][s], acc);
+              }
             }
-          } else {
-            d4 tv = acc0 + acc1;
+            d4 tv = acc;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) tv[r] += (16 * cI + g + 4 * r == fj) ? 1.0 : 0.0;
+            for (int r = 0; r < 4; ++r) tv[r] += (16 * I + g + 4 * r == fj) ? 1.0 : 0.0;
             d4 z = {0, 0, 0, 0};
 #pragma unroll
-            for (int s = 0; s < 4; ++s) z = mfma4(rg[u][s], tv[s], z);
-            double* Zi = ring + (cI % RW) * 256;
-            double* Zg = Zs + (int64_t)(cI - I0) * 256;
+            for (int s = 0; s < 4; ++s) z = mfma4(dv[s], tv[s], z);
+            fetch_d(I + 1);
+            double* Zg = Zs + (int64_t)(I - Iw) * 256;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              Zi[(g + 4 * r) * 16 + li] = z[r];
-              Zg[r * 64 + lane] = z[r];
-            }
-            acc0 = d4{0, 0, 0, 0};
-            acc1 = d4{0, 0, 0, 0};
+            for (int r = 0; r < 4; ++r) Zg[r * 64 + lane] = z[r];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) zr[u][s] = z[s];
+          } else if (I + 1 == Iw) {
+            fetch_d(I + 1);
           }
-          advance(cI, cK);
-          fetch(lI, lK, rg[u]);
-          advance(lI, lK);
-          end = cI >= nbr;
         }
       }
     }
   }
+  __syncthreads();
 
-  // ---- backward: per row I from nbr - 1 down to I0: ph 0 the block Z_I,
-  // ph 1 factor tiles K in (I, min(nbr - 1, I + kb)], ph 2 the transposed
-  // diagonal inverse
+  // ---- backward (the ring holds W_{I+1} .. W_{I+KB})
   {
-    auto khi = [&](int I) { return I + kb < nbr - 1 ? I + kb : nbr - 1; };
-    auto advance = [&](int& I, int& K, int& ph) {
-      if (ph == 0) {
-        if (I + 1 <= khi(I)) {
-          ph = 1;
-          K = I + 1;
-        } else {
-          ph = 2;
-        }
-      } else if (ph == 1) {
-        if (K < khi(I))
-          ++K;
-        else
-          ph = 2;
-      } else {
-        --I;
-        ph = 0;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) zr[k][s] = 0.0;
+    double zv[4];
+    // tile k of row I: rows 16 (I + 1 + k) + c, columns 16 I + i
+    auto fetch = [&](int I) {
+#pragma unroll
+      for (int q = 0; q < SE; ++q) {
+        const int e = tid + NT * q, k = e >> 8, i = e & 15, c = ((e >> 4) & 3) + 4 * ((e >> 6) & 3);
+        const int R = 16 * (I + 1 + k) + c, col = 16 * I + i;
+        const int Rc = R < ndof ? R : ndof - 1, cc = col > Rc - b ? col : Rc - b;
+        const double v = A[Rc * Wm + cc + b];
+        sv[q] = (e < KB * 256 && R < ndof && col >= R - b) ? v : 0.0;
       }
     };
-    auto fetch = [&](int I, int K, int ph, double* d) {
-      if (I < I0) {
+    auto put = [&](int buf) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) d[s] = 0.0;
-      } else if (ph == 0) {
-        const double* Zg = Zs + (int64_t)(I - I0) * 256;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) d[s] = Zg[s * 64 + lane];
-      } else if (ph == 1) {
-        const int col = 16 * I + li;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int R = 16 * K + 4 * g + s, cc = col > R - b ? col : R - b;
-          d[s] = A[R * Wm + cc + b];
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) d[s] = D[(int64_t)I * 512 + 256 + li * 16 + 4 * g + s];
+      for (int q = 0; q < SE; ++q) {
+        const int e = tid + NT * q;
+        if (e < KB * 256) stage[buf][e] = sv[q];
       }
     };
-    int lI = nbr - 1, lK = 0, lph = 0;
-    int cI = nbr - 1, cK = 0, cph = 0;
+    // the diagonal inverse and Z_I
+    auto fetch_d = [&](int I) {
+      const int Ic = I >= 0 ? I : 0, Iz = I >= Iw ? I : Iw;
 #pragma unroll
-    for (int u = 0; u < PD; ++u) {
-      fetch(lI, lK, lph, rg[u]);
-      advance(lI, lK, lph);
-    }
-    bool end = false;
-    while (!end) {
+      for (int s = 0; s < 4; ++s) dv[s] = D[(int64_t)Ic * 512 + 256 + li * 16 + 4 * g + s];
 #pragma unroll
-      for (int u = 0; u < PD; ++u) {
-        if (!end) {
-          if (cph == 0) {
-            acc0 = d4{rg[u][0], rg[u][1], rg[u][2], rg[u][3]};
-            acc1 = d4{0, 0, 0, 0};
-          } else if (cph == 1) {
-            const int col = 16 * cI + li;
-            const double* Wk = ring + (cK % RW) * 256;
+      for (int s = 0; s < 4; ++s) zv[s] = has ? Zs[(int64_t)(Iz - Iw) * 256 + s * 64 + lane] : 0.0;
+    };
+    fetch(nbr - 1);
+    fetch_d(nbr - 1);
+    // rows in rounds of KB from the top: block K in slot K mod KB
+    for (int Itr = (nbr - 1) / KB * KB + KB - 1; Itr >= Ig; Itr -= KB) {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-              const int R = 16 * cK + 4 * g + s;
-              const double va = (R < ndof && col >= R - b) ? -rg[u][s] : 0.0;
-              if (u & 1)
-                acc1 = mfma4(va, Wk[(4 * g + s) * 16 + li], acc1);
-              else
-                acc0 = mfma4(va, Wk[(4 * g + s) * 16 + li], acc0);
-            }
-          } else {
-            const d4 tv = acc0 + acc1;
-            d4 w = {0, 0, 0, 0};
+      for (int u = 0; u < KB; ++u) {
+        const int I = Itr - u;
+        if (I >= Ig && I < nbr) {
+          const int buf = I & 1;
+          put(buf);
+          if (I - 1 >= Ig) fetch(I - 1);
+          __syncthreads();
+          if (I >= Iw) {
+            d4 acc = {zv[0], zv[1], zv[2], zv[3]};
+            const int tb = buf * KB * 256 + lane;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) w = mfma4(rg[u][s], tv[s], w);
-            double* Wi = ring + (cI % RW) * 256;
+            for (int k = 0; k < KB; ++k) {
+              const int K = I + 1 + k;
+              if (K < nbr && k < kb) {
+                const double* tk = &stage[0][after(tb + k * 256, acc[0])];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              Wi[(g + 4 * r) * 16 + li] = w[r];
-              const int R = 16 * cI + g + 4 * r;
-              if (R < ndof) {
-                const int q = a.pos[doff_t + R];
-                if (q >= 0 && (q >> 4) >= cb)
-                  F[tile_index(q >> 4, cb, mt) * 256 + (q & 15) * 16 + li] = (T)w[r];
+                for (int s = 0; s < 4; ++s) acc = mfma4(-tk[64 * s], zr[(KB + k - u) % KB][s], acc);
               }
             }
+            const d4 tv = acc;
+            d4 w = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) w = mfma4(dv[s], tv[s], w);
+            fetch_d(I - 1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int R = 16 * I + g + 4 * r, q = R < ndof ? posl[R] : -1;
+              if (q >= 0 && (q >> 4) >= cb)
+                F[tile_index(q >> 4, cb, mt) * 256 + (q & 15) * 16 + li] = (T)w[r];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) zr[(KB - 1 - u) % KB][s] = w[s];
           }
-          advance(cI, cK, cph);
-          fetch(lI, lK, lph, rg[u]);
-          advance(lI, lK, lph);
-          end = cI < I0;
         }
       }
     }
@@ -428,12 +428,28 @@ void launch_diag_inverse(const SubDev* subs, int64_t count, const int32_t* list,
     diag_inverse_kernel<<<dim3((unsigned)count), dim3(256), 0, st>>>(subs, count, list, band, doff, dinv);
 }
 
+// tiles per staged row: the smallest instantiated count >= ceil(bmax / 16)
+int explicit_form_kb(int bmax) {
+  const int kb = (bmax + 15) / 16;
+  for (int k : {4, 8, 12, 18, 21, 26})
+    if (kb <= k) return k;
+  return 0;
+}
+
 template <typename T>
 void launch_explicit_form(const ExplicitForm& a, int64_t item0, int64_t n, hipStream_t st) {
   if (n <= 0) return;
   const int64_t per = (n + 7) / 8;
-  const size_t lds = (size_t)a.ring * 256 * sizeof(double);
-  explicit_form_kernel<T, 8><<<dim3((unsigned)(8 * per)), dim3(64), lds, st>>>(a, item0, n);
+  const dim3 grid((unsigned)(8 * per)), block(64 * kExplicitWaves);
+  const size_t lds = (size_t)a.max_ndof * sizeof(int);
+  switch (a.kb) {
+    case 4: explicit_form_kernel<T, 4, kExplicitWaves><<<grid, block, lds, st>>>(a, item0, n); break;
+    case 8: explicit_form_kernel<T, 8, kExplicitWaves><<<grid, block, lds, st>>>(a, item0, n); break;
+    case 12: explicit_form_kernel<T, 12, kExplicitWaves><<<grid, block, lds, st>>>(a, item0, n); break;
+    case 18: explicit_form_kernel<T, 18, kExplicitWaves><<<grid, block, lds, st>>>(a, item0, n); break;
+    case 21: explicit_form_kernel<T, 21, kExplicitWaves><<<grid, block, lds, st>>>(a, item0, n); break;
+    default: explicit_form_kernel<T, 26, kExplicitWaves><<<grid, block, lds, st>>>(a, item0, n); break;
+  }
 }
 
 template <typename T>

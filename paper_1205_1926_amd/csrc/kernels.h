@@ -209,17 +209,23 @@ void launch_coarse_pack(int64_t l, const double* Ginv, const int32_t* cidx, doub
 struct ExplicitForm {
   const SubDev* subs;
   const double* band;         // FP64 band factors
-  const double* dinv;         // diagonal-block inverses (512 entries per 16-row block)
+  double* dinv;               // diagonal-block inverses (512 entries per 16-row block),
+                              // followed by the scratch (at zs_off)
   const int64_t* doff;        // their offset per subdomain
   const int32_t* sfidx;
   const int32_t* pos;
   const int64_t* foff;
-  const int32_t* items;       // (subdomain, column block) pairs
-  double* zs;                 // scratch: zstride entries per item of a launch
+  const int32_t* items;       // (subdomain, group of kExplicitWaves column blocks) pairs
+  int64_t zs_off;             // scratch: zstride entries per wavefront of a launch
   int64_t zstride;
-  int32_t ring;               // LDS blocks per wavefront (>= ceil(bmax / 16) + 1)
+  int32_t kb;                 // staged tiles per row, explicit_form_kb(bmax)
+  int32_t max_ndof;           // largest subdomain DOF count (LDS of the position table)
   void* F;                    // Ft storage (double or float)
 };
+// column blocks (wavefronts) per forming workgroup
+constexpr int kExplicitWaves = 8;
+// tiles per staged row of the forming kernel for half bandwidth bmax (0: too wide)
+int explicit_form_kb(int bmax);
 struct ExplicitApply {
   const SubDev* subs;
   const int32_t* order;       // workgroup -> subdomain, or nullptr
@@ -240,7 +246,7 @@ struct ExplicitApply {
 int64_t explicit_tiles(int64_t m);
 void launch_diag_inverse(const SubDev* subs, int64_t count, const int32_t* list, const double* band,
                          const int64_t* doff, double* dinv, hipStream_t st);
-// items [item0, item0 + n) of a.items; n <= the scratch's item capacity
+// groups [item0, item0 + n) of a.items; n <= the scratch's group capacity
 template <typename T>
 void launch_explicit_form(const ExplicitForm& a, int64_t item0, int64_t n, hipStream_t st);
 template <typename T>
