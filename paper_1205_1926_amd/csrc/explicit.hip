@@ -201,14 +201,23 @@ __global__ __launch_bounds__(64 * NW) void explicit_form_kernel(ExplicitForm a, 
           if (I >= Iw) {
             d4 acc = {0, 0, 0, 0};
             const int tb = buf * KB * 256 + lane;
+            // tiles k >= k0 take part; each tile's operands are read while
+            // the products of the tile before it run
+            const int k0 = KB - min(kb, I - Iw);
+            double ac[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) ac[s] = stage[0][tb + min(k0, KB - 1) * 256 + 64 * s];
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
-              const int K = I - KB + k;
-              if (K >= Iw && K >= I - kb) {
-                // read once the products of tile k - 1 are issued
-                const double* tk = &stage[0][after(tb + k * 256, acc[0])];
+              if (k >= k0) {
+                double an[4];
+                const int nx = after(tb + min(k + 1, KB - 1) * 256, acc[0]);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) acc = mfma4(-tk[64 * s], zr[(u + k) % KB][s], acc);
+                for (int s = 0; s < 4; ++s) an[s] = stage[0][nx + 64 * s];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = mfma4(-ac[s], zr[(u + k) % KB][s], acc);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) ac[s] = an[s];
               }
             }
             d4 tv = acc;
@@ -280,13 +289,22 @@ __global__ __launch_bounds__(64 * NW) void explicit_form_kernel(ExplicitForm a, 
           if (I >= Iw) {
             d4 acc = {zv[0], zv[1], zv[2], zv[3]};
             const int tb = buf * KB * 256 + lane;
+            // tiles k < k1 take part
+            const int k1 = min(kb, nbr - 1 - I);
+            double ac[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) ac[s] = stage[0][tb + 64 * s];
 #pragma unroll
             for (int k = 0; k < KB; ++k) {
-              const int K = I + 1 + k;
-              if (K < nbr && k < kb) {
-                const double* tk = &stage[0][after(tb + k * 256, acc[0])];
+              if (k < k1) {
+                double an[4];
+                const int nx = after(tb + min(k + 1, KB - 1) * 256, acc[0]);
 #pragma unroll
-                for (int s = 0; s < 4; ++s) acc = mfma4(-tk[64 * s], zr[(KB + k - u) % KB][s], acc);
+                for (int s = 0; s < 4; ++s) an[s] = stage[0][nx + 64 * s];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) acc = mfma4(-ac[s], zr[(KB + k - u) % KB][s], acc);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) ac[s] = an[s];
               }
             }
             const d4 tv = acc;
