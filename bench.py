@@ -282,6 +282,7 @@ def counter_probe(g, reps: int) -> int:
     print(json.dumps({"probe": "counters", "fapply_reps": reps, "tile": sz["tile"], "schedule": sz["schedule"],
                       "threads": sz["threads"], "skyline_bytes_per_apply": 2 * sz["skyline_entries"] * fb,
                       "stored_panel_bytes_per_apply": 2 * sz["factor_entries"] * fb,
+                      "explicit_bytes_per_apply": sz["explicit_bytes"],
                       "copy_bytes_each_way": src.numel() * 8}), flush=True)
     g.close()
     return 0
@@ -467,6 +468,8 @@ def main() -> int:
     ap.add_argument("--detail", default=None, help="write per-iteration reports of every leg to this JSON file")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="with --counter-probe: the factor precision")
+    ap.add_argument("--fapply-format", default="factors", choices=["factors", "explicit"],
+                    help="with --counter-probe: the F-apply format")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for hardware-counter runs: factorize once, run --fapply-reps F-applies and one "
                          "device copy of 1 GiB (the scale reference of the byte counters), print sizes")
@@ -499,7 +502,8 @@ def main() -> int:
     w = W.config(args.config, load_seed=0)
     if args.counter_probe:
         from paper_1205_1926_amd import GpuSolver
-        g = GpuSolver(w, precision=args.precision or "fp64", tile=args.tile, use_graph=1)
+        g = GpuSolver(w, precision=args.precision or "fp64", tile=args.tile, use_graph=1,
+                      fapply_format=args.fapply_format)
         return counter_probe(g, args.fapply_reps)
 
     # child processes start before anything touches the GPU

@@ -186,21 +186,26 @@ def test_explicit_degenerate_decompositions(S, n, dev):
     P.close()
 
 
-def test_explicit_newton_plastic_matches_oracle(dev):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_explicit_newton_plastic_matches_oracle(precision, dev):
     """Load steps with plastic subdomains refactorized (and their explicit
-    blocks formed again) and elastic ones kept, graph replay on: the oracle's
-    displacements and hardening."""
+    blocks formed again), elastic ones kept and elastic-again ones copied
+    back (their blocks formed from the copied factor), graph replay on: the
+    oracle's displacements and hardening."""
     from paper_1205_1926_amd import GpuSolver
-    w = W.small_cube(S=(2, 2, 2), n=(3, 3, 3), amp=700.0, shear=150.0, steps=3)
+    w = W.small_cube(S=(3, 2, 2), n=(3, 3, 3), amp=650.0, shear=150.0, steps=3)
     o = OracleSolver(w, "tfeti")
-    g = GpuSolver(w, use_graph=1, fapply_format="explicit")
+    g = GpuSolver(w, use_graph=1, fapply_format="explicit", precision=precision)
+    hist = []
     for k in range(w.steps):
         o.load_step()
-        g.load_step()
+        hist += g.load_step()
         ug = N(g.state()["u"])
         assert rel(ug[o.untorn], o.u[o.untorn]) <= 1e-6, k
     st = g.state()
     assert np.abs(N(st["kappa"]) - o.kappa.ravel()).max() <= 1e-6 * np.abs(o.kappa).max()
+    assert any(0 < r["refactored"] < 12 for r in hist)
+    assert sum(r["restored"] for r in hist) > 0
     g.close()
 
 
