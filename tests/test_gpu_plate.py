@@ -67,8 +67,11 @@ def plastic_elements(g):
 
 @pytest.mark.parametrize("opts", [dict(precision="fp64", preconditioner=1),
                                   dict(precision="fp32", preconditioner=2, use_graph=1),
-                                  dict(precision="fp64", preconditioner=2, use_graph=1)],
-                         ids=["fp64_lumped", "fp32_dirichlet_graph", "fp64_dirichlet_graph"])
+                                  dict(precision="fp64", preconditioner=2, use_graph=1),
+                                  dict(precision="fp64", preconditioner=1, use_graph=1, fapply_format="explicit"),
+                                  dict(precision="fp32", preconditioner=1, use_graph=1, fapply_format="explicit")],
+                         ids=["fp64_lumped", "fp32_dirichlet_graph", "fp64_dirichlet_graph", "fp64_explicit_graph",
+                              "fp32_explicit_graph"])
 def test_plate_discretization_a_matches_oracle(opts, oracle_a, gold, dev):
     from paper_1205_1926_amd import GpuSolver
     w, o, ho = oracle_a
@@ -84,15 +87,17 @@ def test_plate_discretization_a_matches_oracle(opts, oracle_a, gold, dev):
     g.close()
 
 
-def test_plate_discretization_b_matches_stored_oracle(gold, dev):
-    """Eight load steps; then the paper's observation that the two time
-    discretizations reach almost the same plastic zone at t = 1/4 (the
+@pytest.mark.parametrize("fmt", ["factors", "explicit"])
+def test_plate_discretization_b_matches_stored_oracle(fmt, gold, dev):
+    """Eight load steps (the F-applies through the factors, or through the
+    explicit local operators); then the paper's observation that the two
+    time discretizations reach almost the same plastic zone at t = 1/4 (the
     plastic element counts within 0.5%)."""
     from paper_1205_1926_amd import GpuSolver
     w = W.plate_notch(1, steps=8)
     m = Mesh(w)
     untorn = m.untorn_index()
-    g = GpuSolver(w, precision="fp64", preconditioner=2, use_graph=1)
+    g = GpuSolver(w, precision="fp64", preconditioner=2, use_graph=1, fapply_format=fmt)
     stride = gold["stride"]
     for k, ref in enumerate(gold["b"]):
         h = g.load_step()
