@@ -24,10 +24,12 @@
 //   forward  Z_I = D_I (S_I - sum_K L_IK Z_K),        K in [I - kb, I)
 //   backward W_I = D_I^T (Z_I - sum_K L_KI^T W_K),     K in (I, I + kb]
 // with D_I the inverse of the diagonal 16 x 16 block (diag_inverse_kernel)
-// and kb = ceil(b / 16).  The last kb + 1 blocks of Z (then W) stay in LDS
-// for the updates; Z goes to a scratch buffer for the backward sweep.  The
-// rows of W at touched DOFs of sorted position >= the first of C are the
-// lower-triangle entries of columns C of Ft_p.
+// and kb = ceil(b / 16).  The factor tiles of a block row are staged in LDS
+// once for the workgroup's wavefronts, the last kb blocks of each
+// wavefront's Z (then W) stay in its registers, and Z goes to a scratch
+// buffer for the backward sweep.  The rows of W at touched DOFs of sorted
+// position >= the first of C are the lower-triangle entries of columns C of
+// Ft_p.
 //
 // Applying (once per F-apply, HBM bound): one workgroup per subdomain;
 // each wavefront walks whole tile columns J and uses every off-diagonal
@@ -111,8 +113,9 @@ __global__ __launch_bounds__(256) void diag_inverse_kernel(const SubDev* __restr
 // the band once per workgroup, masked to the band, and staged in LDS (two
 // buffers: the tiles of the next row are fetched into registers while the
 // current row is computed).  Each wavefront keeps the last KB blocks of its
-// Z (then W) in registers, a shift register advanced once per row, so that
-// block K is the B operand of the product with tile K without any move:
+// Z (then W) in registers, block K in slot K mod KB (a compile-time index:
+// the row loop is unrolled KB rows at a time), so that block K is the B
+// operand of the product with tile K without any move:
 // in step s of a 16 x 16 x 4 product lane l (row or column l % 16, group
 // g = l / 16) supplies contraction index g + 4 s, which is register s of an
 // accumulator (rows g + 4 r).  LDS holds tile k as [s][g][i] = T[i][g + 4 s],
