@@ -339,7 +339,7 @@ __global__ __launch_bounds__(64 * NW) void explicit_apply_kernel(ExplicitApply a
   if (a.done && *a.done) return;
   extern __shared__ double sh[];
   constexpr int CH = (int)sizeof(T) * 256 / 16 / 64;  // 16-byte chunks per lane per tile
-  constexpr int U = 16 / CH;                          // tiles in flight per lane
+  constexpr int U = 8;                                // tiles in flight per lane
   typedef typename std::conditional<sizeof(T) == 8, double2, float4>::type VT;
   const int p = a.order ? a.order[blockIdx.x] : blockIdx.x;
   const int m = a.subs[p].n_iface;
@@ -382,35 +382,46 @@ __global__ __launch_bounds__(64 * NW) void explicit_apply_kernel(ExplicitApply a
 #pragma unroll
         for (int h = 0; h < CH; ++h) v[u][h] = reinterpret_cast<const VT*>(col + (int64_t)(I - J) * 256)[h];
       }
+      // the batch's LDS traffic in three independent groups (x reads, y
+      // reads, y writes; distinct rows), not one read-modify-write chain
+      // per tile: rows past the last tile use the last row and add zero
+      double xi[U], rp[U], yo[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xi[u] = x[16 * (I0 + u < mt ? I0 + u : mt - 1) + rr];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int I = I0 + u;
-        if (I < mt) {
-          double e[4];
+        double e[4];
 #pragma unroll
-          for (int h = 0; h < CH; ++h) {
-            if constexpr (sizeof(T) == 8) {
-              e[2 * h] = v[u][h].x;
-              e[2 * h + 1] = v[u][h].y;
-            } else {
-              e[0] = v[u][h].x;
-              e[1] = v[u][h].y;
-              e[2] = v[u][h].z;
-              e[3] = v[u][h].w;
-            }
-          }
-          double rp = e[0] * xj[0];
-#pragma unroll
-          for (int c = 1; c < 4; ++c) rp = fma(e[c], xj[c], rp);
-          rp += __shfl_xor(rp, 1);
-          rp += __shfl_xor(rp, 2);
-          if (cq == 0) yw[16 * I + rr] += rp;
-          if (I > J) {
-            const double xi = x[16 * I + rr];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) cp[c] = fma(e[c], xi, cp[c]);
+        for (int h = 0; h < CH; ++h) {
+          if constexpr (sizeof(T) == 8) {
+            e[2 * h] = v[u][h].x;
+            e[2 * h + 1] = v[u][h].y;
+          } else {
+            e[0] = v[u][h].x;
+            e[1] = v[u][h].y;
+            e[2] = v[u][h].z;
+            e[3] = v[u][h].w;
           }
         }
+        double r = e[0] * xj[0];
+#pragma unroll
+        for (int c = 1; c < 4; ++c) r = fma(e[c], xj[c], r);
+        r += __shfl_xor(r, 1);
+        r += __shfl_xor(r, 2);
+        rp[u] = I < mt ? r : 0.0;
+        // columns: the diagonal tile (I == J) contributes its rows only
+        const double xu = (I > J && I < mt) ? xi[u] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cp[c] = fma(e[c], xu, cp[c]);
+      }
+      if (cq == 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (I0 + u < mt) yo[u] = yw[16 * (I0 + u) + rr];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (I0 + u < mt) yw[16 * (I0 + u) + rr] = yo[u] + rp[u];
       }
     }
 #pragma unroll
