@@ -486,10 +486,31 @@ void launch_explicit_form(const ExplicitForm& a, int64_t item0, int64_t n, hipSt
 
 template <typename T>
 void launch_explicit_apply(const ExplicitApply& a, int max_iface, hipStream_t st) {
-  constexpr int NW = 2;
+  // four wavefronts per subdomain when every subdomain's workgroup is then
+  // still resident at once (two per compute unit, by registers, if the LDS
+  // of x and four copies of y allows), else two: the launch ends with the
+  // largest operators, which stream faster with more loads in flight
+  static int cus = 0, lds_cu = 0;
+  if (cus == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 1;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds_cu <= 0)
+      lds_cu = 65536;
+  }
   const int mp = (max_iface + 15) / 16 * 16;
-  const size_t lds = (size_t)(NW + 1) * mp * sizeof(double);
-  explicit_apply_kernel<T, NW><<<dim3((unsigned)a.nsub), dim3(64 * NW), lds, st>>>(a);
+  const size_t lds4 = (size_t)5 * mp * sizeof(double);
+  const int64_t per_cu = std::min<int64_t>(2, (int64_t)lds_cu / (int64_t)lds4);
+  if (a.nsub <= per_cu * cus) {
+    if (lds4 > 65536)
+      (void)hipFuncSetAttribute((const void*)explicit_apply_kernel<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds4);
+    explicit_apply_kernel<T, 4><<<dim3((unsigned)a.nsub), dim3(256), lds4, st>>>(a);
+  } else {
+    const size_t lds2 = (size_t)3 * mp * sizeof(double);
+    explicit_apply_kernel<T, 2><<<dim3((unsigned)a.nsub), dim3(128), lds2, st>>>(a);
+  }
 }
 
 template void launch_explicit_form<double>(const ExplicitForm&, int64_t, int64_t, hipStream_t);
