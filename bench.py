@@ -74,6 +74,10 @@ LEGS = {
     # every factorization of a subdomain)
     "fp64_explicit": dict(precision="fp64", use_graph=1, warm_start=1, fapply_format="explicit"),
     "fp32_explicit": dict(precision="fp32", use_graph=1, warm_start=1, fapply_format="explicit"),
+    # in one launch: operators for the subdomains that keep their elastic
+    # factor, factor sweeps for the others
+    "fp32_hybrid": dict(precision="fp32", use_graph=1, warm_start=1, fapply_format="hybrid"),
+    "fp64_hybrid": dict(precision="fp64", use_graph=1, warm_start=1, fapply_format="hybrid"),
 }
 # the learned candidate of the fp32_learned leg (and of fp32_all with --learned)
 DEFAULT_WEIGHTS = os.path.join(ROOT, "paper_1205_1926_amd", "weights", "warmstart_cube8x8x8_uneven.safetensors")
@@ -357,7 +361,10 @@ def run_leg(name, w, args, net, detail):
     fb = 8 if opts["precision"] == "fp64" else 4
     # algorithmic bytes of one F-apply: both sweeps over the factor envelope,
     # or the stored lower triangles of the explicit operators
-    alg = sz["explicit_bytes"] if opts.get("fapply_format") == "explicit" else 2 * sz["skyline_entries"] * fb
+    # (hybrid: the operators' bytes, a lower bound, since the subdomains
+    # solved through their factors read more)
+    alg = (sz["explicit_bytes"] if opts.get("fapply_format") in ("explicit", "hybrid")
+           else 2 * sz["skyline_entries"] * fb)
     iso_kernel_s = iso_ms / max(iso_cnt, 1) / 1e3
     if k_cnt > 0:
         kernel_s, src = k_ms / k_cnt / 1e3, "timed load steps"
@@ -468,7 +475,7 @@ def main() -> int:
     ap.add_argument("--detail", default=None, help="write per-iteration reports of every leg to this JSON file")
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="with --counter-probe: the factor precision")
-    ap.add_argument("--fapply-format", default="factors", choices=["factors", "explicit"],
+    ap.add_argument("--fapply-format", default="factors", choices=["factors", "explicit", "hybrid"],
                     help="with --counter-probe: the F-apply format")
     ap.add_argument("--counter-probe", action="store_true",
                     help="for hardware-counter runs: factorize once, run --fapply-reps F-applies and one "

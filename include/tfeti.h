@@ -129,9 +129,8 @@ typedef struct {
                                    iteration; 0: keep the factor of a subdomain
                                    whose tangent is and was the elastic one      */
   int32_t fapply_format;        /* F-applies inside the PCGP loop (and
-                                   tfeti_fapply) through
-                                   TFETI_FAPPLY_FACTORS or
-                                   TFETI_FAPPLY_EXPLICIT                        */
+                                   tfeti_fapply) through TFETI_FAPPLY_FACTORS,
+                                   TFETI_FAPPLY_EXPLICIT or TFETI_FAPPLY_HYBRID */
   int32_t pad;
 } tfeti_options;
 #define TFETI_FAPPLY_FACTORS 0  /* forward and backward substitution with the
@@ -146,6 +145,12 @@ typedef struct {
                                    the F-apply's precision and applied as one
                                    symmetric product; d, lambda_Im, the FP32
                                    outer refinement and u keep the factors      */
+#define TFETI_FAPPLY_HYBRID 2   /* in one launch, the explicit local dual
+                                   operators of the subdomains that keep the
+                                   factor of their elastic tangent (formed when
+                                   that factor is, copied back with it) and
+                                   the factor sweeps of the others; without
+                                   kept factors (refactor_all) the factor path */
 
 /* ---- reports (host structs) ------------------------------------------- */
 typedef struct {

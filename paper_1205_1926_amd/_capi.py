@@ -21,6 +21,7 @@ PREC_FP64 = 0
 PREC_FP32 = 1
 FAPPLY_FACTORS = 0
 FAPPLY_EXPLICIT = 1
+FAPPLY_HYBRID = 2
 
 
 class Material(C.Structure):
@@ -191,5 +192,6 @@ def make_options(w=None, precision=None, eps_pcg=None, eps_newton=None, precondi
     o.refine_eps = refine_eps
     o.check_every = check_every
     o.refactor_all = refactor_all
-    o.fapply_format = FAPPLY_EXPLICIT if fapply_format in ("explicit", FAPPLY_EXPLICIT) else FAPPLY_FACTORS
+    o.fapply_format = {"factors": FAPPLY_FACTORS, "explicit": FAPPLY_EXPLICIT, "hybrid": FAPPLY_HYBRID}.get(
+        fapply_format, fapply_format)
     return o

@@ -90,6 +90,13 @@ struct tfeti_handle {
   int32_t *d_ex_sfidx = nullptr, *d_ex_sit = nullptr, *d_ex_pos = nullptr;
   int32_t *d_ex_items[2] = {};  // (subdomain, column block) of the copied-back and the factorized subdomains
   std::vector<int32_t> ex_items[2];
+  // TFETI_FAPPLY_HYBRID: subdomains applied through their operator (those
+  // keeping an elastic factor), the operators of the kept elastic factors
+  bool hyb = false;
+  uint8_t* d_exuse = nullptr;
+  std::vector<uint8_t> exuse;
+  std::vector<int32_t> ex_el;   // factorized subdomains whose (elastic) factor is kept
+  void* d_efx = nullptr;
   int64_t ex_slots = 0, ex_zstride = 0, ex_zs_off = 0, ex_bytes = 0;
   int ex_kb = 0;
   // state
@@ -222,7 +229,8 @@ double read_scalar(tfeti_handle* h, const double* d) {
 // ------------------------------------------------------------------ operators
 void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double lam_sign, double* out_iface,
             double* out_full, const double* alpha, const int32_t* done, bool use64 = false,
-            const double* lam2 = nullptr, double* out_iface2 = nullptr, const PcgFold& fold = PcgFold{}) {
+            const double* lam2 = nullptr, double* out_iface2 = nullptr, const PcgFold& fold = PcgFold{},
+            bool hybrid = false) {
   if (h->prec == TFETI_PREC_FP64 || use64) {
     KsolveArgs<double> a{};
     a.subs = h->d_subs;
@@ -246,6 +254,13 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.lam2 = lam2;
     a.out_iface2 = out_iface2;
     a.fold = fold;
+    if (hybrid) {
+      a.xuse = h->d_exuse;
+      a.xF = h->d_fx;
+      a.xfoff = h->d_ex_foff;
+      a.xsit = h->d_ex_sit;
+      a.x_mp = (h->max_iface + 15) / 16 * 16;
+    }
     launch_ksolve<double>(a, h->TS, h->nt, h->npad_max, h->st);
   } else {
     KsolveArgs<float> a{};
@@ -270,6 +285,13 @@ void ksolve(tfeti_handle* h, const double* in_full, const double* lam, double la
     a.lam2 = lam2;
     a.out_iface2 = out_iface2;
     a.fold = fold;
+    if (hybrid) {
+      a.xuse = h->d_exuse;
+      a.xF = h->d_fx;
+      a.xfoff = h->d_ex_foff;
+      a.xsit = h->d_ex_sit;
+      a.x_mp = (h->max_iface + 15) / 16 * 16;
+    }
     launch_ksolve<float>(a, h->TS, h->nt, h->npad_max, h->st);
   }
 }
@@ -307,7 +329,9 @@ void fapply(tfeti_handle* h, const double* lam, double* q, const double* dotv, d
             const int32_t* done, bool timed = false, bool use64 = false, bool factors = false) {
   const bool rec = timed && h->timing && 2 * h->ev_used + 1 < (int)h->ev.size();
   if (rec) (void)hipEventRecord(h->ev[2 * h->ev_used], h->st);
-  if (h->exf && !use64 && !factors)
+  if (h->hyb && !use64 && !factors)
+    ksolve(h, nullptr, lam, 1.0, h->d_iface, nullptr, nullptr, done, false, nullptr, nullptr, PcgFold{}, true);
+  else if (h->exf && !use64 && !factors)
     explicit_apply(h, lam, h->d_iface, done);
   else
     ksolve(h, nullptr, lam, 1.0, h->d_iface, nullptr, nullptr, done, use64);
@@ -457,7 +481,10 @@ void enqueue_iteration_b(tfeti_handle* h, const int32_t* done) {
 
 // The subdomain-solve kernel of one iteration's F-apply, on p = y + beta p.
 void iteration_ksolve(tfeti_handle* h, const int32_t* done) {
-  if (h->exf)
+  if (h->hyb)
+    ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done, false, nullptr, nullptr, fold_direction(h),
+           true);
+  else if (h->exf)
     explicit_apply(h, h->d_p, h->d_iface, done, fold_direction(h));
   else
     ksolve(h, nullptr, h->d_p, 1.0, h->d_iface, nullptr, nullptr, done, false, nullptr, nullptr, fold_direction(h));
@@ -1056,6 +1083,16 @@ int setup_explicit(tfeti_handle* h) {
   else
     RC(dalloc(h, (float**)&h->d_fx, nf));
   HIPCHK(hipMemset(h->d_fx, 0, (size_t)nf * esz));
+  if (h->hyb) {
+    if (!h->opt.refactor_all) {
+      if (h->prec == TFETI_PREC_FP64)
+        RC(dalloc(h, (double**)&h->d_efx, nf));
+      else
+        RC(dalloc(h, (float**)&h->d_efx, nf));
+    }
+    h->exuse.assign(M.n_sub, 0);
+    RC(upload(h, &h->d_exuse, h->exuse));
+  }
   return 0;
 }
 
@@ -1298,7 +1335,11 @@ int factorize(tfeti_handle* h) {
     HIPCHK(hipMemcpyAsync(h->d_rlist, restore.data(), restore.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                           h->st));
     pack(h, (int64_t)restore.size(), h->d_rlist, h->d_eband);
-    RC(form_explicit(h, restore, h->d_rlist, h->d_eband, 0));
+    if (h->hyb)
+      launch_copy_explicit(h->d_subs, (int64_t)restore.size(), h->d_rlist, h->d_ex_foff, h->d_efx, h->d_fx,
+                           h->prec == TFETI_PREC_FP64 ? sizeof(double) : sizeof(float), h->st);
+    else
+      RC(form_explicit(h, restore, h->d_rlist, h->d_eband, 0));
     if (h->dirichlet) {
       const int64_t ni = interior_list(h, restore.data(), (int64_t)restore.size(), h->ilist_keep[1], h->d_ilist_r);
       pack_interior(h, ni, h->d_ilist_r, h->d_eiband);
@@ -1331,7 +1372,23 @@ int factorize(tfeti_handle* h) {
     }
     // a subdomain packed again keeps its explicit operator (formed from
     // the same factor)
-    if (!fresh.empty()) RC(form_explicit(h, fresh, h->d_flist, h->d_band, 1));
+    // (the hybrid format forms the operators of the factors that are kept,
+    // the elastic ones, only)
+    if (!fresh.empty()) {
+      if (h->hyb) {
+        std::vector<int32_t>& el = h->ex_el;
+        el.clear();
+        for (int32_t p : fresh)
+          if (!h->opt.refactor_all && !h->subpl[p]) el.push_back(p);
+        if (!el.empty()) {
+          HIPCHK(hipMemcpyAsync(h->d_alist, el.data(), el.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                h->st));
+          RC(form_explicit(h, el, h->d_alist, h->d_band, 1));
+        }
+      } else {
+        RC(form_explicit(h, fresh, h->d_flist, h->d_band, 1));
+      }
+    }
     HIPCHK(hipMemcpyAsync(h->d_flist, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->st));
     const int64_t cnt = (int64_t)list.size();
     pack(h, cnt, h->d_flist);
@@ -1354,6 +1411,11 @@ int factorize(tfeti_handle* h) {
     }
     for (int32_t p : fresh) h->band_factored[p] = 1;
     for (int32_t p : list) h->fact_elastic[p] = h->opt.refactor_all ? 0 : (h->subpl[p] ? 0 : 1);
+  }
+  if (h->hyb) {
+    // operators for the kept elastic factors, factor sweeps for the others
+    for (int64_t p = 0; p < M.n_sub; ++p) h->exuse[p] = h->fact_elastic[p];
+    HIPCHK(hipMemcpyAsync(h->d_exuse, h->exuse.data(), M.n_sub, hipMemcpyHostToDevice, h->st));
   }
   h->factored = true;
   if (h->tune_pending) {
@@ -1380,6 +1442,7 @@ int factorize(tfeti_handle* h) {
       HIPCHK(hipMemcpyAsync(h->d_ekit, h->d_kit_val, (size_t)M.kit.goff.back() * vb, hipMemcpyDeviceToDevice, h->st));
       HIPCHK(hipMemcpyAsync(h->d_ekti, h->d_kti_val, (size_t)M.kti.goff.back() * vb, hipMemcpyDeviceToDevice, h->st));
     }
+    if (h->hyb) HIPCHK(hipMemcpyAsync(h->d_efx, h->d_fx, (size_t)h->ex_bytes, hipMemcpyDeviceToDevice, h->st));
     h->e_valid = true;
   }
   return 0;
@@ -1424,9 +1487,12 @@ int tfeti_setup(const tfeti_problem* prob, const tfeti_options* opt, void* strea
   if (h->opt.precision != TFETI_PREC_FP64 && h->opt.precision != TFETI_PREC_FP32)
     return fail(h, TFETI_E_INVALID, "precision must be TFETI_PREC_FP64 or TFETI_PREC_FP32");
   h->prec = h->opt.precision;
-  if (h->opt.fapply_format != TFETI_FAPPLY_FACTORS && h->opt.fapply_format != TFETI_FAPPLY_EXPLICIT)
-    return fail(h, TFETI_E_INVALID, "fapply_format must be TFETI_FAPPLY_FACTORS or TFETI_FAPPLY_EXPLICIT");
-  h->exf = h->opt.fapply_format == TFETI_FAPPLY_EXPLICIT;
+  if (h->opt.fapply_format != TFETI_FAPPLY_FACTORS && h->opt.fapply_format != TFETI_FAPPLY_EXPLICIT &&
+      h->opt.fapply_format != TFETI_FAPPLY_HYBRID)
+    return fail(h, TFETI_E_INVALID,
+                "fapply_format must be TFETI_FAPPLY_FACTORS, TFETI_FAPPLY_EXPLICIT or TFETI_FAPPLY_HYBRID");
+  h->exf = h->opt.fapply_format != TFETI_FAPPLY_FACTORS;
+  h->hyb = h->opt.fapply_format == TFETI_FAPPLY_HYBRID;
   int TS = h->opt.tile;
   h->tune_pending = TS == 0;
   if (TS == 0) TS = 32;

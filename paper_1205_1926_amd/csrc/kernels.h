@@ -144,6 +144,14 @@ struct KsolveArgs {
   double* out_iface2;         // its z at the touched DOFs (with lam2)
   int32_t vec_stride;         // LDS entries per right-hand side; set by the launcher
   PcgFold fold;               // fold.S: lam is p, taken as fma(beta, p, fold.y)
+  // explicit local operators applied instead of the solve to the subdomains
+  // with xuse[p] != 0 (nullptr: none): their storage (type T), offsets and
+  // sorted touched DOFs; x_mp: the largest 16 ceil(m_p / 16)
+  const uint8_t* xuse;
+  const void* xF;
+  const int64_t* xfoff;
+  const int32_t* xsit;
+  int32_t x_mp;
 };
 template <typename T>
 void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hipStream_t st);
@@ -242,6 +250,9 @@ struct ExplicitApply {
   const int32_t* done;
   PcgFold fold;               // as in KsolveArgs
 };
+// copy the operators of the listed subdomains from src to dst
+void launch_copy_explicit(const SubDev* subs, int64_t count, const int32_t* list, const int64_t* foff,
+                          const void* src, void* dst, size_t elem, hipStream_t st);
 // tiles of the lower triangle of an m x m operator
 int64_t explicit_tiles(int64_t m);
 void launch_diag_inverse(const SubDev* subs, int64_t count, const int32_t* list, const double* band,

@@ -31,7 +31,7 @@
 // 64-row tiles of large subdomains take 8), a lane's last chunks of a block
 // row in one batch as well except in the FP64 narrow-tile and two-right-hand-
 // side kernels.
-#include "kernels.h"
+#include "explicit_apply.h"
 
 namespace tfeti {
 
@@ -77,8 +77,8 @@ __device__ __forceinline__ auto vdot(const VT& a, const VT& b) -> decltype(a[0] 
 
 }  // namespace
 
-template <typename T, int TS, int NT, int NR>
-__global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
+template <typename T, int TS, int NT, int NR, bool X = false>
+__global__ __launch_bounds__(NT, (X && TS <= 32) ? 4 : 1) void ksolve_kernel(KsolveArgs<T> A) {
   using VT = typename Vec<T>::type;
   constexpr int V = Vec<T>::V;
   constexpr int RPT = NT / TS;           // threads per tile row
@@ -101,6 +101,25 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   if (A.done && *A.done) return;
   const int tid = threadIdx.x;
   const int32_t p = A.order[blockIdx.x];
+  // (a separate instance: the plain solve keeps its registers and occupancy)
+  if constexpr (X) if (A.xuse[p]) {
+    // a kept elastic factor's explicit operator: two wavefronts walk its
+    // tiles (four in flight per lane), all threads build x and sum y
+    ExplicitApply e{};
+    e.subs = A.subs;
+    e.F = A.xF;
+    e.foff = A.xfoff;
+    e.sit = A.xsit;
+    e.lam = A.lam;
+    e.lam_sign = A.lam_sign;
+    e.out_iface = A.out_iface;
+    e.if_rp = A.if_rp;
+    e.if_row = A.if_row;
+    e.if_coef = A.if_coef;
+    e.fold = A.fold;
+    explicit_apply_body<T, 2, NT, 4>(e, p, reinterpret_cast<double*>(smem));
+    return;
+  }
   const SubDev s = A.subs[p];
   const int n = s.npad, nb = n / TS;
 
@@ -527,26 +546,26 @@ __global__ __launch_bounds__(NT) void ksolve_kernel(KsolveArgs<T> A) {
   }
 }
 
-template <typename T, int NT, int NR>
+template <typename T, int NT, int NR, bool X = false>
 static void launch_ts(const KsolveArgs<T>& b, int TS, size_t shm, hipStream_t st) {
   dim3 grid((unsigned)b.nsub), block(NT);
   // the diagonal tile's LDS copy of the tiles wider than 8 vectors of 16 bytes
   if ((size_t)TS * sizeof(T) > 128) shm += (size_t)TS * TS * sizeof(T);
   if (TS == 16) {
     if (shm > 65536)
-      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 16, NT, NR>,
+      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 16, NT, NR, X>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    ksolve_kernel<T, 16, NT, NR><<<grid, block, shm, st>>>(b);
+    ksolve_kernel<T, 16, NT, NR, X><<<grid, block, shm, st>>>(b);
   } else if (TS == 32) {
     if (shm > 65536)
-      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 32, NT, NR>,
+      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 32, NT, NR, X>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    ksolve_kernel<T, 32, NT, NR><<<grid, block, shm, st>>>(b);
+    ksolve_kernel<T, 32, NT, NR, X><<<grid, block, shm, st>>>(b);
   } else if constexpr (NT <= 512) {
     if (shm > 65536)
-      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 64, NT, NR>,
+      (void)hipFuncSetAttribute((const void*)ksolve_kernel<T, 64, NT, NR, X>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    ksolve_kernel<T, 64, NT, NR><<<grid, block, shm, st>>>(b);
+    ksolve_kernel<T, 64, NT, NR, X><<<grid, block, shm, st>>>(b);
   }
 }
 
@@ -561,10 +580,20 @@ void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hi
   const int NT = (threads == 1024 && TS <= 32) ? 1024 : (threads == 512 ? 512 : 256);
   const int NR = a.lam2 ? 2 : 1;
   const size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
-  const size_t shm = NR * (vec + (size_t)NT * sizeof(T)) + (vec / 4 + 15) / 16 * 16;
+  size_t shm = NR * (vec + (size_t)NT * sizeof(T)) + (vec / 4 + 15) / 16 * 16;
+  // x and two copies of y of the explicit operators' product
+  if (a.xuse) shm = std::max(shm, (size_t)3 * a.x_mp * sizeof(double));
   KsolveArgs<T> b = a;
   b.vec_stride = (int32_t)(vec / sizeof(T));
-  if (NR == 2) {
+  if (a.xuse) {
+    // the F-apply of the PCGP loop (one right-hand side)
+    if (NT == 1024)
+      launch_ts<T, 1024, 1, true>(b, TS, shm, st);
+    else if (NT == 512)
+      launch_ts<T, 512, 1, true>(b, TS, shm, st);
+    else
+      launch_ts<T, 256, 1, true>(b, TS, shm, st);
+  } else if (NR == 2) {
     if (NT == 1024)
       launch_ts<T, 1024, 2>(b, TS, shm, st);
     else if (NT == 512)

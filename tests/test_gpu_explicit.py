@@ -75,7 +75,7 @@ class Pair:
         self.a = assembly.assemble(self.mesh, ed, self.mesh.n_torn, self.du, sigma, kappa)
         self.tf.set_matrix(self.a["K"])
         self.g = {}
-        for fmt in ("explicit", "factors"):
+        for fmt in ("explicit", "hybrid", "factors"):
             g = GpuSolver(w, precision=precision, tile=tile, fapply_format=fmt)
             g.set_state(sigma=T(sigma.ravel(), dev), kappa=T(kappa.ravel(), dev))
             g.assemble(T(self.du, dev))
@@ -117,32 +117,35 @@ def test_explicit_fapply_matches_oracle(pair, dev):
     P = pair
     rng = np.random.default_rng(3)
     lam = rng.standard_normal(P.mesh.m)
-    qe = N(P.g["explicit"].fapply(T(lam, dev)))
     qf = N(P.g["factors"].fapply(T(lam, dev)))
-    assert emax(qe, qf) <= 1e-10
-    if P.name != "uneven":
-        assert emax(qe, P.tf.F(lam)) <= 1e-9
     lk = P.tf.project(lam)
-    assert emax(P.tf.project(N(P.g["explicit"].fapply(T(lk, dev)))), P.tf.project(P.tf.F(lk))) <= 1e-9
+    for fmt in ("explicit", "hybrid"):
+        qe = N(P.g[fmt].fapply(T(lam, dev)))
+        assert emax(qe, qf) <= 1e-10, fmt
+        if P.name != "uneven":
+            assert emax(qe, P.tf.F(lam)) <= 1e-9, fmt
+        assert emax(P.tf.project(N(P.g[fmt].fapply(T(lk, dev)))), P.tf.project(P.tf.F(lk))) <= 1e-9, fmt
 
 
 def test_explicit_fapply_deterministic(pair, dev):
     rng = np.random.default_rng(8)
     lam = T(rng.standard_normal(pair.mesh.m), dev)
-    a = N(pair.g["explicit"].fapply(lam))
-    b = N(pair.g["explicit"].fapply(lam))
-    assert np.array_equal(a, b)
+    for fmt in ("explicit", "hybrid"):
+        a = N(pair.g[fmt].fapply(lam))
+        b = N(pair.g[fmt].fapply(lam))
+        assert np.array_equal(a, b), fmt
 
 
 def test_explicit_dual_pcg(pair, dev):
     P = pair
     f = P.mesh.torn_load(1.0) - P.a["fint"]
     ref = P.tf.solve(f, eps=1e-8)
-    lam, u, rep, rc = P.g["explicit"].dual_pcg(T(f, dev))
-    assert rep["converged"] == 1
-    assert abs(rep["iters"] - ref["iters"]) <= 1
-    assert rel(N(u), ref["u"]) <= 1e-6
-    assert rel(N(lam), ref["lam"]) <= 1e-5
+    for fmt in ("explicit", "hybrid"):
+        lam, u, rep, rc = P.g[fmt].dual_pcg(T(f, dev))
+        assert rep["converged"] == 1, fmt
+        assert abs(rep["iters"] - ref["iters"]) <= 1, fmt
+        assert rel(N(u), ref["u"]) <= 1e-6, fmt
+        assert rel(N(lam), ref["lam"]) <= 1e-5, fmt
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -154,16 +157,17 @@ def test_explicit_fp32(name, dev):
     P = Pair(w, dev, precision="fp32", plastic_step=plastic)
     rng = np.random.default_rng(5)
     lam = rng.standard_normal(P.mesh.m)
-    if name != "uneven":
-        assert emax(N(P.g["explicit"].fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-5
     lk = P.tf.project(lam)
-    assert emax(P.tf.project(N(P.g["explicit"].fapply(T(lk, dev)))), P.tf.project(P.tf.F(lk))) <= 1e-5
     f = P.mesh.torn_load(1.0) - P.a["fint"]
     ref = P.tf.solve(f, eps=1e-8)
-    lam_g, u, rep, rc = P.g["explicit"].dual_pcg(T(f, dev))
-    assert rep["converged"] == 1 and 1 <= rep["outer"] <= 4
-    assert rel(N(u), ref["u"]) <= 1e-6
-    assert rel(N(lam_g), ref["lam"]) <= 1e-5
+    for fmt in ("explicit", "hybrid"):
+        if name != "uneven":
+            assert emax(N(P.g[fmt].fapply(T(lam, dev))), P.tf.F(lam)) <= 1e-5, fmt
+        assert emax(P.tf.project(N(P.g[fmt].fapply(T(lk, dev)))), P.tf.project(P.tf.F(lk))) <= 1e-5, fmt
+        lam_g, u, rep, rc = P.g[fmt].dual_pcg(T(f, dev))
+        assert rep["converged"] == 1 and 1 <= rep["outer"] <= 4, fmt
+        assert rel(N(u), ref["u"]) <= 1e-6, fmt
+        assert rel(N(lam_g), ref["lam"]) <= 1e-5, fmt
     P.close()
 
 
@@ -177,25 +181,29 @@ def test_explicit_degenerate_decompositions(S, n, dev):
     P = Pair(w, dev, tile=16)
     rng = np.random.default_rng(2)
     lam = rng.standard_normal(P.mesh.m)
-    assert emax(N(P.g["explicit"].fapply(T(lam, dev))), N(P.g["factors"].fapply(T(lam, dev)))) <= 1e-10
     f = P.mesh.torn_load(1.0) - P.a["fint"]
     ref = P.tf.solve(f, eps=1e-8)
-    lam_g, u, rep, rc = P.g["explicit"].dual_pcg(T(f, dev))
-    assert rep["converged"] == 1
-    assert rel(N(u), ref["u"]) <= 1e-6
+    for fmt in ("explicit", "hybrid"):
+        assert emax(N(P.g[fmt].fapply(T(lam, dev))), N(P.g["factors"].fapply(T(lam, dev)))) <= 1e-10, fmt
+        lam_g, u, rep, rc = P.g[fmt].dual_pcg(T(f, dev))
+        assert rep["converged"] == 1, fmt
+        assert rel(N(u), ref["u"]) <= 1e-6, fmt
     P.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_explicit_newton_plastic_matches_oracle(precision, dev):
-    """Load steps with plastic subdomains refactorized (and their explicit
-    blocks formed again), elastic ones kept and elastic-again ones copied
-    back (their blocks formed from the copied factor), graph replay on: the
-    oracle's displacements and hardening."""
+@pytest.mark.parametrize("fmt,precision", [("explicit", "fp64"), ("explicit", "fp32"), ("hybrid", "fp64"),
+                                            ("hybrid", "fp32")])
+def test_explicit_newton_plastic_matches_oracle(fmt, precision, dev):
+    """Load steps with plastic subdomains refactorized, elastic ones kept and
+    elastic-again ones copied back, graph replay on.  Explicit: every
+    factorized or copied-back subdomain's block formed again.  Hybrid: the
+    subdomains with kept elastic factors use their blocks (formed with the
+    factor, copied back with it), the others their factor sweeps, in one
+    launch.  The oracle's displacements and hardening."""
     from paper_1205_1926_amd import GpuSolver
     w = W.small_cube(S=(3, 2, 2), n=(3, 3, 3), amp=650.0, shear=150.0, steps=3)
     o = OracleSolver(w, "tfeti")
-    g = GpuSolver(w, use_graph=1, fapply_format="explicit", precision=precision)
+    g = GpuSolver(w, use_graph=1, fapply_format=fmt, precision=precision)
     hist = []
     for k in range(w.steps):
         o.load_step()
