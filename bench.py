@@ -9,24 +9,34 @@ then the commit.  Default workload: the 10x10x10 cube of 8^3-element
 subdomains; W untimed load steps, then K timed ones.
 
 The same load steps run in several forms (legs), each on a fresh handle
-(default: fp32_all, fp64_plain, fp64_graph_warm, fp64_dirichlet, fp32_learned):
-  fp32_all        FP32 panels of the FP64 factor in the inner PCGP with FP64
-                  outer dual refinement, warm start, PCGP iteration replayed
-                  from a HIP graph (the headline line; --learned adds the
-                  learned warm-start candidate);
+(default: fp32_hybrid, fp32_all, fp64_plain, fp64_graph_warm,
+fp64_dirichlet, fp32_learned, fp64_explicit):
+  fp32_hybrid     the headline line: FP32 inner PCGP with FP64 outer dual
+                  refinement, warm start, PCGP iteration replayed from a HIP
+                  graph; each F-apply in one launch applies the explicit
+                  local operator of every subdomain that keeps its elastic
+                  factor and the FP32 factor sweeps to the others;
+  fp32_all        the same with the factor sweeps for every subdomain
+                  (--learned adds the learned warm-start candidate);
   fp32_learned    fp32_all with the learned warm-start candidate of the
                   network in the package (trained on the uneven 8x8x8 mesh);
   fp64_plain      FP64 factors, cold start, eager launches (plain GPU TFETI);
   fp64_graph_warm FP64 factors with the warm start and the graph;
   fp64_dirichlet, fp32_dirichlet  the same with the Dirichlet preconditioner
-                  Bbar Sbar Bbar^T instead of the lumped one (Section 4.2).
+                  Bbar Sbar Bbar^T instead of the lumped one (Section 4.2);
+  fp64_explicit, fp32_explicit, fp64_hybrid  the explicit operators for
+                  every subdomain (formed at each factorization), or the
+                  hybrid launch, in FP64 or FP32.
 
 value = F-applies inside the timed load steps of the headline leg / their
 wall time; newton_step_ms = wall time / Newton iterations with a solve.
 roofline: the headline leg's subdomain-solve kernel of the F-apply;
-algorithmic bytes = two passes over the skyline (envelope) of every
-subdomain factor, divided by the kernel's mean duration from HIP events on
-the library's stream over the timed region.
+algorithmic bytes per launch = two passes over the envelope of each factor
+it solves with plus the stored tiles of each explicit operator it applies
+(as the library counts them for the timed launches), divided by the
+kernel's mean duration from HIP events on the library's stream over the
+timed region; traffic (FETCH_SIZE + WRITE_SIZE) only for the factor sweeps'
+kernel, as measured.
 rel_error_vs_oracle: displacements and multipliers of load step 1 of every
 leg against the FP64 oracle at full size (computed in a child process that
 runs beside the GPU legs), and the headline leg's displacements after the
@@ -336,6 +346,7 @@ def run_leg(name, w, args, net, detail):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     k_ms, k_cnt = g.timing()
+    k_bytes = g.timing_bytes()
     graph_state = g.graph_active()
     g.set_timing(False)
     u_final = g.state()["u"].cpu().numpy()
@@ -356,15 +367,15 @@ def run_leg(name, w, args, net, detail):
     torch.cuda.synchronize()
     iso = (time.perf_counter() - t1) / args.fapply_reps
     iso_ms, iso_cnt = g.timing()
+    iso_bytes = g.timing_bytes()
     g.set_timing(False)
     g.close()
-    fb = 8 if opts["precision"] == "fp64" else 4
     # algorithmic bytes of one F-apply: both sweeps over the factor envelope,
     # or the stored lower triangles of the explicit operators
-    # (hybrid: the operators' bytes, a lower bound, since the subdomains
-    # solved through their factors read more)
-    alg = (sz["explicit_bytes"] if opts.get("fapply_format") in ("explicit", "hybrid")
-           else 2 * sz["skyline_entries"] * fb)
+    # algorithmic bytes per F-apply launch, as the library counts them for
+    # the timed launches: both sweeps over the factor envelopes, or the
+    # stored operator tiles, or (hybrid) the mix of each factorization
+    alg = k_bytes / k_cnt if k_cnt > 0 else iso_bytes / max(iso_cnt, 1)
     iso_kernel_s = iso_ms / max(iso_cnt, 1) / 1e3
     if k_cnt > 0:
         kernel_s, src = k_ms / k_cnt / 1e3, "timed load steps"
@@ -464,7 +475,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed load steps before them (at least 1)")
     ap.add_argument("--learned", default=None, help="safetensors weights of the warm-start network (fp32_all leg)")
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--legs", default="fp32_all,fp64_plain,fp64_graph_warm,fp64_dirichlet,fp32_learned,fp64_explicit",
+    ap.add_argument("--legs", default="fp32_hybrid,fp32_all,fp64_plain,fp64_graph_warm,fp64_dirichlet,fp32_learned,"
+                                      "fp64_explicit",
                     help="comma-separated forms; the first is the headline line")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--refine-eps", type=float, default=0.0, help="FP32 mode: inner PCGP tolerance")
@@ -582,7 +594,9 @@ def main() -> int:
     sz = head["sizes"]
     kernel_s = head["kernel_s"]
     achieved = head["alg_bytes"] / kernel_s / 1e9
-    traffic = measured_traffic(w.name, head["precision"], sz["tile"], sz["threads"])
+    # (measured for the factor sweeps' kernel; none for the other formats)
+    traffic = (measured_traffic(w.name, head["precision"], sz["tile"], sz["threads"])
+               if LEGS[legs[0]].get("fapply_format", "factors") == "factors" else None)
     newton_ms = {n: r["elapsed"] / max(r["solves"], 1) * 1e3 for n, r in results.items()}
     line = {
         "metric": METRIC,

@@ -313,6 +313,12 @@ int tfeti_get_lambda(const tfeti_handle* h, double* lambda);
  * totals). */
 int tfeti_set_timing(tfeti_handle* h, int on);
 int tfeti_get_timing(tfeti_handle* h, double* ms_host, int64_t* count_host);
+/* Algorithmic bytes of the F-apply kernels counted by tfeti_get_timing since
+ * timing was switched on: per launch, both triangular sweeps over the
+ * envelope of each factor the launch solves with, plus the stored tiles of
+ * each explicit operator it applies (with TFETI_FAPPLY_HYBRID the mix of
+ * the factorization in use).  Section 4.2 (F = B K^+ B^T). */
+int tfeti_get_timing_bytes(tfeti_handle* h, double* bytes_host);
 
 /* Graph replay state of the PCGP iteration: 0 not captured (yet or option
  * off), 1 replaying a captured graph, 2 capture failed (eager launches). */

@@ -99,6 +99,7 @@ SIGNATURES = {
     "tfeti_get_lambda": (I32, [P, P]),
     "tfeti_set_timing": (I32, [P, I32]),
     "tfeti_get_timing": (I32, [P, C.POINTER(D), C.POINTER(I64)]),
+    "tfeti_get_timing_bytes": (I32, [P, C.POINTER(D)]),
     "tfeti_graph_status": (I32, [P]),
     "tfeti_model_host": (I32, [C.POINTER(Problem), I32, C.POINTER(Sizes), C.POINTER(I64), P, P, P]),
     "return_map": (I32, [C.POINTER(Material), I64, P, P, P, P, P, P, P, P]),

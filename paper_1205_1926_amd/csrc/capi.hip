@@ -144,6 +144,8 @@ struct tfeti_handle {
   bool timing = false;
   double t_ms = 0.0;
   int64_t t_count = 0;
+  double t_bytes = 0.0;         // algorithmic bytes of the timed F-apply kernels
+  double fa_bytes = 0.0;        // those of one loop F-apply with the current factorization
   std::vector<hipEvent_t> ev;   // pairs (start, stop) around F-apply solve kernels
   int ev_used = 0;
   int last_f64 = 0;             // FP64 F-applies of the last solve
@@ -353,6 +355,7 @@ void harvest_timing(tfeti_handle* h, int valid) {
     if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
       h->t_ms += ms;
       h->t_count += 1;
+      h->t_bytes += h->fa_bytes;
     }
   }
   h->ev_used = 0;
@@ -1417,6 +1420,17 @@ int factorize(tfeti_handle* h) {
     for (int64_t p = 0; p < M.n_sub; ++p) h->exuse[p] = h->fact_elastic[p];
     HIPCHK(hipMemcpyAsync(h->d_exuse, h->exuse.data(), M.n_sub, hipMemcpyHostToDevice, h->st));
   }
+  // algorithmic bytes of one loop F-apply: both sweeps over each factor's
+  // envelope, or the operator's stored tiles
+  {
+    const double esz = h->prec == TFETI_PREC_FP64 ? 8.0 : 4.0;
+    double fb = 0.0;
+    for (int64_t p = 0; p < M.n_sub; ++p) {
+      const bool op = h->hyb ? h->exuse[p] != 0 : h->exf;
+      fb += op ? (double)explicit_tiles(M.subs[p].n_iface) * 256.0 * esz : 2.0 * (double)M.skyline_sub[p] * esz;
+    }
+    h->fa_bytes = fb;
+  }
   h->factored = true;
   if (h->tune_pending) {
     h->tune_pending = false;
@@ -2159,6 +2173,7 @@ int tfeti_set_timing(tfeti_handle* h, int on) {
   h->timing = on != 0;
   h->t_ms = 0.0;
   h->t_count = 0;
+  h->t_bytes = 0.0;
   h->ev_used = 0;
   return TFETI_OK;
 }
@@ -2174,6 +2189,13 @@ int tfeti_get_timing(tfeti_handle* h, double* ms_host, int64_t* count_host) {
   harvest_timing(h, 1 << 30);
   *ms_host = h->t_ms;
   *count_host = h->t_count;
+  return TFETI_OK;
+}
+
+int tfeti_get_timing_bytes(tfeti_handle* h, double* bytes_host) {
+  if (!h || !bytes_host) return TFETI_E_INVALID;
+  harvest_timing(h, 1 << 30);
+  *bytes_host = h->t_bytes;
   return TFETI_OK;
 }
 

@@ -168,7 +168,9 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
   // skyline (envelope) size of the factors: per row, distance to the first
   // coupled column in the factor ordering
   M.skyline_entries = 0;
+  M.skyline_sub.assign(M.subs.size(), 0);
   for (const SubDev& s : M.subs) {
+    const int64_t sky0 = M.skyline_entries;
     int32_t N0 = s.N[s.perm[0]], N1 = s.N[s.perm[1]], N2 = s.N[s.perm[2]];
     for (int32_t c2 = 0; c2 < N2; ++c2)
       for (int32_t c1 = 0; c1 < N1; ++c1)
@@ -180,6 +182,7 @@ std::string build_model(const tfeti_problem& P, HostModel& M) {
           int32_t fmin = g0 + N0 * (g1 + N1 * g2);
           for (int c = 0; c < 3; ++c) M.skyline_entries += 3 * (f - fmin) + c + 1;
         }
+    M.skyline_sub[&s - M.subs.data()] = M.skyline_entries - sky0;
   }
 
   // ---- global node -> copies (p ascending) ----

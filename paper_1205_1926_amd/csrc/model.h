@@ -110,6 +110,7 @@ struct HostModel {
   // sizes
   int64_t band_entries = 0;             // sum npad * Wb
   int64_t skyline_entries = 0;          // sum of envelope widths of the factors
+  std::vector<int64_t> skyline_sub;      // envelope entries of each subdomain's factor
 };
 
 // Build the host model; returns an empty string on success, else a message.

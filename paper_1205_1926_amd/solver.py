@@ -240,6 +240,12 @@ class GpuSolver:
         self._check(self.lib.tfeti_get_timing(self.h, C.byref(ms), C.byref(cnt)), "get_timing")
         return ms.value, cnt.value
 
+    def timing_bytes(self) -> float:
+        """Algorithmic bytes of the F-apply kernels that timing() counts."""
+        b = C.c_double()
+        self._check(self.lib.tfeti_get_timing_bytes(self.h, C.byref(b)), "get_timing_bytes")
+        return b.value
+
 
 def model_host(workload, tile: int = 0):
     """Host-only model build (no GPU): sizes and B in CSR."""
