@@ -326,12 +326,12 @@ __global__ __launch_bounds__(64 * NW) void explicit_form_kernel(ExplicitForm a, 
 }
 
 // y = Ft_p x per subdomain: one workgroup of NW wavefronts per subdomain.
-template <typename T, int NW>
+template <typename T, int NW, int U>
 __global__ __launch_bounds__(64 * NW) void explicit_apply_kernel(ExplicitApply a) {
   if (a.done && *a.done) return;
   extern __shared__ double sh[];
   const int p = a.order ? a.order[blockIdx.x] : blockIdx.x;
-  explicit_apply_body<T, NW, 64 * NW, 8>(a, p, sh);
+  explicit_apply_body<T, NW, 64 * NW, U>(a, p, sh);
 }
 
 // the operator of each listed subdomain copied as 16-byte vectors (its
@@ -395,7 +395,9 @@ void launch_explicit_apply(const ExplicitApply& a, int max_iface, hipStream_t st
   // four wavefronts per subdomain when every subdomain's workgroup is then
   // still resident at once (two per compute unit, by registers, if the LDS
   // of x and four copies of y allows), else two: the launch ends with the
-  // largest operators, which stream faster with more loads in flight
+  // largest operators, which stream faster with more loads in flight (with
+  // at most two workgroups per compute unit, registers allow batches of 16
+  // tiles; with two wavefronts and many workgroups per unit, 8)
   static int cus = 0, lds_cu = 0;
   if (cus == 0) {
     int dev = 0;
@@ -410,12 +412,12 @@ void launch_explicit_apply(const ExplicitApply& a, int max_iface, hipStream_t st
   const int64_t per_cu = std::min<int64_t>(2, (int64_t)lds_cu / (int64_t)lds4);
   if (a.nsub <= per_cu * cus) {
     if (lds4 > 65536)
-      (void)hipFuncSetAttribute((const void*)explicit_apply_kernel<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds4);
-    explicit_apply_kernel<T, 4><<<dim3((unsigned)a.nsub), dim3(256), lds4, st>>>(a);
+      (void)hipFuncSetAttribute((const void*)explicit_apply_kernel<T, 4, 16>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds4);
+    explicit_apply_kernel<T, 4, 16><<<dim3((unsigned)a.nsub), dim3(256), lds4, st>>>(a);
   } else {
     const size_t lds2 = (size_t)3 * mp * sizeof(double);
-    explicit_apply_kernel<T, 2><<<dim3((unsigned)a.nsub), dim3(128), lds2, st>>>(a);
+    explicit_apply_kernel<T, 2, 8><<<dim3((unsigned)a.nsub), dim3(128), lds2, st>>>(a);
   }
 }
 
