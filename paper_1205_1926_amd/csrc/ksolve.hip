@@ -103,8 +103,12 @@ __global__ __launch_bounds__(NT, (X && TS <= 32) ? 4 : 1) void ksolve_kernel(Kso
   const int32_t p = A.order[blockIdx.x];
   // (a separate instance: the plain solve keeps its registers and occupancy)
   if constexpr (X) if (A.xuse[p]) {
-    // a kept elastic factor's explicit operator: two wavefronts walk its
-    // tiles (four in flight per lane), all threads build x and sum y
+    // a kept elastic factor's explicit operator: all threads build x and
+    // sum y; two wavefronts walk its tiles, four per batch, in the instances
+    // held to four wavefronts per SIMD (tiles of 16 and 32 rows), and half
+    // of the workgroup's wavefronts, eight per batch, in the 64-row instances,
+    // which keep their registers (large subdomains, whose operators are the
+    // launch's longest chains)
     ExplicitApply e{};
     e.subs = A.subs;
     e.F = A.xF;
@@ -117,7 +121,8 @@ __global__ __launch_bounds__(NT, (X && TS <= 32) ? 4 : 1) void ksolve_kernel(Kso
     e.if_row = A.if_row;
     e.if_coef = A.if_coef;
     e.fold = A.fold;
-    explicit_apply_body<T, 2, NT, 4>(e, p, reinterpret_cast<double*>(smem));
+    constexpr int XW = TS >= 64 ? NT / 128 : 2, XU = TS >= 64 ? 8 : 4;
+    explicit_apply_body<T, XW, NT, XU>(e, p, reinterpret_cast<double*>(smem));
     return;
   }
   const SubDev s = A.subs[p];
@@ -581,8 +586,10 @@ void launch_ksolve(const KsolveArgs<T>& a, int TS, int threads, int npad_max, hi
   const int NR = a.lam2 ? 2 : 1;
   const size_t vec = ((size_t)npad_max * sizeof(T) + 15) / 16 * 16;
   size_t shm = NR * (vec + (size_t)NT * sizeof(T)) + (vec / 4 + 15) / 16 * 16;
-  // x and two copies of y of the explicit operators' product
-  if (a.xuse) shm = std::max(shm, (size_t)3 * a.x_mp * sizeof(double));
+  // x and one copy of y per tile-walking wavefront of the explicit
+  // operators' product
+  const int xw = TS >= 64 ? NT / 128 : 2;
+  if (a.xuse) shm = std::max(shm, (size_t)(xw + 1) * a.x_mp * sizeof(double));
   KsolveArgs<T> b = a;
   b.vec_stride = (int32_t)(vec / sizeof(T));
   if (a.xuse) {

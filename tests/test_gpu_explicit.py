@@ -256,3 +256,32 @@ def test_explicit_sizes_report_bytes(dev):
         g = GpuSolver(w, precision=prec)
         assert g.sizes["explicit_bytes"] == 0
         g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["cube_plastic", "uneven"])
+def test_hybrid_wide_tiles(name, precision, dev):
+    """64-row tiles: the solve kernel's wide-tile instances walk an
+    operator's tiles with half of the workgroup's wavefronts.  The hybrid
+    F-apply equals the factor path's (FP64) or the oracle's F within 1e-5
+    (FP32, on Ker G for the uneven mesh), and its dual solve reaches the
+    oracle's solution."""
+    w, plastic = CASES[name]()
+    P = Pair(w, dev, precision=precision, plastic_step=plastic, tile=64)
+    rng = np.random.default_rng(13)
+    lam = rng.standard_normal(P.mesh.m)
+    lk = P.tf.project(lam)
+    qh = N(P.g["hybrid"].fapply(T(lam, dev)))
+    if precision == "fp64":
+        assert emax(qh, N(P.g["factors"].fapply(T(lam, dev)))) <= 1e-10
+    elif name != "uneven":
+        assert emax(qh, P.tf.F(lam)) <= 1e-5
+    assert emax(P.tf.project(N(P.g["hybrid"].fapply(T(lk, dev)))), P.tf.project(P.tf.F(lk))) <= 1e-5
+    f = P.mesh.torn_load(1.0) - P.a["fint"]
+    ref = P.tf.solve(f, eps=1e-8)
+    lam_g, u, rep, rc = P.g["hybrid"].dual_pcg(T(f, dev))
+    assert rep["converged"] == 1
+    assert rel(N(u), ref["u"]) <= 1e-6
+    assert rel(N(lam_g), ref["lam"]) <= 1e-5
+    assert P.g["hybrid"].sizes["tile"] == 64
+    P.close()
